@@ -1,0 +1,206 @@
+/*
+ * sfft.h -- C-ABI of the MI355X (gfx950) aliasing-filter sparse FFT library.
+ *
+ * Problem (Li, Jiang & Chen 2020, Sect. 2.1): given a signal x of N complex
+ * samples whose spectrum xhat = F_N x (Eq. 1-2, F_N carries 1/N) is K-sparse,
+ * return K frequency positions f_0..f_{K-1} and their values xhat_{f_j}.
+ *
+ * Method: frequency bucketization with the aliasing filter (Sect. 2.2,
+ * Eq. 3-6): for every round (or stage) and every delay, subsample x with
+ * stride L = N/B after a shift, take the B-point DFT, and read bucket c.
+ * Reconstruction (Sect. 3.2-3.3): each bucket vector is tested as zero-ton /
+ * single-ton / multi-ton; a single-ton is located from the phase of adjacent
+ * delays (exact mode) or by enumeration of its L candidates (noisy mode), and
+ * its value is the least-squares mean of the de-rotated measurements.  When N
+ * is a product of co-prime prime powers the library runs the FFAST peeling
+ * decoder (Sect. 3.2, Eq. 19-20); when N is a power of two it runs the binary
+ * tree search (Sect. 3.3, Eq. 23), opening the two children c and c + B of
+ * every multi-ton at the next level.
+ *
+ * Conventions.  Samples use an advance shift, y[m] = x[(sigma m L + s + d)
+ * mod N]; bucket c then holds sum_{f = c mod B} xhat_f e^{+2 pi i f (s+d)/N}
+ * (Eq. 6 with tau -> -tau).  Values are in the 1/N scale of Eq. 2, so a tone
+ * x[n] = a e^{2 pi i f n / N} is reported as a.  Signals and values are
+ * interleaved complex64 (float re, float im).
+ *
+ * Memory.  Every pointer passed to an exec call is a DEVICE pointer (memory
+ * of the current HIP device); the library never reads or writes host memory
+ * through them and returns SFFT_EINVAL for a host pointer.  Buffers stay
+ * owned by the caller and must stay valid until the work completes on the
+ * stream.  Plans own their device tables and workspace, created on first use
+ * on a device and released by sfft_destroy.  One exec may be in flight per
+ * plan; concurrent solves use separate plans or one sfft_exec_batch call.
+ *
+ * Errors.  Functions that return a pointer return NULL on error; functions
+ * that return an integer return a negative SFFT_E* code.  The last code is
+ * also kept per thread (sfft_last_error).  A decoding failure is not an
+ * error: the solve reports status SFFT_PARTIAL and the frequencies it found.
+ */
+#ifndef SFFT_H
+#define SFFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFFT_MAX_ROUNDS 16
+#define SFFT_MAX_STAGES 8
+
+/* error codes (negative returns) */
+#define SFFT_OK 0
+#define SFFT_EINVAL (-1)       /* bad argument: B does not divide N, K < 1, K > N,
+                                  delays < 2 in exact mode, a host pointer, ... */
+#define SFFT_EUNSUPPORTED (-2) /* N not factorable into `stages` co-prime parts,
+                                  a size beyond the kernels' limits */
+#define SFFT_ENOMEM (-3)       /* device allocation failed */
+#define SFFT_EDEVICE (-4)      /* HIP runtime or kernel launch error */
+
+/* solve status (per signal) */
+#define SFFT_STATUS_OK 0
+#define SFFT_STATUS_PARTIAL 1  /* an unresolved multi-ton remained (decode failure,
+                                  level cap or list overflow); found subset returned */
+
+/* decoding modes */
+#define SFFT_EXACT 0 /* exactly sparse: relative zero / single thresholds,
+                        phase-to-index location (Sect. 3.2, Subproblem 2) */
+#define SFFT_NOISY 1 /* general sparse: noise-scaled thresholds T0, T1 and
+                        enumeration of the L candidates (Sect. 3.1, Method 2) */
+
+/* plan kinds */
+#define SFFT_KIND_TREE 0  /* N a power of two: binary tree search */
+#define SFFT_KIND_FFAST 1 /* N a product of co-prime stages: peeling */
+
+typedef struct sfft_plan_s *sfft_plan_t;
+
+/* Full parameter record.  sfft_params_init fills the defaults below. */
+typedef struct {
+  int64_t N;               /* signal length */
+  int64_t K;               /* sparsity = capacity of out_idx / out_val */
+  int32_t stages;          /* FFAST: co-prime stages; tree: rounds */
+  int32_t delays;          /* D consecutive delays {0..D-1} per round/stage */
+  uint64_t seed;           /* SplitMix64 seed of the per-round sigma, shift */
+  int32_t mode;            /* SFFT_EXACT (default) or SFFT_NOISY */
+  int64_t B0;              /* tree: level-0 buckets (power of two);
+                              0 = next power of two >= 2K, capped at N */
+  int32_t max_levels;      /* tree: deepest level; -1 = log2(N/B0) (to L = 1) */
+  int32_t window;          /* noisy: search +-window candidates around the phase
+                              estimate; 0 = all L candidates */
+  int32_t identity_round0; /* tree: round 0 uses sigma = 1, shift = 0 */
+  int32_t nstage_B;        /* FFAST: 0 = factor N into prime powers; else the
+                              number of explicit co-prime stage sizes below */
+  int64_t stage_B[SFFT_MAX_STAGES];
+  int32_t max_peel_rounds; /* FFAST: cap on peeling rounds (default 64) */
+  double eps0;             /* exact: zero-ton if |Y|^2 <= eps0^2 sref^2 n (1e-4) */
+  double eps1;             /* exact: single-ton if residual^2 <= eps1^2 |Y|^2 (1e-4) */
+  double zero_k;           /* noisy: T0^2 = s_b^2 (n + zero_k sqrt(n))        (4) */
+  double single_k;         /* noisy: T1^2 = s_b^2 (n-1 + single_k sqrt(n-1)) (4) */
+  double noise_var;        /* noisy: time-domain noise variance; 0 = estimate */
+} sfft_params_t;
+
+/* Read-only description of a plan (what the kernels will compute). */
+typedef struct {
+  int64_t N, K;
+  int32_t kind;            /* SFFT_KIND_TREE or SFFT_KIND_FFAST */
+  int32_t mode;
+  int32_t R;               /* rounds (tree) or stages (FFAST) */
+  int32_t D;               /* delays */
+  int64_t B0;              /* tree: level-0 buckets */
+  int32_t max_levels;
+  int32_t window;
+  int64_t stage_B[SFFT_MAX_STAGES];   /* FFAST stage sizes */
+  uint64_t sigma[SFFT_MAX_ROUNDS];    /* odd permutation factor per round */
+  uint64_t shift[SFFT_MAX_ROUNDS];    /* shift per round */
+  double eps0, eps1, zero_k, single_k, noise_var;
+  int32_t max_peel_rounds;
+  int32_t found_cap;       /* device list capacities per signal */
+  int32_t multi_cap;
+} sfft_plan_info_t;
+
+/* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */
+typedef struct {
+  int64_t count;           /* frequencies returned */
+  int32_t status;          /* SFFT_STATUS_* */
+  int32_t levels;          /* tree: deepest level reached; FFAST: peeling rounds */
+  int64_t samples;         /* signal samples read (with multiplicity) */
+  int64_t found;           /* frequencies found before the top-K cut */
+  double noise_var;        /* noise variance used (noisy mode) */
+  double sref2;            /* mean level-0 bucket power */
+  uint64_t level_mask;     /* tree: bit l set when level l gathered samples */
+} sfft_stats_t;
+
+/* Defaults for (N, K, stages, delays, seed). */
+void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages,
+                      int32_t delays, uint64_t seed);
+
+/* Plan from the problem statement; exact mode, defaults as above.  Host-only
+   work (factoring, SplitMix64 draws); no device memory is touched until the
+   first exec.  NULL on error (see sfft_last_error). */
+sfft_plan_t sfft_plan(int64_t N, int64_t K, int32_t stages, int32_t delays, uint64_t seed);
+sfft_plan_t sfft_plan_ex(const sfft_params_t *p);
+int32_t sfft_plan_info(sfft_plan_t plan, sfft_plan_info_t *out);
+void sfft_destroy(sfft_plan_t plan);
+
+/* Synchronous solve on the null stream.  x: device complex64[N];
+   out_idx: device int64[K]; out_val: device complex64[K].  Entries [count, K)
+   are padded with index -1 and value 0.  Returns count >= 0 or SFFT_E*. */
+int64_t sfft_exec(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val);
+
+/* Asynchronous solve on `stream` (a hipStream_t; NULL = null stream).
+   d_count: device int64[1], d_status: device int32[1] receive the result. */
+int32_t sfft_exec_async(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val,
+                        int64_t *d_count, int32_t *d_status, void *stream);
+
+/* Batched solve of n independent signals (any mix of plans, N and K) in one
+   fused pipeline: one persistent level-0 launch over all signals and one
+   launch per tree level, replayed from a captured HIP graph when the same
+   plan list is used again.  xs[i], idx[i], vals[i] are device pointers;
+   d_counts: device int64[n]; d_status: device int32[n]. */
+#define SFFT_BATCH_NO_GRAPH 1 /* launch eagerly instead of replaying a graph */
+int32_t sfft_exec_batch(const sfft_plan_t *plans, const void *const *xs,
+                        int64_t *const *idx, void *const *vals, int64_t *d_counts,
+                        int32_t *d_status, int32_t n, void *stream);
+int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs,
+                           int64_t *const *idx, void *const *vals, int64_t *d_counts,
+                           int32_t *d_status, int32_t n, void *stream, int32_t flags);
+
+/* Profiling form of sfft_exec_batch: runs the same pipeline eagerly on the
+   batch's internal stream with a timing event after every kernel launch, waits
+   for it, and writes the elapsed milliseconds of up to `cap` launches to ms[]
+   and their kernel ids (SFFT_KERNEL_* | level << 8) to kernel[].  Returns the
+   number of entries or SFFT_E*. */
+#define SFFT_KERNEL_RESET 0
+#define SFFT_KERNEL_LEVEL0 1        /* level-0 gather + FFT + classify (and FFAST peel) */
+#define SFFT_KERNEL_SCHED 2
+#define SFFT_KERNEL_EXPAND_FFT 3    /* odd-offset gather + LDS FFT, B' <= 8192 */
+#define SFFT_KERNEL_EXPAND_DIRECT 4 /* odd-offset gather + per-bin partial sums */
+#define SFFT_KERNEL_CHILDREN 5
+#define SFFT_KERNEL_FINALIZE 6
+int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
+                                int64_t *const *idx, void *const *vals, int64_t *d_counts,
+                                int32_t *d_status, int32_t n, float *ms, int32_t *kernel,
+                                int32_t cap);
+
+/* Bucketization alone (Eq. 5-6, level 0): out (device complex64) receives,
+   for a tree plan, B0 class vectors of R*D values (class-major: out[c*R*D +
+   r*D + d] = bucket sigma_r c mod B0 of round r, delay d); for an FFAST plan,
+   the stages one after another, out[(off_j + h)*D + d].  Synchronous on the
+   null stream.  Returns SFFT_OK or SFFT_E*. */
+int32_t sfft_bucketize(sfft_plan_t plan, const void *x, void *out);
+
+/* Statistics of the last exec / exec_async of `plan` (synchronises), or of
+   signal i of the last sfft_exec_batch with that plan list (i < n). */
+int32_t sfft_exec_stats(sfft_plan_t plan, sfft_stats_t *out);
+int32_t sfft_batch_stats(const sfft_plan_t *plans, int32_t n, int32_t i, sfft_stats_t *out);
+
+/* Release every cached batch context (graphs, workspaces). */
+void sfft_release_batches(void);
+
+int32_t sfft_last_error(void);
+const char *sfft_strerror(int32_t code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,311 @@
+"""Python binding of libsfft (aliasing-filter sparse FFT on MI355X / gfx950).
+
+Argument marshalling only: every step of a solve runs in the HIP kernels of
+``csrc/``; torch supplies device memory and streams.  Importing this package
+raises if the compiled library is missing -- there is no CPU fallback.
+
+    import torch, paper_2011_05749_amd as sfft
+    plan = sfft.Plan(N=2**22, K=1024, stages=4, delays=2, seed=1, B0=2048)
+    idx, val, count = plan.exec(x)            # x: complex64 cuda tensor [N]
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libsfft.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libsfft.so not found at {LIB_PATH}: build it with "
+        "`python paper_2011_05749_amd/build.py` (hipcc, gfx950); there is no fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MAX_ROUNDS = 16
+MAX_STAGES = 8
+EXACT, NOISY = 0, 1
+KIND_TREE, KIND_FFAST = 0, 1
+STATUS_OK, STATUS_PARTIAL = 0, 1
+BATCH_NO_GRAPH = 1
+ERRORS = {0: "ok", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM", -4: "EDEVICE"}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+        ("stages", ctypes.c_int32), ("delays", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("mode", ctypes.c_int32),
+        ("B0", ctypes.c_int64),
+        ("max_levels", ctypes.c_int32), ("window", ctypes.c_int32),
+        ("identity_round0", ctypes.c_int32), ("nstage_B", ctypes.c_int32),
+        ("stage_B", ctypes.c_int64 * MAX_STAGES),
+        ("max_peel_rounds", ctypes.c_int32),
+        ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
+        ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
+        ("noise_var", ctypes.c_double),
+    ]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+        ("kind", ctypes.c_int32), ("mode", ctypes.c_int32),
+        ("R", ctypes.c_int32), ("D", ctypes.c_int32),
+        ("B0", ctypes.c_int64),
+        ("max_levels", ctypes.c_int32), ("window", ctypes.c_int32),
+        ("stage_B", ctypes.c_int64 * MAX_STAGES),
+        ("sigma", ctypes.c_uint64 * MAX_ROUNDS),
+        ("shift", ctypes.c_uint64 * MAX_ROUNDS),
+        ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
+        ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
+        ("noise_var", ctypes.c_double),
+        ("max_peel_rounds", ctypes.c_int32),
+        ("found_cap", ctypes.c_int32), ("multi_cap", ctypes.c_int32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("count", ctypes.c_int64), ("status", ctypes.c_int32), ("levels", ctypes.c_int32),
+        ("samples", ctypes.c_int64), ("found", ctypes.c_int64),
+        ("noise_var", ctypes.c_double), ("sref2", ctypes.c_double),
+        ("level_mask", ctypes.c_uint64),
+    ]
+
+
+KERNEL_NAMES = {0: "k_reset", 1: "k_level0", 2: "k_sched", 3: "k_expand_fft",
+                4: "k_expand_direct", 5: "k_children", 6: "k_finalize"}
+
+_vp = ctypes.c_void_p
+_lib.sfft_params_init.argtypes = [ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int64,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64]
+_lib.sfft_params_init.restype = None
+_lib.sfft_plan.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.c_uint64]
+_lib.sfft_plan.restype = _vp
+_lib.sfft_plan_ex.argtypes = [ctypes.POINTER(Params)]
+_lib.sfft_plan_ex.restype = _vp
+_lib.sfft_plan_info.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
+_lib.sfft_plan_info.restype = ctypes.c_int32
+_lib.sfft_destroy.argtypes = [_vp]
+_lib.sfft_destroy.restype = None
+_lib.sfft_exec.argtypes = [_vp, _vp, _vp, _vp]
+_lib.sfft_exec.restype = ctypes.c_int64
+_lib.sfft_exec_async.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.sfft_exec_async.restype = ctypes.c_int32
+_lib.sfft_exec_batch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp]
+_lib.sfft_exec_batch.restype = ctypes.c_int32
+_lib.sfft_exec_batch_ex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
+                                    ctypes.c_int32]
+_lib.sfft_exec_batch_ex.restype = ctypes.c_int32
+_lib.sfft_exec_batch_profile.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp,
+                                         ctypes.c_int32]
+_lib.sfft_exec_batch_profile.restype = ctypes.c_int32
+_lib.sfft_bucketize.argtypes = [_vp, _vp, _vp]
+_lib.sfft_bucketize.restype = ctypes.c_int32
+_lib.sfft_exec_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
+_lib.sfft_exec_stats.restype = ctypes.c_int32
+_lib.sfft_batch_stats.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Stats)]
+_lib.sfft_batch_stats.restype = ctypes.c_int32
+_lib.sfft_release_batches.argtypes = []
+_lib.sfft_release_batches.restype = None
+_lib.sfft_last_error.argtypes = []
+_lib.sfft_last_error.restype = ctypes.c_int32
+_lib.sfft_strerror.argtypes = [ctypes.c_int32]
+_lib.sfft_strerror.restype = ctypes.c_char_p
+
+EXPORTS = ["sfft_params_init", "sfft_plan", "sfft_plan_ex", "sfft_plan_info", "sfft_destroy",
+           "sfft_exec", "sfft_exec_async", "sfft_exec_batch", "sfft_exec_batch_ex",
+           "sfft_exec_batch_profile",
+           "sfft_bucketize", "sfft_exec_stats", "sfft_batch_stats", "sfft_release_batches",
+           "sfft_last_error", "sfft_strerror"]
+
+
+class SfftError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = int(code)
+        msg = _lib.sfft_strerror(self.code).decode()
+        super().__init__(f"{what}: {ERRORS.get(self.code, self.code)} ({msg})")
+
+
+def _check(rc: int, what: str) -> int:
+    if rc < 0:
+        raise SfftError(rc, what)
+    return rc
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+def _dev_ptr(t, dtype_name, n=None, what="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise SfftError(-1, f"{what} must be a device tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise SfftError(-1, f"{what} must be {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise SfftError(-1, f"{what} must be contiguous")
+    if n is not None and t.numel() < n:
+        raise SfftError(-1, f"{what} holds {t.numel()} < {n} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """An sfft plan (immutable).  Keyword parameters map onto sfft_params_t:
+    mode ('exact'|'noisy' or 0|1), B0, max_levels, window, identity_round0,
+    stage_B (explicit co-prime FFAST stages), max_peel_rounds, eps0, eps1,
+    zero_k, single_k, noise_var."""
+
+    def __init__(self, N: int, K: int, stages: int, delays: int, seed: int = 0, **kw):
+        p = Params()
+        _lib.sfft_params_init(ctypes.byref(p), N, K, stages, delays, seed)
+        for k, v in kw.items():
+            if k == "mode":
+                v = {"exact": EXACT, "noisy": NOISY}.get(v, v)
+            if k == "stage_B":
+                p.nstage_B = len(v)
+                for j, b in enumerate(v):
+                    p.stage_B[j] = int(b)
+                continue
+            if not hasattr(p, k):
+                raise TypeError(f"unknown plan parameter {k}")
+            setattr(p, k, v)
+        self.params = p
+        h = _lib.sfft_plan_ex(ctypes.byref(p))
+        if not h:
+            raise SfftError(_lib.sfft_last_error(), "sfft_plan_ex")
+        self._h = ctypes.c_void_p(h)
+        inf = PlanInfo()
+        _check(_lib.sfft_plan_info(self._h, ctypes.byref(inf)), "sfft_plan_info")
+        self.info = inf
+        self.N, self.K = int(inf.N), int(inf.K)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sfft_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def n_meas(self) -> int:
+        return self.info.R * self.info.D if self.info.kind == KIND_TREE else self.info.D
+
+    def exec(self, x, out_idx=None, out_val=None):
+        """Synchronous solve: returns (idx int64[K], val complex64[K], count)."""
+        import torch
+        xp = _dev_ptr(x, "complex64", self.N, "x")
+        if out_idx is None:
+            out_idx = torch.empty(self.K, dtype=torch.int64, device=x.device)
+        if out_val is None:
+            out_val = torch.empty(self.K, dtype=torch.complex64, device=x.device)
+        ip = _dev_ptr(out_idx, "int64", self.K, "out_idx")
+        vp = _dev_ptr(out_val, "complex64", self.K, "out_val")
+        cnt = _check(_lib.sfft_exec(self._h, xp, ip, vp), "sfft_exec")
+        return out_idx, out_val, int(cnt)
+
+    def exec_async(self, x, out_idx, out_val, d_count, d_status, stream=None):
+        _check(_lib.sfft_exec_async(
+            self._h, _dev_ptr(x, "complex64", self.N, "x"),
+            _dev_ptr(out_idx, "int64", self.K, "out_idx"),
+            _dev_ptr(out_val, "complex64", self.K, "out_val"),
+            _dev_ptr(d_count, "int64", 1, "d_count"), _dev_ptr(d_status, "int32", 1, "d_status"),
+            _stream_handle(stream)), "sfft_exec_async")
+
+    def bucketize(self, x):
+        """Level-0 class vectors (complex64): tree (B0, R*D); FFAST (sum B_j, D)."""
+        import torch
+        inf = self.info
+        if inf.kind == KIND_TREE:
+            shape = (int(inf.B0), int(inf.R * inf.D))
+        else:
+            shape = (int(sum(inf.stage_B[j] for j in range(inf.R))), int(inf.D))
+        out = torch.empty(shape, dtype=torch.complex64, device=x.device)
+        _check(_lib.sfft_bucketize(self._h, _dev_ptr(x, "complex64", self.N, "x"),
+                                   _dev_ptr(out, "complex64", None, "out")), "sfft_bucketize")
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(_lib.sfft_exec_stats(self._h, ctypes.byref(s)), "sfft_exec_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))(*[p.value if isinstance(p, ctypes.c_void_p) else p
+                                          for p in ptrs])
+    return arr
+
+
+class Batch:
+    """Pre-marshalled arguments of sfft_exec_batch for a fixed list of plans and
+    buffers (so that the timed call does no Python-side allocation)."""
+
+    def __init__(self, plans, xs, idxs=None, vals=None):
+        import torch
+        n = len(plans)
+        if n < 1 or len(xs) != n:
+            raise SfftError(-1, "Batch needs one signal per plan")
+        dev = xs[0].device
+        self.plans = list(plans)
+        self.xs = list(xs)
+        self.idxs = idxs if idxs is not None else [
+            torch.empty(p.K, dtype=torch.int64, device=dev) for p in plans]
+        self.vals = vals if vals is not None else [
+            torch.empty(p.K, dtype=torch.complex64, device=dev) for p in plans]
+        self.counts = torch.zeros(n, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(n, dtype=torch.int32, device=dev)
+        self._plans = _ptr_array([p.handle for p in plans])
+        self._xs = _ptr_array([_dev_ptr(x, "complex64", p.N, "x") for p, x in zip(plans, self.xs)])
+        self._idx = _ptr_array([_dev_ptr(t, "int64", p.K, "idx") for p, t in zip(plans, self.idxs)])
+        self._val = _ptr_array([_dev_ptr(t, "complex64", p.K, "val")
+                                for p, t in zip(plans, self.vals)])
+        self._cnt = _dev_ptr(self.counts, "int64", n, "counts")
+        self._st = _dev_ptr(self.status, "int32", n, "status")
+        self.n = n
+
+    def run(self, graph: bool = True, stream=None):
+        _check(_lib.sfft_exec_batch_ex(self._plans, self._xs, self._idx, self._val, self._cnt,
+                                       self._st, self.n, _stream_handle(stream),
+                                       0 if graph else BATCH_NO_GRAPH), "sfft_exec_batch")
+
+    def profile(self, cap: int = 4096):
+        """Eager run with a HIP event after every launch: list of
+        (kernel name, level, milliseconds) in launch order."""
+        ms = (ctypes.c_float * cap)()
+        ids = (ctypes.c_int32 * cap)()
+        n = _check(_lib.sfft_exec_batch_profile(self._plans, self._xs, self._idx, self._val,
+                                                self._cnt, self._st, self.n, ms, ids, cap),
+                   "sfft_exec_batch_profile")
+        return [(KERNEL_NAMES.get(ids[i] & 255, str(ids[i] & 255)), ids[i] >> 8, float(ms[i]))
+                for i in range(n)]
+
+    def stats(self, i: int) -> dict:
+        s = Stats()
+        _check(_lib.sfft_batch_stats(self._plans, self.n, i, ctypes.byref(s)), "sfft_batch_stats")
+        return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+
+def exec_batch(plans, xs, graph: bool = True, stream=None):
+    """One batched solve; returns the Batch holding idxs, vals, counts, status."""
+    b = Batch(plans, xs)
+    b.run(graph=graph, stream=stream)
+    return b
+
+
+def release_batches():
+    _lib.sfft_release_batches()

@@ -1,0 +1,781 @@
+// sfft_host.cpp -- plans, batch contexts and the C-ABI of the aliasing-filter
+// sparse FFT library (host side; the kernels live in sfft_kernels.hip).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "sfft_internal.h"
+
+using namespace sfft;
+
+namespace {
+
+thread_local int32_t g_last_error = SFFT_OK;
+
+int32_t fail(int32_t code) {
+  g_last_error = code;
+  return code;
+}
+
+bool pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) l++;
+  return l;
+}
+int64_t npow2(int64_t v) {
+  int64_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// SplitMix64 of Steele, Lea & Flood (OOPSLA 2014): Weyl increment by the
+// 64-bit golden ratio, then the two xor-shift-multiply mixing steps.
+struct SplitMix64 {
+  uint64_t x;
+  uint64_t next() {
+    x += 0x9E3779B97F4A7C15ULL;
+    uint64_t v = x;
+    v ^= v >> 30;
+    v *= 0xBF58476D1CE4E5B9ULL;
+    v ^= v >> 27;
+    v *= 0x94D049BB133111EBULL;
+    v ^= v >> 31;
+    return v;
+  }
+};
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+struct BatchCtx;
+
+}  // namespace
+
+struct sfft_plan_s {
+  sfft_plan_info_t info;
+  int64_t stage_off[SFFT_MAX_STAGES + 1];
+  int64_t nb;            // FFAST buckets (sum of stage sizes)
+  double noise_p_den;
+  int64_t noise_at;
+  std::unique_ptr<BatchCtx> single;
+};
+
+namespace {
+
+constexpr int64_t kMaxN = int64_t(1) << 30;
+
+// ------------------------------------------------------------ device buffers
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t bytes) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    return hipMalloc(&p, bytes ? bytes : 16);
+  }
+};
+
+// per-device twiddle table e^{-2 pi i k / kFftMax}
+std::mutex g_tw_mu;
+std::map<int, float2 *> g_tw;
+
+hipError_t device_twiddles(int dev, const float2 **out) {
+  std::lock_guard<std::mutex> lk(g_tw_mu);
+  auto it = g_tw.find(dev);
+  if (it != g_tw.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  std::vector<float2> h(kFftMax);
+  for (int k = 0; k < kFftMax; k++) {
+    const double a = 2.0 * M_PI * (double)k / (double)kFftMax;
+    h[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+  float2 *d = nullptr;
+  hipError_t e = hipMalloc(&d, sizeof(float2) * kFftMax);
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(d, h.data(), sizeof(float2) * kFftMax, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  g_tw[dev] = d;
+  *out = d;
+  return hipSuccess;
+}
+
+struct LevelLaunch {
+  bool fft, direct;
+  int grid_fft, grid_direct, grid_children;
+};
+
+struct BatchCtx {
+  int device = -1;
+  std::vector<const sfft_plan_s *> plans;
+  int nsig = 0;
+  std::vector<SigDesc> desc;
+  DevBuf b_desc, b_io, b_st, b_lists, b_y0, b_fst, b_ff, b_fa, b_mc, b_my, b_mz, b_pre, b_out;
+  LaunchCtx lc{};
+  std::vector<LevelLaunch> levels;
+  std::vector<SigIO> io_last;
+  SigIO *io_pinned = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_io = nullptr;
+  bool io_pending = false;
+
+  ~BatchCtx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (stream) (void)hipStreamDestroy(stream);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (ev_io) (void)hipEventDestroy(ev_io);
+    if (io_pinned) (void)hipHostFree(io_pinned);
+  }
+
+  int32_t build(const std::vector<const sfft_plan_s *> &ps) {
+    plans = ps;
+    nsig = (int)ps.size();
+    if (hipGetDevice(&device) != hipSuccess) return SFFT_EDEVICE;
+    desc.resize(nsig);
+    int64_t y0 = 0, fst = 0, fc = 0, mc = 0, mz = 0;
+    int nmax = 1, maxB0 = 1, maxStage = 1, maxFcap = 64, maxLevels = 0;
+    std::vector<std::pair<int64_t, int>> tree, ffast;
+    for (int s = 0; s < nsig; s++) {
+      const sfft_plan_s *p = ps[s];
+      const sfft_plan_info_t &in = p->info;
+      SigDesc d{};
+      d.N = in.N;
+      d.K = in.K;
+      d.B0 = in.B0;
+      d.log2N = pow2(in.N) ? ilog2(in.N) : -1;
+      d.log2B0 = in.kind == SFFT_KIND_TREE ? ilog2(in.B0) : 0;
+      d.kind = in.kind;
+      d.mode = in.mode;
+      d.R = in.R;
+      d.D = in.D;
+      d.n = in.kind == SFFT_KIND_TREE ? in.R * in.D : in.D;
+      d.max_levels = in.max_levels;
+      d.window = in.window;
+      d.nstages = in.kind == SFFT_KIND_FFAST ? in.R : 0;
+      d.max_peel_rounds = in.max_peel_rounds;
+      d.found_cap = in.found_cap;
+      d.multi_cap = in.multi_cap;
+      for (int j = 0; j < SFFT_MAX_STAGES; j++) d.stageB[j] = in.stage_B[j];
+      for (int j = 0; j <= SFFT_MAX_STAGES; j++) d.stageOff[j] = p->stage_off[j];
+      for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.shift[r] = in.shift[r];
+      d.eps0 = in.eps0;
+      d.eps1 = in.eps1;
+      d.zero_k = in.zero_k;
+      d.single_k = in.single_k;
+      d.noise_var = in.noise_var;
+      d.noise_p_den = p->noise_p_den;
+      d.noise_at = p->noise_at;
+      d.y0_off = y0;
+      d.found_off = fc;
+      d.multi_off = mc;
+      d.fst_off = fst;
+      if (in.kind == SFFT_KIND_TREE) {
+        y0 += (int64_t)d.n * in.B0;
+        mc += d.multi_cap;
+
+        tree.push_back({(int64_t)d.n * in.B0 * (in.max_levels + 1), s});
+        maxB0 = std::max<int64_t>(maxB0, in.B0);
+        maxLevels = std::max(maxLevels, in.max_levels);
+      } else {
+        y0 += (int64_t)in.D * p->nb;
+        fst += p->nb * (2 * (int64_t)in.D + 2);
+        ffast.push_back({(int64_t)in.D * p->nb, s});
+        for (int j = 0; j < in.R; j++) maxStage = std::max<int64_t>(maxStage, in.stage_B[j]);
+      }
+      fc += d.found_cap;
+      nmax = std::max(nmax, d.n);
+      maxFcap = std::max(maxFcap, d.found_cap);
+      desc[s] = d;
+    }
+    mz = mc * (int64_t)nmax;  // multi-ton vectors use the batch-wide stride nmax
+    // longest solves first (LPT order) for the persistent level-0 launches
+    std::stable_sort(tree.begin(), tree.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    std::stable_sort(ffast.begin(), ffast.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    std::vector<int32_t> lists;
+    for (auto &t : tree) lists.push_back(t.second);
+    for (auto &t : ffast) lists.push_back(t.second);
+    auto ck = [](hipError_t e) { return e == hipSuccess; };
+    const size_t ns = (size_t)nsig;
+    if (!ck(b_desc.alloc(sizeof(SigDesc) * ns)) || !ck(b_io.alloc(sizeof(SigIO) * ns)) ||
+        !ck(b_st.alloc(sizeof(SigState) * ns)) || !ck(b_lists.alloc(sizeof(int32_t) * (lists.size() + 1))) ||
+        !ck(b_y0.alloc(sizeof(float2) * (size_t)y0)) || !ck(b_fst.alloc(sizeof(double2) * (size_t)fst)) ||
+        !ck(b_ff.alloc(sizeof(int64_t) * (size_t)fc)) || !ck(b_fa.alloc(sizeof(double2) * (size_t)fc)) ||
+        !ck(b_mc.alloc(2 * sizeof(int64_t) * (size_t)mc)) || !ck(b_my.alloc(2 * sizeof(float2) * (size_t)mz)) ||
+        !ck(b_mz.alloc(2 * sizeof(double2) * (size_t)mz)) || !ck(b_pre.alloc(3 * sizeof(int32_t) * (ns + 1))) ||
+        !ck(b_out.alloc((sizeof(int64_t) + sizeof(int32_t)) * 2)))
+      return SFFT_ENOMEM;
+    if (hipMemcpy(b_desc.p, desc.data(), sizeof(SigDesc) * ns, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b_lists.p, lists.data(), sizeof(int32_t) * lists.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return SFFT_EDEVICE;
+    const float2 *tw = nullptr;
+    if (device_twiddles(device, &tw) != hipSuccess) return SFFT_EDEVICE;
+    LaunchCtx &c = lc;
+    c.desc = (const SigDesc *)b_desc.p;
+    c.io = nullptr;
+    c.st = (SigState *)b_st.p;
+    c.A.y0 = (float2 *)b_y0.p;
+    c.A.fst = (double2 *)b_fst.p;
+    c.A.found_f = (int64_t *)b_ff.p;
+    c.A.found_a = (double2 *)b_fa.p;
+    c.A.multi_c[0] = (int64_t *)b_mc.p;
+    c.A.multi_c[1] = (int64_t *)b_mc.p + mc;
+    c.A.multi_y[0] = (float2 *)b_my.p;
+    c.A.multi_y[1] = (float2 *)b_my.p + mz;
+    c.A.multi_z[0] = (double2 *)b_mz.p;
+    c.A.multi_z[1] = (double2 *)b_mz.p + mz;
+    c.A.pre = (int32_t *)b_pre.p;
+    c.A.tw = tw;
+    c.tree_list = (const int32_t *)b_lists.p;
+    c.ffast_list = (const int32_t *)b_lists.p + tree.size();
+    c.nsig = nsig;
+    c.ntree = (int)tree.size();
+    c.nffast = (int)ffast.size();
+    c.nmax = nmax;
+    c.max_B0 = maxB0;
+    c.max_stage_B = maxStage;
+    c.max_found_cap = (int)npow2(maxFcap);
+    // static launch shape of every tree level
+    levels.clear();
+    for (int l = 1; l <= maxLevels; l++) {
+      LevelLaunch L{};
+      int64_t nf = 0, nd = 0, nch = 0;
+      for (int s = 0; s < nsig; s++) {
+        const SigDesc &d = desc[s];
+        if (d.kind != SFFT_KIND_TREE || l > d.max_levels) continue;
+        const int64_t Bp = d.B0 << (l - 1);
+        if (Bp <= kFftMax) nf += d.R;
+        else nd += (int64_t)d.R * ((Bp + kChunk - 1) / kChunk);
+        nch += 2 * (int64_t)d.multi_cap;
+      }
+      L.fft = nf > 0;
+      L.direct = nd > 0;
+      L.grid_fft = (int)std::min<int64_t>(std::max<int64_t>(nf, 1), 4096);
+      L.grid_direct = (int)std::min<int64_t>(std::max<int64_t>(nd, 1), 8192);
+      L.grid_children = (int)std::min<int64_t>(std::max<int64_t>((nch + kThreads - 1) / kThreads, 1), 2048);
+      levels.push_back(L);
+    }
+    io_last.assign(ns, SigIO{});
+    return SFFT_OK;
+  }
+
+  // The whole pipeline on stream s.  With `prof`, a timing event is recorded
+  // after every launch and the kernel id of each interval is appended.
+  struct Prof {
+    std::vector<hipEvent_t> ev;
+    std::vector<int32_t> id;
+  };
+  hipError_t launch_all(const LaunchCtx &c, hipStream_t s, Prof *prof = nullptr) {
+    hipError_t e;
+    auto mark = [&](int id) -> hipError_t {
+      if (!prof) return hipSuccess;
+      hipEvent_t ev;
+      hipError_t r = hipEventCreate(&ev);
+      if (r != hipSuccess) return r;
+      prof->ev.push_back(ev);
+      prof->id.push_back(id);
+      return hipEventRecord(ev, s);
+    };
+    if ((e = mark(-1)) != hipSuccess) return e;
+    if ((e = launch_reset(c, s)) != hipSuccess || (e = mark(SFFT_KERNEL_RESET)) != hipSuccess) return e;
+    if ((e = launch_level0(c, s)) != hipSuccess || (e = mark(SFFT_KERNEL_LEVEL0)) != hipSuccess) return e;
+    for (size_t i = 0; i < levels.size(); i++) {
+      const LevelLaunch &L = levels[i];
+      const int l = (int)i + 1;
+      if ((e = launch_sched(c, l, s)) != hipSuccess || (e = mark(SFFT_KERNEL_SCHED)) != hipSuccess) return e;
+      if (L.fft && ((e = launch_expand_fft(c, l, L.grid_fft, s)) != hipSuccess ||
+                    (e = mark(SFFT_KERNEL_EXPAND_FFT | (l << 8))) != hipSuccess))
+        return e;
+      if (L.direct && ((e = launch_expand_direct(c, l, L.grid_direct, s)) != hipSuccess ||
+                       (e = mark(SFFT_KERNEL_EXPAND_DIRECT | (l << 8))) != hipSuccess))
+        return e;
+      if ((e = launch_children(c, l, L.grid_children, s)) != hipSuccess ||
+          (e = mark(SFFT_KERNEL_CHILDREN | (l << 8))) != hipSuccess)
+        return e;
+    }
+    if ((e = launch_finalize(c, s)) != hipSuccess) return e;
+    return mark(SFFT_KERNEL_FINALIZE);
+  }
+};
+
+bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+std::mutex g_batch_mu;
+std::map<std::vector<const sfft_plan_s *>, std::unique_ptr<BatchCtx>> g_batches;
+
+// drop every cached batch that uses plan p
+void forget_plan(const sfft_plan_s *p) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (auto it = g_batches.begin(); it != g_batches.end();) {
+    if (std::find(it->first.begin(), it->first.end(), p) != it->first.end()) it = g_batches.erase(it);
+    else ++it;
+  }
+}
+
+int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
+  const sfft_params_t &p = *pp;
+  sfft_plan_info_t &in = pl->info;
+  memset(&in, 0, sizeof(in));
+  if (p.N < 2 || p.N > kMaxN || p.K < 1 || p.K > p.N || p.K > 4096) return SFFT_EINVAL;
+  if (p.delays < 1 || p.stages < 1) return SFFT_EINVAL;
+  if (p.mode != SFFT_EXACT && p.mode != SFFT_NOISY) return SFFT_EINVAL;
+  if (p.mode == SFFT_EXACT && p.delays < 2) return SFFT_EINVAL;
+  if (p.window < 0) return SFFT_EINVAL;
+  in.N = p.N;
+  in.K = p.K;
+  in.mode = p.mode;
+  in.D = p.delays;
+  in.window = p.window;
+  in.eps0 = p.eps0;
+  in.eps1 = p.eps1;
+  in.zero_k = p.zero_k;
+  in.single_k = p.single_k;
+  in.noise_var = p.noise_var;
+  in.max_peel_rounds = p.max_peel_rounds > 0 ? p.max_peel_rounds : 64;
+  in.found_cap = (int32_t)std::max<int64_t>(64, npow2(2 * p.K));
+  in.multi_cap = (int32_t)std::max<int64_t>(64, p.K);
+  memset(pl->stage_off, 0, sizeof(pl->stage_off));
+  double phi = 1.0;
+  int64_t cnt = 0;
+  if (pow2(p.N) && p.nstage_B == 0) {
+    // binary tree search over R rounds sharing B0
+    if (p.stages > SFFT_MAX_ROUNDS) return SFFT_EINVAL;
+    if ((int64_t)p.stages * p.delays > kMaxMeas) return SFFT_EUNSUPPORTED;
+    if (p.delays > kMaxD) return SFFT_EUNSUPPORTED;
+    int64_t B0 = p.B0;
+    if (B0 <= 0) B0 = std::min<int64_t>(npow2(2 * p.K), p.N);
+    if (!pow2(B0) || B0 > p.N) return SFFT_EINVAL;
+    if (B0 > kFftMax) return SFFT_EUNSUPPORTED;
+    in.kind = SFFT_KIND_TREE;
+    in.R = p.stages;
+    in.B0 = B0;
+    const int full = ilog2(p.N / B0);
+    in.max_levels = (p.max_levels < 0 || p.max_levels > full) ? full : p.max_levels;
+    SplitMix64 g{p.seed};
+    for (int r = 0; r < p.stages; r++) {
+      if (r == 0 && p.identity_round0) {
+        in.sigma[r] = 1;
+        in.shift[r] = 0;
+      } else {
+        const uint64_t a = g.next(), b = g.next();
+        in.sigma[r] = 2 * (a % (uint64_t)(p.N / 2)) + 1;
+        in.shift[r] = b % (uint64_t)p.N;
+      }
+    }
+    phi = std::pow(1.0 - 1.0 / (double)B0, (double)p.K);
+    cnt = (int64_t)p.stages * p.delays * B0;
+  } else {
+    // FFAST: co-prime stages, from explicit sizes or the prime powers of N
+    std::vector<int64_t> st;
+    if (p.nstage_B > 0) {
+      if (p.nstage_B > SFFT_MAX_STAGES) return SFFT_EINVAL;
+      int64_t prod = 1;
+      for (int j = 0; j < p.nstage_B; j++) {
+        const int64_t b = p.stage_B[j];
+        if (b < 1 || p.N % b) return SFFT_EINVAL;
+        for (int64_t o : st)
+          if (gcd64((uint64_t)o, (uint64_t)b) != 1) return SFFT_EINVAL;
+        st.push_back(b);
+        prod *= b;
+      }
+      (void)prod;
+    } else {
+      int64_t rest = p.N;
+      for (int64_t q = 2; q * q <= rest; q++) {
+        if (rest % q) continue;
+        int64_t pw = 1;
+        while (rest % q == 0) {
+          rest /= q;
+          pw *= q;
+        }
+        st.push_back(pw);
+      }
+      if (rest > 1) st.push_back(rest);
+      if ((int)st.size() != p.stages) return SFFT_EUNSUPPORTED;
+    }
+    if ((int)st.size() > SFFT_MAX_STAGES) return SFFT_EUNSUPPORTED;
+    if (p.delays > kMaxMeas || p.N >= (int64_t(1) << 31)) return SFFT_EUNSUPPORTED;
+    in.kind = SFFT_KIND_FFAST;
+    in.R = (int32_t)st.size();
+    int64_t off = 0;
+    double wphi = 0;
+    for (size_t j = 0; j < st.size(); j++) {
+      const int64_t b = st[j];
+      if (pow2(b) ? b > kFftMax : b > kDirectMax) return SFFT_EUNSUPPORTED;
+      in.stage_B[j] = b;
+      in.sigma[j] = 1;
+      in.shift[j] = 0;
+      pl->stage_off[j] = off;
+      off += b;
+      wphi += (double)b * std::pow(1.0 - 1.0 / (double)b, (double)p.K);
+    }
+    for (size_t j = st.size(); j <= SFFT_MAX_STAGES; j++) pl->stage_off[j] = off;
+    if (off > kMaxFfastBuckets) return SFFT_EUNSUPPORTED;
+    pl->nb = off;
+    phi = wphi / (double)off;
+    cnt = off * p.delays;
+  }
+  // noise estimator constants: p-quantile of B |yhat|^2 with p = min(1/4, phi/2)
+  const double q = std::min(0.25, phi / 2.0);
+  pl->noise_at = (int64_t)(q * (double)(cnt - 1));
+  pl->noise_p_den = -std::log(1.0 - q / phi);
+  return SFFT_OK;
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+int32_t check_io(const void *x, const void *idx, const void *val) {
+  if (!is_device_ptr(x) || !is_device_ptr(idx) || !is_device_ptr(val)) return SFFT_EINVAL;
+  return SFFT_OK;
+}
+
+BatchCtx *single_ctx(sfft_plan_t plan, int32_t *rc) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *rc = SFFT_EDEVICE;
+    return nullptr;
+  }
+  if (!plan->single || plan->single->device != dev) {
+    plan->single.reset(new BatchCtx());
+    const int32_t r = plan->single->build({plan});
+    if (r != SFFT_OK) {
+      plan->single.reset();
+      *rc = r;
+      return nullptr;
+    }
+  }
+  *rc = SFFT_OK;
+  return plan->single.get();
+}
+
+int32_t run_single(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val,
+                   int64_t *d_count, int32_t *d_status, hipStream_t stream) {
+  int32_t rc;
+  BatchCtx *b = single_ctx(plan, &rc);
+  if (!b) return rc;
+  LaunchCtx c = b->lc;
+  c.io = nullptr;
+  c.io1.x = (const float2 *)x;
+  c.io1.idx = out_idx;
+  c.io1.val = (float2 *)out_val;
+  c.io1.count = d_count ? d_count : (int64_t *)b->b_out.p;
+  c.io1.status = d_status ? d_status : (int32_t *)((int64_t *)b->b_out.p + 2);
+  if (b->launch_all(c, stream) != hipSuccess) return SFFT_EDEVICE;
+  return SFFT_OK;
+}
+
+}  // namespace
+
+// ================================================================== C-ABI
+extern "C" {
+
+void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages, int32_t delays,
+                      uint64_t seed) {
+  memset(p, 0, sizeof(*p));
+  p->N = N;
+  p->K = K;
+  p->stages = stages;
+  p->delays = delays;
+  p->seed = seed;
+  p->mode = SFFT_EXACT;
+  p->B0 = 0;
+  p->max_levels = -1;
+  p->window = 0;
+  p->identity_round0 = 0;
+  p->nstage_B = 0;
+  p->max_peel_rounds = 64;
+  p->eps0 = 1e-4;
+  p->eps1 = 1e-4;
+  p->zero_k = 4.0;
+  p->single_k = 4.0;
+  p->noise_var = 0.0;
+}
+
+sfft_plan_t sfft_plan_ex(const sfft_params_t *p) {
+  if (!p) {
+    fail(SFFT_EINVAL);
+    return nullptr;
+  }
+  std::unique_ptr<sfft_plan_s> pl(new sfft_plan_s());
+  const int32_t rc = validate_and_fill(p, pl.get());
+  if (rc != SFFT_OK) {
+    fail(rc);
+    return nullptr;
+  }
+  g_last_error = SFFT_OK;
+  return pl.release();
+}
+
+sfft_plan_t sfft_plan(int64_t N, int64_t K, int32_t stages, int32_t delays, uint64_t seed) {
+  sfft_params_t p;
+  sfft_params_init(&p, N, K, stages, delays, seed);
+  return sfft_plan_ex(&p);
+}
+
+int32_t sfft_plan_info(sfft_plan_t plan, sfft_plan_info_t *out) {
+  if (!plan || !out) return fail(SFFT_EINVAL);
+  *out = plan->info;
+  return SFFT_OK;
+}
+
+void sfft_destroy(sfft_plan_t plan) {
+  if (!plan) return;
+  forget_plan(plan);
+  delete plan;
+}
+
+int64_t sfft_exec(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val) {
+  if (!plan) return fail(SFFT_EINVAL);
+  int32_t rc = check_io(x, out_idx, out_val);
+  if (rc != SFFT_OK) return fail(rc);
+  rc = run_single(plan, x, out_idx, out_val, nullptr, nullptr, nullptr);
+  if (rc != SFFT_OK) return fail(rc);
+  int64_t cnt = 0;
+  if (hipMemcpy(&cnt, plan->single->b_out.p, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(SFFT_EDEVICE);
+  return cnt;
+}
+
+int32_t sfft_exec_async(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val,
+                        int64_t *d_count, int32_t *d_status, void *stream) {
+  if (!plan) return fail(SFFT_EINVAL);
+  int32_t rc = check_io(x, out_idx, out_val);
+  if (rc != SFFT_OK) return fail(rc);
+  if ((d_count && !is_device_ptr(d_count)) || (d_status && !is_device_ptr(d_status)))
+    return fail(SFFT_EINVAL);
+  rc = run_single(plan, x, out_idx, out_val, d_count, d_status, as_stream(stream));
+  return rc == SFFT_OK ? SFFT_OK : fail(rc);
+}
+
+int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs, int64_t *const *idx,
+                           void *const *vals, int64_t *d_counts, int32_t *d_status, int32_t n,
+                           void *stream, int32_t flags) {
+  if (!plans || !xs || !idx || !vals || n < 1) return fail(SFFT_EINVAL);
+  if (!is_device_ptr(d_counts) || !is_device_ptr(d_status)) return fail(SFFT_EINVAL);
+  std::vector<const sfft_plan_s *> key(plans, plans + n);
+  for (int i = 0; i < n; i++) {
+    if (!plans[i]) return fail(SFFT_EINVAL);
+    const int32_t rc = check_io(xs[i], idx[i], vals[i]);
+    if (rc != SFFT_OK) return fail(rc);
+  }
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SFFT_EDEVICE);
+  auto &slot = g_batches[key];
+  if (!slot || slot->device != dev) {
+    slot.reset(new BatchCtx());
+    const int32_t rc = slot->build(key);
+    if (rc != SFFT_OK) {
+      g_batches.erase(key);
+      return fail(rc);
+    }
+    if (hipStreamCreateWithFlags(&slot->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&slot->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&slot->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&slot->ev_io, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc((void **)&slot->io_pinned, sizeof(SigIO) * (size_t)n) != hipSuccess) {
+      g_batches.erase(key);
+      return fail(SFFT_EDEVICE);
+    }
+  }
+  BatchCtx *b = slot.get();
+  hipStream_t caller = as_stream(stream);
+  // per-call pointers: upload only when they changed
+  std::vector<SigIO> io(n);
+  for (int i = 0; i < n; i++) {
+    io[i] = SigIO{};
+    io[i].x = (const float2 *)xs[i];
+    io[i].idx = idx[i];
+    io[i].val = (float2 *)vals[i];
+    io[i].count = d_counts + i;
+    io[i].status = d_status + i;
+  }
+  if (hipEventRecord(b->ev_in, caller) != hipSuccess ||
+      hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess)
+    return fail(SFFT_EDEVICE);
+  if (memcmp(io.data(), b->io_last.data(), sizeof(SigIO) * (size_t)n) != 0) {
+    if (b->io_pending && hipEventSynchronize(b->ev_io) != hipSuccess) return fail(SFFT_EDEVICE);
+    memcpy(b->io_pinned, io.data(), sizeof(SigIO) * (size_t)n);
+    if (hipMemcpyAsync(b->b_io.p, b->io_pinned, sizeof(SigIO) * (size_t)n, hipMemcpyHostToDevice,
+                       b->stream) != hipSuccess ||
+        hipEventRecord(b->ev_io, b->stream) != hipSuccess)
+      return fail(SFFT_EDEVICE);
+    b->io_pending = true;
+    b->io_last = io;
+  }
+  LaunchCtx c = b->lc;
+  c.io = (const SigIO *)b->b_io.p;
+  if (flags & SFFT_BATCH_NO_GRAPH) {
+    if (b->launch_all(c, b->stream) != hipSuccess) return fail(SFFT_EDEVICE);
+  } else {
+    if (!b->gexec) {
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(SFFT_EDEVICE);
+      const hipError_t le = b->launch_all(c, b->stream);
+      const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+      if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(SFFT_EDEVICE);
+      }
+      const hipError_t ie = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) {
+        b->gexec = nullptr;
+        return fail(SFFT_EDEVICE);
+      }
+    }
+    if (hipGraphLaunch(b->gexec, b->stream) != hipSuccess) return fail(SFFT_EDEVICE);
+  }
+  if (hipEventRecord(b->ev_out, b->stream) != hipSuccess ||
+      hipStreamWaitEvent(caller, b->ev_out, 0) != hipSuccess)
+    return fail(SFFT_EDEVICE);
+  return SFFT_OK;
+}
+
+int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
+                                int64_t *const *idx, void *const *vals, int64_t *d_counts,
+                                int32_t *d_status, int32_t n, float *ms, int32_t *kernel,
+                                int32_t cap) {
+  // make sure the batch context exists and holds these pointers
+  int32_t rc = sfft_exec_batch_ex(plans, xs, idx, vals, d_counts, d_status, n, nullptr,
+                                  SFFT_BATCH_NO_GRAPH);
+  if (rc != SFFT_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  std::vector<const sfft_plan_s *> key(plans, plans + n);
+  BatchCtx *b = g_batches[key].get();
+  LaunchCtx c = b->lc;
+  c.io = (const SigIO *)b->b_io.p;
+  BatchCtx::Prof prof;
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(SFFT_EDEVICE);
+  const hipError_t le = b->launch_all(c, b->stream, &prof);
+  const hipError_t se = hipStreamSynchronize(b->stream);
+  int32_t cnt = 0;
+  if (le == hipSuccess && se == hipSuccess) {
+    for (size_t i = 1; i < prof.ev.size() && cnt < cap; i++, cnt++) {
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, prof.ev[i - 1], prof.ev[i]);
+      if (ms) ms[cnt] = t;
+      if (kernel) kernel[cnt] = prof.id[i];
+    }
+  }
+  for (hipEvent_t e : prof.ev) (void)hipEventDestroy(e);
+  if (le != hipSuccess || se != hipSuccess) return fail(SFFT_EDEVICE);
+  return cnt;
+}
+
+int32_t sfft_exec_batch(const sfft_plan_t *plans, const void *const *xs, int64_t *const *idx,
+                        void *const *vals, int64_t *d_counts, int32_t *d_status, int32_t n,
+                        void *stream) {
+  return sfft_exec_batch_ex(plans, xs, idx, vals, d_counts, d_status, n, stream, 0);
+}
+
+int32_t sfft_bucketize(sfft_plan_t plan, const void *x, void *out) {
+  if (!plan) return fail(SFFT_EINVAL);
+  if (!is_device_ptr(x) || !is_device_ptr(out)) return fail(SFFT_EINVAL);
+  int32_t rc;
+  BatchCtx *b = single_ctx(plan, &rc);
+  if (!b) return fail(rc);
+  LaunchCtx c = b->lc;
+  c.io = nullptr;
+  c.io1.x = (const float2 *)x;
+  c.io1.count = (int64_t *)b->b_out.p;
+  c.io1.status = (int32_t *)((int64_t *)b->b_out.p + 2);
+  if (launch_reset(c, nullptr) != hipSuccess || launch_level0(c, nullptr) != hipSuccess ||
+      launch_export_level0(c, out, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+    return fail(SFFT_EDEVICE);
+  return SFFT_OK;
+}
+
+static void fill_stats(const SigState &st, const SigDesc &d, int64_t count, int32_t status,
+                       sfft_stats_t *out) {
+  out->count = count;
+  out->status = status;
+  out->levels = st.levels;
+  out->samples = st.samples;
+  out->found = st.found;
+  out->noise_var = st.noise_var;
+  out->sref2 = st.sref2;
+  out->level_mask = st.level_mask;
+  (void)d;
+}
+
+int32_t sfft_exec_stats(sfft_plan_t plan, sfft_stats_t *out) {
+  if (!plan || !out || !plan->single) return fail(SFFT_EINVAL);
+  BatchCtx *b = plan->single.get();
+  SigState st;
+  int64_t cnt = 0;
+  int32_t status = 0;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(&st, b->b_st.p, sizeof(SigState), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&cnt, b->b_out.p, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&status, (int64_t *)b->b_out.p + 2, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(SFFT_EDEVICE);
+  fill_stats(st, b->desc[0], cnt, status, out);
+  return SFFT_OK;
+}
+
+int32_t sfft_batch_stats(const sfft_plan_t *plans, int32_t n, int32_t i, sfft_stats_t *out) {
+  if (!plans || n < 1 || i < 0 || i >= n || !out) return fail(SFFT_EINVAL);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  std::vector<const sfft_plan_s *> key(plans, plans + n);
+  auto it = g_batches.find(key);
+  if (it == g_batches.end()) return fail(SFFT_EINVAL);
+  BatchCtx *b = it->second.get();
+  SigState st;
+  int64_t cnt = 0;
+  int32_t status = 0;
+  const SigIO &io = b->io_last[i];
+  if (hipStreamSynchronize(b->stream) != hipSuccess ||
+      hipMemcpy(&st, (SigState *)b->b_st.p + i, sizeof(SigState), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&cnt, io.count, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&status, io.status, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(SFFT_EDEVICE);
+  fill_stats(st, b->desc[i], cnt, status, out);
+  return SFFT_OK;
+}
+
+void sfft_release_batches(void) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  g_batches.clear();
+}
+
+int32_t sfft_last_error(void) { return g_last_error; }
+
+const char *sfft_strerror(int32_t code) {
+  switch (code) {
+    case SFFT_OK: return "ok";
+    case SFFT_EINVAL: return "invalid argument";
+    case SFFT_EUNSUPPORTED: return "unsupported size or factorisation";
+    case SFFT_ENOMEM: return "device allocation failed";
+    case SFFT_EDEVICE: return "HIP runtime or kernel launch error";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

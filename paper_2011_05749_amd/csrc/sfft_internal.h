@@ -1,0 +1,105 @@
+// sfft_internal.h -- layouts shared by the host driver and the gfx950 kernels
+// of the aliasing-filter sparse FFT library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sfft.h"
+
+namespace sfft {
+
+constexpr int kThreads = 256;        // work-group size of every kernel
+constexpr int kFftMax = 8192;        // largest LDS-resident pow2 FFT (64 KiB complex64)
+constexpr int kLog2FftMax = 13;
+constexpr int kDirectMax = 2048;     // largest non-pow2 stage (direct DFT in LDS)
+constexpr int kChunk = 2048;         // samples per direct partial-sum work item
+constexpr int kPerThread = kChunk / kThreads;
+constexpr int kMaxD = 4;             // delays handled by the direct partial-sum kernel
+constexpr int kMaxMeas = 64;         // rounds x delays per class vector
+constexpr int kMaxFfastBuckets = 4096;
+
+// Static description of one signal of a batch (from its plan).
+struct SigDesc {
+  int64_t N, K, B0;
+  int32_t log2N;          // -1 when N is not a power of two
+  int32_t log2B0;
+  int32_t kind, mode, R, D, n;
+  int32_t max_levels, window, nstages, max_peel_rounds;
+  int32_t found_cap, multi_cap;
+  int32_t pad0;
+  int64_t stageB[SFFT_MAX_STAGES];
+  int64_t stageOff[SFFT_MAX_STAGES + 1];
+  uint64_t shift[SFFT_MAX_ROUNDS];
+  double eps0, eps1, zero_k, single_k, noise_var;
+  double noise_p_den;     // -ln(1 - p/phi) of the noise estimator
+  int64_t noise_at;       // rank of the p-quantile among the level-0 entries
+  // offsets into the batch arenas
+  int64_t y0_off;         // float2 level-0 planes (tree: n*B0; FFAST: D*sum B)
+  int64_t fst_off;        // double2 FFAST state (D*sum B) + per-bucket scratch
+  int64_t found_off;      // found list slots
+  int64_t multi_off;      // multi-ton slots (per parity)
+};
+
+// Per-call pointers of one signal.
+struct SigIO {
+  const float2 *x;
+  int64_t *idx;
+  float2 *val;
+  int64_t *count;
+  int32_t *status;
+  int32_t pad[2];
+};
+
+// Per-signal device state of one exec.
+struct SigState {
+  int32_t found;          // appended frequencies
+  int32_t multi[2];       // multi-tons per level parity
+  int32_t flags;          // bit 0: unresolved multi-ton / cap; bit 1: list overflow
+  int32_t levels;         // deepest tree level opened / peeling rounds
+  int32_t pad;
+  int64_t samples;
+  uint64_t level_mask;    // bit l set when tree level l gathered samples
+  double sref2;
+  double noise_var;
+};
+
+struct Arena {
+  float2 *y0;
+  double2 *fst;
+  int64_t *found_f;
+  double2 *found_a;
+  int64_t *multi_c[2];
+  float2 *multi_y[2];
+  double2 *multi_z[2];
+  int32_t *pre;           // 3 prefix arrays of nsig+1: fft items, direct items, children
+  const float2 *tw;       // e^{-2 pi i k / kFftMax}, k < kFftMax
+};
+
+// host-side kernel launchers (sfft_kernels.hip)
+struct LaunchCtx {
+  const SigDesc *desc;
+  const SigIO *io;        // per-signal pointers in device memory (batches), or
+  SigIO io1;              // null and the single signal's pointers by value
+  SigState *st;
+  Arena A;
+  const int32_t *tree_list;
+  const int32_t *ffast_list;
+  int32_t nsig, ntree, nffast;
+  int32_t nmax;           // largest n = R*D of the batch (selects the template)
+  int32_t max_B0;
+  int32_t max_stage_B;
+  int32_t max_found_cap;
+};
+
+hipError_t launch_reset(const LaunchCtx &c, hipStream_t s);
+hipError_t launch_level0(const LaunchCtx &c, hipStream_t s);
+hipError_t launch_sched(const LaunchCtx &c, int level, hipStream_t s);
+hipError_t launch_expand_fft(const LaunchCtx &c, int level, int grid, hipStream_t s);
+hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStream_t s);
+hipError_t launch_children(const LaunchCtx &c, int level, int grid, hipStream_t s);
+hipError_t launch_finalize(const LaunchCtx &c, hipStream_t s);
+// level-0 class vectors in class-major order (tree: out[c*n + i]; FFAST as stored)
+hipError_t launch_export_level0(const LaunchCtx &c, void *out, hipStream_t s);
+
+}  // namespace sfft

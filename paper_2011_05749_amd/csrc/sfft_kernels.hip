@@ -1,0 +1,1068 @@
+// sfft_kernels.hip -- gfx950 kernels of the aliasing-filter sparse FFT.
+//
+// Pipeline of one exec (any number of signals, one pass per phase):
+//   k_reset        zero the per-signal state
+//   k_level0_tree  (power-of-two N) per signal: gather of the B0 samples of
+//                  every round and delay (Eq. 5, advance shift), B0-point FFT
+//                  in LDS (Eq. 6), level-0 statistics, classification of the
+//                  B0 classes (Sect. 3.2 Subproblems 1-2) with wave-ballot
+//                  compaction of single-tons and multi-tons
+//   k_ffast        (co-prime N) per signal: stage DFTs and the whole peeling
+//                  decoder (Sect. 3.2, Subproblem 3, Eq. 20) in one work-group
+//   per tree level l >= 1 (Sect. 3.3):
+//     k_sched        prefix sums of the work of every signal
+//     k_expand_fft   B'-point FFT of the B' odd-offset samples (B' <= 8192)
+//     k_expand_direct  partial DFT sums of the odd-offset samples at the
+//                  parents' bins only (Eq. 23 evaluated per node), B' > 8192
+//     k_children     child vectors 1/2 (parent +- w Z), classification
+//   k_finalize     top-K by magnitude, sort by index, outputs
+//
+// Bucket relabeling: the GPU reads samples in natural order m = 0..B-1 at
+// stride L.  A permutation sigma only relabels buckets under the aliasing
+// filter (bin sigma c of the permuted transform is bin c of the natural one),
+// so class c is read directly at bin c and sigma never touches the gather.
+#include <hip/hip_runtime.h>
+
+#include "sfft_internal.h"
+
+namespace sfft {
+
+namespace {
+
+constexpr int kZero = 0, kSingle = 1, kMulti = 2;
+
+__device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 to_d(float2 v) { return make_double2(v.x, v.y); }
+
+// e^{sign * 2 pi i t / M}, t an exact integer already reduced modulo M
+__device__ __forceinline__ double2 unit_d(uint64_t t, uint64_t M, int sign) {
+  double s, c;
+  sincospi(2.0 * (double)t / (double)M, &s, &c);
+  return make_double2(c, sign * s);
+}
+
+__device__ __forceinline__ uint64_t mod_n(uint64_t v, const SigDesc &d) {
+  return d.log2N >= 0 ? (v & (uint64_t)(d.N - 1)) : v % (uint64_t)d.N;
+}
+
+// delay of measurement i of a class vector: shift of its round + its delay
+__device__ __forceinline__ uint64_t tau_of(const SigDesc &d, int i) {
+  if (d.kind == SFFT_KIND_FFAST) return (uint64_t)i;
+  return mod_n(d.shift[i / d.D] + (uint64_t)(i % d.D), d);
+}
+
+__device__ __forceinline__ SigIO io_of(const LaunchCtx &c, int s) {
+  return c.io ? c.io[s] : c.io1;
+}
+
+__device__ __forceinline__ uint32_t bitrev(uint32_t m, int lg) {
+  return lg == 0 ? 0u : (__brev(m) >> (32 - lg));
+}
+
+// In-place radix-2 decimation-in-time FFT of B = 2^lg complex64 values held in
+// LDS in bit-reversed order; forward sign e^{-2 pi i hm / B}, no scaling.
+// Twiddles come from the kFftMax-point table.
+__device__ void fft_lds(float2 *X, int lg, const float2 *__restrict__ tw) {
+  const int B = 1 << lg;
+  for (int s = 1; s <= lg; s++) {
+    const int h = 1 << (s - 1);
+    const int tsh = kLog2FftMax - s;
+    for (int t = threadIdx.x; t < (B >> 1); t += blockDim.x) {
+      const int j = t & (h - 1);
+      const int i0 = ((t >> (s - 1)) << s) + j;
+      const int i1 = i0 + h;
+      const float2 w = tw[j << tsh];
+      const float2 a = X[i0];
+      const float2 b = cmulf(X[i1], w);
+      X[i0] = make_float2(a.x + b.x, a.y + b.y);
+      X[i1] = make_float2(a.x - b.x, a.y - b.y);
+    }
+    __syncthreads();
+  }
+}
+
+// wave-wide compaction: lanes with pred get consecutive slots of *counter;
+// must be reached by every lane of the wave
+__device__ __forceinline__ int wave_append(int32_t *counter, bool pred) {
+  const unsigned long long mask = __ballot(pred);
+  if (mask == 0ull) return -1;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)mask) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, (int)__popcll(mask));
+  base = __shfl(base, leader);
+  return base + (int)__popcll(mask & ((1ull << lane) - 1ull));
+}
+
+__device__ double block_sum_d(double v, double *red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double t = 0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); i++) t += red[i];
+  __syncthreads();
+  return t;
+}
+
+// exclusive scan of one int per thread over the work-group; returns the
+// prefix, *total receives the sum
+__device__ int block_scan_excl(int v, int *red, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int inc = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(inc, o);
+    if (lane >= o) inc += u;
+  }
+  __syncthreads();
+  if (lane == 63) red[w] = inc;
+  __syncthreads();
+  int before = 0, tot = 0;
+  for (int i = 0; i < nw; i++) {
+    if (i < w) before += red[i];
+    tot += red[i];
+  }
+  __syncthreads();
+  *total = tot;
+  return before + inc - v;
+}
+
+// index s with pre[s] <= item < pre[s+1] (pre non-decreasing, n+1 entries)
+__device__ __forceinline__ int find_owner(const int32_t *pre, int n, int item) {
+  int lo = 0, hi = n;  // pre[lo] <= item < pre[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pre[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// k-th smallest (0-based) of scale*|v|^2 over cnt complex64 values, by a
+// four-pass radix select on the float bit patterns (all values >= 0)
+__device__ float select_kth_power(const float2 *v, int64_t cnt, float scale, int64_t k,
+                                  uint32_t *hist, uint32_t *sel) {
+  uint32_t prefix = 0, mask = 0;
+  for (int pass = 0; pass < 4; pass++) {
+    const int sh = 24 - 8 * pass;
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+      const float2 y = v[i];
+      const float p = scale * (y.x * y.x + y.y * y.y);
+      const uint32_t key = __float_as_uint(p);
+      if ((key & mask) == prefix) atomicAdd(&hist[(key >> sh) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t acc = 0;
+      uint32_t dsel = 255;
+      for (uint32_t dg = 0; dg < 256; dg++) {
+        if (acc + (int64_t)hist[dg] > k) { dsel = dg; break; }
+        acc += hist[dg];
+      }
+      sel[0] = dsel;
+      sel[1] = (uint32_t)(k - acc);
+    }
+    __syncthreads();
+    prefix |= sel[0] << sh;
+    mask |= 255u << sh;
+    k = sel[1];
+    __syncthreads();
+  }
+  return __uint_as_float(prefix);
+}
+
+struct Verdict {
+  int cls;
+  int64_t f;
+  double2 a;
+};
+
+// Singleton test (Sect. 3.2, Subproblems 1-2) of one class vector Y (n values,
+// rounds x D layout) of class c among B buckets.
+template <int NMAX>
+__device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
+                            int64_t c, int64_t B, double sref2, double noise_var) {
+  Verdict v;
+  v.cls = kZero;
+  v.f = -1;
+  v.a = make_double2(0.0, 0.0);
+  const int64_t N = d.N;
+  const int64_t L = N / B;
+  const int D = d.D;
+  double E2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; i++)
+    if (i < n) E2 += Y[i].x * Y[i].x + Y[i].y * Y[i].y;
+  double T0sq, T1sq;
+  if (d.mode == SFFT_EXACT) {
+    T0sq = d.eps0 * d.eps0 * sref2 * (double)n;
+    T1sq = d.eps1 * d.eps1 * E2;
+  } else {
+    const double sb2 = noise_var / (double)B;
+    T0sq = sb2 * ((double)n + d.zero_k * sqrt((double)n));
+    T1sq = sb2 * ((double)(n - 1) + d.single_k * sqrt((double)(n - 1)));
+  }
+  if (E2 <= T0sq) return v;
+
+  // phase-to-index (exact-case locator, advance-shift sign)
+  int64_t ksnap = 0;
+  if (D >= 2) {
+    double2 P = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int i = 0; i + 1 < NMAX; i++) {
+      if (i + 1 < n && (i % D) != D - 1 && (i / D) < rounds) {
+        const double2 a = Y[i + 1], b = Y[i];
+        P.x += a.x * b.x + a.y * b.y;
+        P.y += a.y * b.x - a.x * b.y;
+      }
+    }
+    double phi = atan2(P.y, P.x);
+    const double two_pi = 6.283185307179586476925286766559;
+    if (phi < 0) phi += two_pi;
+    const double u = phi * (double)N / two_pi;
+    const double kf = floor((u - (double)c) / (double)B + 0.5);
+    int64_t k = (int64_t)kf % L;
+    if (k < 0) k += L;
+    ksnap = k;
+  }
+  int64_t k = ksnap;
+  if (d.mode == SFFT_NOISY) {
+    // enumeration of the candidates c + kB (Sect. 3.1, Method 2) by the
+    // matched filter |sum_i Y_i e^{-2 pi i (c + kB) tau_i / N}|, FP32 MACs,
+    // twiddles re-anchored exactly every 32 candidates
+    int64_t lo, cnt;
+    if (d.window > 0 && D >= 2 && 2 * (int64_t)d.window + 1 < L) {
+      lo = ksnap - d.window;
+      cnt = 2 * (int64_t)d.window + 1;
+    } else {
+      lo = 0;
+      cnt = L;
+    }
+    float2 Yf[NMAX], tw[NMAX], st[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; i++) Yf[i] = make_float2((float)Y[i].x, (float)Y[i].y);
+    float best = -1.0f;
+    int64_t bestk = 0;
+    for (int64_t o0 = 0; o0 < cnt; o0 += 32) {
+      const int64_t k0 = ((lo + o0) % L + L) % L;
+      const uint64_t f0 = (uint64_t)(c + k0 * B);
+#pragma unroll
+      for (int i = 0; i < NMAX; i++) {
+        if (i < n) {
+          const uint64_t ti = tau_of(d, i);
+          const double2 a = unit_d(mod_n(f0 * ti, d), (uint64_t)N, -1);
+          const double2 b = unit_d(mod_n(mod_n((uint64_t)B * ti, d), d), (uint64_t)N, -1);
+          tw[i] = make_float2((float)a.x, (float)a.y);
+          st[i] = make_float2((float)b.x, (float)b.y);
+        }
+      }
+      const int64_t lim = (cnt - o0) < 32 ? (cnt - o0) : 32;
+      for (int64_t o = 0; o < lim; o++) {
+        float gx = 0.f, gy = 0.f;
+#pragma unroll
+        for (int i = 0; i < NMAX; i++) {
+          if (i < n) {
+            gx += Yf[i].x * tw[i].x - Yf[i].y * tw[i].y;
+            gy += Yf[i].x * tw[i].y + Yf[i].y * tw[i].x;
+            tw[i] = cmulf(tw[i], st[i]);
+          }
+        }
+        const float m2 = gx * gx + gy * gy;
+        int64_t kk = k0 + o;
+        if (kk >= L) kk -= L;
+        if (m2 > best || (m2 == best && kk < bestk)) {
+          best = m2;
+          bestk = kk;
+        }
+      }
+    }
+    k = bestk;
+  }
+  const int64_t f = c + k * B;
+  // value: least-squares mean of the de-rotated measurements (FP64)
+  double2 e[NMAX];
+  double2 a = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int i = 0; i < NMAX; i++) {
+    if (i < n) {
+      e[i] = unit_d(mod_n((uint64_t)f * tau_of(d, i), d), (uint64_t)N, -1);
+      const double2 t = cmul(Y[i], e[i]);
+      a.x += t.x;
+      a.y += t.y;
+    }
+  }
+  a.x /= (double)n;
+  a.y /= (double)n;
+  double rho2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; i++) {
+    if (i < n) {
+      const double2 r = cmul(a, make_double2(e[i].x, -e[i].y));
+      const double ex = Y[i].x - r.x, ey = Y[i].y - r.y;
+      rho2 += ex * ex + ey * ey;
+    }
+  }
+  v.f = f;
+  v.a = a;
+  v.cls = (rho2 <= T1sq) ? kSingle : kMulti;
+  return v;
+}
+
+__device__ __forceinline__ void push_found(const LaunchCtx &c, int s, const SigDesc &d, int slot,
+                                           int64_t f, double2 a) {
+  if (slot < d.found_cap) {
+    c.A.found_f[d.found_off + slot] = f;
+    c.A.found_a[d.found_off + slot] = a;
+  } else {
+    atomicOr(&c.st[s].flags, 3);
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ void k_reset(LaunchCtx c) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= c.nsig) return;
+  SigState z;
+  z.found = 0;
+  z.multi[0] = 0;
+  z.multi[1] = 0;
+  z.flags = 0;
+  z.levels = 0;
+  z.pad = 0;
+  z.samples = 0;
+  z.level_mask = 0;
+  z.sref2 = 0.0;
+  z.noise_var = 0.0;
+  c.st[s] = z;
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(kThreads) void k_level0_tree(LaunchCtx c) {
+  extern __shared__ float2 lds[];
+  __shared__ double red[16];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sel[2];
+  for (int li = blockIdx.x; li < c.ntree; li += gridDim.x) {
+    const int s = c.tree_list[li];
+    const SigDesc &d = c.desc[s];
+    const float2 *__restrict__ x = io_of(c, s).x;
+    const int64_t N = d.N;
+    const int lb = d.log2B0;
+    const int64_t B = d.B0;
+    const int64_t L = N >> lb;
+    const int n = d.n;
+    float2 *Y0 = c.A.y0 + d.y0_off;
+    double psum = 0.0;
+    const float inv = 1.0f / (float)B;
+    for (int i = 0; i < n; i++) {
+      const uint64_t tau = tau_of(d, i);
+      for (int64_t m = threadIdx.x; m < B; m += blockDim.x) {
+        const uint64_t pos = ((uint64_t)m * (uint64_t)L + tau) & (uint64_t)(N - 1);
+        lds[bitrev((uint32_t)m, lb)] = x[pos];
+      }
+      __syncthreads();
+      fft_lds(lds, lb, c.A.tw);
+      for (int64_t m = threadIdx.x; m < B; m += blockDim.x) {
+        const float2 v = make_float2(lds[m].x * inv, lds[m].y * inv);
+        Y0[(int64_t)i * B + m] = v;
+        psum += (double)v.x * v.x + (double)v.y * v.y;
+      }
+      __syncthreads();
+    }
+    const double sref2 = block_sum_d(psum, red) / (double)(n * B);
+    double nv = d.noise_var;
+    if (d.mode == SFFT_NOISY && !(nv > 0.0)) {
+      const float q = select_kth_power(Y0, (int64_t)n * B, (float)B, d.noise_at, hist, sel);
+      nv = (double)q / d.noise_p_den;
+    }
+    for (int64_t base = 0; base < B; base += blockDim.x) {
+      const int64_t cc = base + threadIdx.x;
+      const bool valid = cc < B;
+      Verdict v;
+      v.cls = kZero;
+      double2 Y[NMAX];
+#pragma unroll
+      for (int i = 0; i < NMAX; i++) Y[i] = make_double2(0.0, 0.0);
+      if (valid) {
+#pragma unroll
+        for (int i = 0; i < NMAX; i++)
+          if (i < n) Y[i] = to_d(Y0[(int64_t)i * B + cc]);
+        v = classify<NMAX>(Y, d, n, d.R, cc, B, sref2, nv);
+      }
+      const bool single = valid && v.cls == kSingle;
+      const int fs = wave_append(&c.st[s].found, single);
+      if (single) push_found(c, s, d, fs, v.f, v.a);
+      const bool multi = valid && v.cls == kMulti;
+      const bool open = multi && L >= 2 && d.max_levels >= 1;
+      if (multi && !open) atomicOr(&c.st[s].flags, 1);
+      const int ms = wave_append(&c.st[s].multi[0], open);
+      if (open) {
+        if (ms < d.multi_cap) {
+          const int64_t slot = d.multi_off + ms;
+          c.A.multi_c[0][slot] = cc;
+#pragma unroll
+          for (int i = 0; i < NMAX; i++)
+            if (i < n) {
+              c.A.multi_y[0][slot * c.nmax + i] = make_float2((float)Y[i].x, (float)Y[i].y);
+              c.A.multi_z[0][slot * c.nmax + i] = make_double2(0.0, 0.0);
+            }
+        } else {
+          atomicOr(&c.st[s].flags, 3);
+        }
+      }
+    }
+    if (threadIdx.x == 0) {
+      c.st[s].sref2 = sref2;
+      c.st[s].noise_var = nv;
+      c.st[s].samples = (int64_t)n * B;
+      c.st[s].level_mask = 1ull;
+      c.st[s].levels = 0;
+    }
+    __syncthreads();
+  }
+}
+
+// FFAST: one work-group per signal runs the stage DFTs and the peeling decoder.
+template <int NMAX>
+__global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
+  extern __shared__ float2 lds[];                 // kFftMax samples
+  float2 *twd = lds + kFftMax;                     // kDirectMax twiddles
+  uint8_t *active = (uint8_t *)(twd + kDirectMax); // kMaxFfastBuckets each
+  uint8_t *det = active + kMaxFfastBuckets;
+  uint8_t *modf = det + kMaxFfastBuckets;
+  uint8_t *cls = modf + kMaxFfastBuckets;
+  uint8_t *isnew = cls + kMaxFfastBuckets;
+  __shared__ double red[16];
+  __shared__ int ired[16];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sel[2];
+  __shared__ int flag_any;
+  for (int li = blockIdx.x; li < c.nffast; li += gridDim.x) {
+    const int s = c.ffast_list[li];
+    const SigDesc &d = c.desc[s];
+    const float2 *__restrict__ x = io_of(c, s).x;
+    const int64_t N = d.N;
+    const int D = d.D;
+    const int S = d.nstages;
+    const int nb = (int)d.stageOff[S];
+    float2 *Y0 = c.A.y0 + d.y0_off;           // complex64 copy (bucketization output)
+    double2 *Yf = c.A.fst + d.fst_off;         // FP64 peeling state
+    double2 *va = Yf + (int64_t)nb * D;
+    int64_t *vf = (int64_t *)(va + nb);
+    double psum = 0.0;
+    for (int j = 0; j < S; j++) {
+      const int64_t B = d.stageB[j];
+      const int64_t L = N / B;
+      const int lb = (B & (B - 1)) == 0 ? (31 - __clz((int)B)) : -1;
+      const float inv = 1.0f / (float)B;
+      if (lb < 0) {
+        for (int t = threadIdx.x; t < B; t += blockDim.x) {
+          const double2 w = unit_d((uint64_t)t, (uint64_t)B, -1);
+          twd[t] = make_float2((float)w.x, (float)w.y);
+        }
+      }
+      for (int dl = 0; dl < D; dl++) {
+        for (int64_t m = threadIdx.x; m < B; m += blockDim.x) {
+          const uint64_t pos = ((uint64_t)m * (uint64_t)L + (uint64_t)dl) % (uint64_t)N;
+          lds[lb >= 0 ? (int64_t)bitrev((uint32_t)m, lb) : m] = x[pos];
+        }
+        __syncthreads();
+        float2 res[kDirectMax / kThreads];
+        if (lb >= 0) {
+          fft_lds(lds, lb, c.A.tw);
+        } else {
+          // direct B-point DFT for a stage that is not a power of two
+          int q = 0;
+          for (int64_t h = threadIdx.x; h < B; h += blockDim.x, q++) {
+            float ax = 0.f, ay = 0.f;
+            int64_t t = 0;
+            for (int64_t m = 0; m < B; m++) {
+              const float2 y = lds[m], w = twd[t];
+              ax += y.x * w.x - y.y * w.y;
+              ay += y.x * w.y + y.y * w.x;
+              t += h;
+              if (t >= B) t -= B;
+            }
+            res[q] = make_float2(ax, ay);
+          }
+          __syncthreads();
+          q = 0;
+          for (int64_t h = threadIdx.x; h < B; h += blockDim.x, q++) lds[h] = res[q];
+          __syncthreads();
+        }
+        for (int64_t h = threadIdx.x; h < B; h += blockDim.x) {
+          const float2 v = make_float2(lds[h].x * inv, lds[h].y * inv);
+          const int64_t b = d.stageOff[j] + h;
+          Y0[b * D + dl] = v;
+          Yf[b * D + dl] = to_d(v);
+          psum += (double)v.x * v.x + (double)v.y * v.y;
+        }
+        __syncthreads();
+      }
+    }
+    const double sref2 = block_sum_d(psum, red) / (double)((int64_t)nb * D);
+    double nv = d.noise_var;
+    if (d.mode == SFFT_NOISY && !(nv > 0.0)) {
+      // stage sizes differ: select on B_j |Y|^2 needs the per-entry scale, so
+      // the select runs on a rescaled FP32 copy held in the FP64 state's tail
+      float2 *tmp = (float2 *)(vf + nb);
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        int j = 0;
+        while (j + 1 < S && d.stageOff[j + 1] <= b) j++;
+        const float sc = sqrtf((float)d.stageB[j]);
+        for (int dl = 0; dl < D; dl++) {
+          const float2 v = Y0[(int64_t)b * D + dl];
+          tmp[(int64_t)b * D + dl] = make_float2(v.x * sc, v.y * sc);
+        }
+      }
+      __syncthreads();
+      const float q = select_kth_power(tmp, (int64_t)nb * D, 1.0f, d.noise_at, hist, sel);
+      nv = (double)q / d.noise_p_den;
+    }
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      active[b] = 1;
+      cls[b] = kZero;
+    }
+    if (threadIdx.x == 0) flag_any = 1;
+    __syncthreads();
+    int nfound = 0, round = 0, partial = 0;
+    const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
+    for (;;) {
+      if (!flag_any) break;
+      if (round == d.max_peel_rounds) {
+        partial = 1;
+        break;
+      }
+      // 1. identify every active bucket on the state at the start of the round
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        det[b] = 0;
+        if (!active[b]) continue;
+        int j = 0;
+        while (j + 1 < S && d.stageOff[j + 1] <= b) j++;
+        const int64_t h = b - d.stageOff[j];
+        double2 Y[NMAX];
+#pragma unroll
+        for (int i = 0; i < NMAX; i++) Y[i] = i < D ? Yf[(int64_t)b * D + i] : make_double2(0.0, 0.0);
+        const Verdict v = classify<NMAX>(Y, d, D, 1, h, d.stageB[j], sref2, nv);
+        cls[b] = (uint8_t)v.cls;
+        if (v.cls == kSingle) {
+          det[b] = 1;
+          vf[b] = v.f;
+          va[b] = v.a;
+        }
+      }
+      __syncthreads();
+      // 2. a detection is new unless an earlier bucket (stage-major order) or a
+      //    previous round already found the same frequency
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        uint8_t nw = 0;
+        if (det[b]) {
+          nw = 1;
+          const int64_t f = vf[b];
+          for (int q = 0; q < b && nw; q++)
+            if (det[q] && vf[q] == f) nw = 0;
+          for (int q = 0; q < nfound && nw; q++)
+            if (c.A.found_f[d.found_off + q] == f) nw = 0;
+        }
+        isnew[b] = nw;
+      }
+      __syncthreads();
+      // 3. append the new frequencies in bucket order (segment scan)
+      int cntv = 0;
+      const int b0 = threadIdx.x * per;
+      for (int b = b0; b < b0 + per && b < nb; b++) cntv += isnew[b];
+      int total = 0;
+      int pos = block_scan_excl(cntv, ired, &total);
+      for (int b = b0; b < b0 + per && b < nb; b++) {
+        if (!isnew[b]) continue;
+        const int slot = nfound + pos++;
+        if (slot < d.found_cap) {
+          c.A.found_f[d.found_off + slot] = vf[b];
+          c.A.found_a[d.found_off + slot] = va[b];
+        }
+      }
+      __syncthreads();
+      round++;
+      if (total == 0) break;
+      int nnew = total;
+      if (nfound + nnew > d.found_cap) {
+        nnew = d.found_cap - nfound;
+        partial = 1;
+      }
+      // 4. subtract every new frequency from its bucket in every stage (Eq. 20)
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        int j = 0;
+        while (j + 1 < S && d.stageOff[j + 1] <= b) j++;
+        const int64_t Bj = d.stageB[j];
+        const int64_t h = b - d.stageOff[j];
+        uint8_t m = 0;
+        for (int q = 0; q < nnew; q++) {
+          const int64_t f = c.A.found_f[d.found_off + nfound + q];
+          if (f % Bj != h) continue;
+          const double2 a = c.A.found_a[d.found_off + nfound + q];
+          for (int dl = 0; dl < D; dl++) {
+            const double2 r = cmul(a, unit_d(((uint64_t)f * (uint64_t)dl) % (uint64_t)N, (uint64_t)N, +1));
+            Yf[(int64_t)b * D + dl].x -= r.x;
+            Yf[(int64_t)b * D + dl].y -= r.y;
+          }
+          m = 1;
+        }
+        modf[b] = m;
+      }
+      nfound += nnew;
+      __syncthreads();
+      if (threadIdx.x == 0) flag_any = 0;
+      __syncthreads();
+      // 5. next active set: changed buckets minus those that held a detection
+      for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        active[b] = modf[b] && !det[b];
+        if (active[b]) flag_any = 1;
+      }
+      __syncthreads();
+      if (partial) break;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) flag_any = 0;
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x)
+      if (cls[b] == kMulti) flag_any = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      c.st[s].found = nfound;
+      c.st[s].flags = (partial || flag_any) ? 1 : 0;
+      c.st[s].levels = round;
+      c.st[s].samples = (int64_t)nb * D;
+      c.st[s].sref2 = sref2;
+      c.st[s].noise_var = nv;
+    }
+    __syncthreads();
+  }
+}
+
+// Work of tree level `level` for every signal: prefix sums of FFT items,
+// direct partial-sum items and children; resets this level's multi-ton count.
+__global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
+  __shared__ int red[16];
+  const int par = (level - 1) & 1;
+  int carry_f = 0, carry_d = 0, carry_c = 0;
+  int32_t *pf = c.A.pre, *pd = c.A.pre + (c.nsig + 1), *pc = c.A.pre + 2 * (c.nsig + 1);
+  for (int base = 0; base < c.nsig; base += blockDim.x) {
+    const int s = base + threadIdx.x;
+    int nf = 0, nd = 0, nc = 0;
+    if (s < c.nsig) {
+      const SigDesc &d = c.desc[s];
+      if (d.kind == SFFT_KIND_TREE && level <= d.max_levels) {
+        int m = c.st[s].multi[par];
+        if (m > d.multi_cap) m = d.multi_cap;
+        const int64_t Bp = d.B0 << (level - 1);
+        if (m > 0) {
+          if (Bp <= kFftMax) nf = d.R;
+          else nd = d.R * (int)((Bp + kChunk - 1) / kChunk);
+          nc = 2 * m;
+          c.st[s].levels = level;
+          c.st[s].samples += (int64_t)d.n * Bp;
+          c.st[s].level_mask |= 1ull << level;
+        }
+      }
+      c.st[s].multi[level & 1] = 0;
+    }
+    int tf, td, tc;
+    const int ef = block_scan_excl(nf, red, &tf);
+    const int ed = block_scan_excl(nd, red, &td);
+    const int ec = block_scan_excl(nc, red, &tc);
+    if (s < c.nsig) {
+      pf[s] = carry_f + ef;
+      pd[s] = carry_d + ed;
+      pc[s] = carry_c + ec;
+    }
+    carry_f += tf;
+    carry_d += td;
+    carry_c += tc;
+  }
+  if (threadIdx.x == 0) {
+    pf[c.nsig] = carry_f;
+    pd[c.nsig] = carry_d;
+    pc[c.nsig] = carry_c;
+  }
+}
+
+// Odd-offset samples of level `level` (B' = B0 2^{level-1} per round and
+// delay, offset L'/2) by a B'-point LDS FFT; writes the bins of the parents.
+__global__ __launch_bounds__(kThreads) void k_expand_fft(LaunchCtx c, int level) {
+  extern __shared__ float2 lds[];
+  const int par = (level - 1) & 1;
+  const int32_t *pf = c.A.pre;
+  const int total = pf[c.nsig];
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_owner(pf, c.nsig, item);
+    const int r = item - pf[s];
+    const SigDesc &d = c.desc[s];
+    const float2 *__restrict__ x = io_of(c, s).x;
+    const int64_t N = d.N;
+    const int lb = d.log2B0 + level - 1;
+    const int64_t Bp = (int64_t)1 << lb;
+    const int64_t Lp = N >> lb;
+    int m_s = c.st[s].multi[par];
+    if (m_s > d.multi_cap) m_s = d.multi_cap;
+    const int n = d.n;
+    for (int dl = 0; dl < d.D; dl++) {
+      const uint64_t tau = (d.shift[r] + (uint64_t)dl + (uint64_t)(Lp >> 1)) & (uint64_t)(N - 1);
+      for (int64_t m = threadIdx.x; m < Bp; m += blockDim.x) {
+        const uint64_t pos = ((uint64_t)m * (uint64_t)Lp + tau) & (uint64_t)(N - 1);
+        lds[bitrev((uint32_t)m, lb)] = x[pos];
+      }
+      __syncthreads();
+      fft_lds(lds, lb, c.A.tw);
+      for (int j = threadIdx.x; j < m_s; j += blockDim.x) {
+        const int64_t slot = d.multi_off + j;
+        const int64_t cc = c.A.multi_c[par][slot];
+        c.A.multi_z[par][slot * c.nmax + r * d.D + dl] = to_d(lds[cc]);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Partial DFT sums of the odd-offset samples at the parents' bins only, for
+// B' > kFftMax: item = (signal, round, chunk of kChunk samples); FP64 atomics
+// combine the chunks.
+__global__ __launch_bounds__(kThreads) void k_expand_direct(LaunchCtx c, int level) {
+  __shared__ float red[4][2 * kMaxD];
+  const int par = (level - 1) & 1;
+  const int32_t *pd = c.A.pre + (c.nsig + 1);
+  const int total = pd[c.nsig];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_owner(pd, c.nsig, item);
+    const int rem = item - pd[s];
+    const SigDesc &d = c.desc[s];
+    const float2 *__restrict__ x = io_of(c, s).x;
+    const int64_t N = d.N;
+    const int lb = d.log2B0 + level - 1;
+    const int64_t Bp = (int64_t)1 << lb;
+    const int64_t Lp = N >> lb;
+    const int nch = (int)((Bp + kChunk - 1) / kChunk);
+    const int r = rem / nch, ch = rem % nch;
+    const int64_t m0 = (int64_t)ch * kChunk;
+    int m_s = c.st[s].multi[par];
+    if (m_s > d.multi_cap) m_s = d.multi_cap;
+    const int n = d.n, D = d.D;
+    const uint64_t base_tau = (d.shift[r] + (uint64_t)(Lp >> 1)) & (uint64_t)(N - 1);
+    float2 z[kPerThread][kMaxD];
+#pragma unroll
+    for (int q = 0; q < kPerThread; q++) {
+      const int64_t m = m0 + threadIdx.x + (int64_t)q * kThreads;
+      const uint64_t p0 = (uint64_t)m * (uint64_t)Lp + base_tau;
+#pragma unroll
+      for (int dl = 0; dl < kMaxD; dl++) {
+        z[q][dl] = make_float2(0.f, 0.f);
+        if (dl < D && m < Bp) z[q][dl] = x[(p0 + (uint64_t)dl) & (uint64_t)(N - 1)];
+      }
+    }
+    for (int j = 0; j < m_s; j++) {
+      const int64_t slot = d.multi_off + j;
+      const uint64_t cb = (uint64_t)c.A.multi_c[par][slot];
+      const uint64_t msk = (uint64_t)Bp - 1;
+      const double2 w0 = unit_d((cb * (uint64_t)(m0 + threadIdx.x)) & msk, (uint64_t)Bp, -1);
+      const double2 ws = unit_d((cb * (uint64_t)kThreads) & msk, (uint64_t)Bp, -1);
+      float2 tw = make_float2((float)w0.x, (float)w0.y);
+      const float2 stp = make_float2((float)ws.x, (float)ws.y);
+      float acc[2 * kMaxD];
+#pragma unroll
+      for (int i = 0; i < 2 * kMaxD; i++) acc[i] = 0.f;
+#pragma unroll
+      for (int q = 0; q < kPerThread; q++) {
+#pragma unroll
+        for (int dl = 0; dl < kMaxD; dl++) {
+          const float2 t = cmulf(z[q][dl], tw);
+          acc[2 * dl] += t.x;
+          acc[2 * dl + 1] += t.y;
+        }
+        tw = cmulf(tw, stp);
+      }
+#pragma unroll
+      for (int i = 0; i < 2 * kMaxD; i++) {
+        float v = acc[i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        acc[i] = v;
+      }
+      if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < 2 * kMaxD; i++) red[w][i] = acc[i];
+      }
+      __syncthreads();
+      if (threadIdx.x < 2 * D) {
+        const int i = threadIdx.x;
+        const double v = (double)red[0][i] + (double)red[1][i] + (double)red[2][i] + (double)red[3][i];
+        double *zz = (double *)&c.A.multi_z[par][slot * c.nmax + r * D + (i >> 1)];
+        atomicAdd(zz + (i & 1), v);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Children of every multi-ton of level-1: Y_child = 1/2 (Y_parent +- w Z/B'),
+// w = e^{-pi i c / B'} (radix-2 split of the level's transform); classify.
+template <int NMAX>
+__global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
+  const int par = (level - 1) & 1, cur = level & 1;
+  const int32_t *pc = c.A.pre + 2 * (c.nsig + 1);
+  const int total = pc[c.nsig];
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+    const int s = find_owner(pc, c.nsig, g);
+    const int q = g - pc[s];
+    const int j = q >> 1, side = q & 1;
+    const SigDesc &d = c.desc[s];
+    const int n = d.n;
+    const int lb = d.log2B0 + level - 1;
+    const int64_t Bp = (int64_t)1 << lb;
+    const int64_t B = Bp << 1;
+    const int64_t L = d.N >> (lb + 1);
+    const int64_t slot = d.multi_off + j;
+    const int64_t cpar = c.A.multi_c[par][slot];
+    double sw, cw;
+    sincospi((double)cpar / (double)Bp, &sw, &cw);
+    const double wx = cw, wy = -sw;                 // e^{-pi i c / B'}
+    const double sg = side ? -0.5 : 0.5;
+    const double invB = 1.0 / (double)Bp;
+    double2 Y[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; i++) {
+      Y[i] = make_double2(0.0, 0.0);
+      if (i < n) {
+        const float2 p = c.A.multi_y[par][slot * c.nmax + i];
+        const double2 zz = c.A.multi_z[par][slot * c.nmax + i];
+        const double zx = zz.x * invB, zy = zz.y * invB;
+        const double tx = wx * zx - wy * zy, ty = wx * zy + wy * zx;
+        Y[i] = make_double2(0.5 * (double)p.x + sg * tx, 0.5 * (double)p.y + sg * ty);
+      }
+    }
+    const int64_t cc = cpar + (side ? Bp : 0);
+    const SigState &ss = c.st[s];
+    const Verdict v = classify<NMAX>(Y, d, n, d.R, cc, B, ss.sref2, ss.noise_var);
+    if (v.cls == kSingle) {
+      const int fs = atomicAdd(&c.st[s].found, 1);
+      push_found(c, s, d, fs, v.f, v.a);
+    } else if (v.cls == kMulti) {
+      if (L >= 2 && level + 1 <= d.max_levels) {
+        const int ms = atomicAdd(&c.st[s].multi[cur], 1);
+        if (ms < d.multi_cap) {
+          const int64_t sl = d.multi_off + ms;
+          c.A.multi_c[cur][sl] = cc;
+#pragma unroll
+          for (int i = 0; i < NMAX; i++)
+            if (i < n) {
+              c.A.multi_y[cur][sl * c.nmax + i] = make_float2((float)Y[i].x, (float)Y[i].y);
+              c.A.multi_z[cur][sl * c.nmax + i] = make_double2(0.0, 0.0);
+            }
+        } else {
+          atomicOr(&c.st[s].flags, 3);
+        }
+      } else {
+        atomicOr(&c.st[s].flags, 1);
+      }
+    }
+  }
+}
+
+// Top-K by magnitude (ties: lower index), then ascending index; padding.
+__global__ __launch_bounds__(kThreads) void k_finalize(LaunchCtx c) {
+  extern __shared__ uint64_t keys[];
+  int32_t *ix = (int32_t *)(keys + c.max_found_cap);
+  for (int s = blockIdx.x; s < c.nsig; s += gridDim.x) {
+    const SigDesc &d = c.desc[s];
+    const SigIO io = io_of(c, s);
+    int cnt = c.st[s].found;
+    if (cnt > d.found_cap) cnt = d.found_cap;
+    const int K = (int)d.K;
+    const int64_t *ff = c.A.found_f + d.found_off;
+    const double2 *fa = c.A.found_a + d.found_off;
+    int kept = cnt < K ? cnt : K;
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    if (cnt > K) {
+      // sort by (magnitude descending, index ascending)
+      for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        if (i < cnt) {
+          const double2 a = fa[i];
+          const double m2 = a.x * a.x + a.y * a.y;
+          keys[i] = ~(uint64_t)__double_as_longlong(m2);
+        } else {
+          keys[i] = ~0ull;
+        }
+        ix[i] = i;
+      }
+      __syncthreads();
+      for (int k = 2; k <= P; k <<= 1)
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+          for (int i = threadIdx.x; i < P; i += blockDim.x) {
+            const int o = i ^ jj;
+            if (o > i) {
+              const uint64_t ka = keys[i], kb = keys[o];
+              bool gt = ka > kb;
+              if (ka == kb && ix[i] < cnt && ix[o] < cnt) gt = ff[ix[i]] > ff[ix[o]];
+              if (gt == ((i & k) == 0)) {
+                keys[i] = kb;
+                keys[o] = ka;
+                const int t = ix[i];
+                ix[i] = ix[o];
+                ix[o] = t;
+              }
+            }
+          }
+          __syncthreads();
+        }
+    } else {
+      for (int i = threadIdx.x; i < P; i += blockDim.x) ix[i] = i;
+      __syncthreads();
+    }
+    // sort the kept entries by index
+    int P2 = 1;
+    while (P2 < kept) P2 <<= 1;
+    for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+      keys[i] = i < kept ? (uint64_t)ff[ix[i]] : ~0ull;
+      if (i >= kept) ix[i] = -1;
+    }
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1)
+      for (int jj = k >> 1; jj > 0; jj >>= 1) {
+        for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+          const int o = i ^ jj;
+          if (o > i) {
+            const uint64_t ka = keys[i], kb = keys[o];
+            if ((ka > kb) == ((i & k) == 0)) {
+              keys[i] = kb;
+              keys[o] = ka;
+              const int t = ix[i];
+              ix[i] = ix[o];
+              ix[o] = t;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (int i = threadIdx.x; i < K; i += blockDim.x) {
+      if (i < kept) {
+        io.idx[i] = ff[ix[i]];
+        const double2 a = fa[ix[i]];
+        io.val[i] = make_float2((float)a.x, (float)a.y);
+      } else {
+        io.idx[i] = -1;
+        io.val[i] = make_float2(0.f, 0.f);
+      }
+    }
+    if (threadIdx.x == 0) {
+      *io.count = kept;
+      *io.status = c.st[s].flags ? SFFT_STATUS_PARTIAL : SFFT_STATUS_OK;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_export_level0(LaunchCtx c, float2 *out) {
+  const SigDesc &d = c.desc[0];
+  if (d.kind == SFFT_KIND_FFAST) {
+    const int64_t tot = d.stageOff[d.nstages] * d.D;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x)
+      out[i] = c.A.y0[d.y0_off + i];
+  } else {
+    const int64_t tot = (int64_t)d.n * d.B0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t cc = i / d.n, k = i % d.n;
+      out[i] = c.A.y0[d.y0_off + k * d.B0 + cc];
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_export_level0(const LaunchCtx &c, void *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_export_level0, dim3(256), dim3(256), 0, s, c, (float2 *)out);
+  return hipGetLastError();
+}
+
+static int nmax_bucket(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : 64); }
+
+// kernels whose dynamic LDS can exceed 64 KiB declare the gfx950 maximum once
+static void configure_lds() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  const int big = 160 * 1024;
+  (void)hipFuncSetAttribute((const void *)k_ffast<8>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void *)k_ffast<16>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void *)k_ffast<64>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipFuncSetAttribute((const void *)k_finalize, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  (void)hipGetLastError();
+}
+
+hipError_t launch_reset(const LaunchCtx &c, hipStream_t s) {
+  configure_lds();
+  hipLaunchKernelGGL(k_reset, dim3((c.nsig + 255) / 256), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
+  const int nm = nmax_bucket(c.nmax);
+  if (c.ntree > 0) {
+    const int grid = c.ntree < 4096 ? c.ntree : 4096;
+    const size_t lds = sizeof(float2) * (size_t)c.max_B0;
+    if (nm == 8) hipLaunchKernelGGL(k_level0_tree<8>, dim3(grid), dim3(kThreads), lds, s, c);
+    else if (nm == 16) hipLaunchKernelGGL(k_level0_tree<16>, dim3(grid), dim3(kThreads), lds, s, c);
+    else hipLaunchKernelGGL(k_level0_tree<64>, dim3(grid), dim3(kThreads), lds, s, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (c.nffast > 0) {
+    const int grid = c.nffast < 4096 ? c.nffast : 4096;
+    const size_t lds = sizeof(float2) * (kFftMax + kDirectMax) + 5 * kMaxFfastBuckets;
+    if (nm == 8) hipLaunchKernelGGL(k_ffast<8>, dim3(grid), dim3(kThreads), lds, s, c);
+    else if (nm == 16) hipLaunchKernelGGL(k_ffast<16>, dim3(grid), dim3(kThreads), lds, s, c);
+    else hipLaunchKernelGGL(k_ffast<64>, dim3(grid), dim3(kThreads), lds, s, c);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_sched(const LaunchCtx &c, int level, hipStream_t s) {
+  hipLaunchKernelGGL(k_sched, dim3(1), dim3(1024), 0, s, c, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_fft(const LaunchCtx &c, int level, int grid, hipStream_t s) {
+  const size_t lds = sizeof(float2) * (size_t)kFftMax;
+  hipLaunchKernelGGL(k_expand_fft, dim3(grid), dim3(kThreads), lds, s, c, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_expand_direct, dim3(grid), dim3(kThreads), 0, s, c, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_children(const LaunchCtx &c, int level, int grid, hipStream_t s) {
+  const int nm = nmax_bucket(c.nmax);
+  if (nm == 8) hipLaunchKernelGGL(k_children<8>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  else if (nm == 16) hipLaunchKernelGGL(k_children<16>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  else hipLaunchKernelGGL(k_children<64>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const LaunchCtx &c, hipStream_t s) {
+  const int grid = c.nsig < 4096 ? c.nsig : 4096;
+  const size_t lds = (sizeof(uint64_t) + sizeof(int32_t)) * (size_t)c.max_found_cap;
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kThreads), lds, s, c);
+  return hipGetLastError();
+}
+
+}  // namespace sfft

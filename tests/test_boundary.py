@@ -1,0 +1,102 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every symbol include/sfft.h declares, its structs match the binding, and its
+plan logic (factoring, SplitMix64 draws, validation) agrees with the
+oracle's independent implementation."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import oracle
+import paper_2011_05749_amd as sfft
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "sfft.h")
+
+
+def header_functions():
+    txt = open(HDR).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(sfft_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = header_functions()
+    assert len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", sfft.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(l.split()[-1] for l in out.splitlines() if l.strip())
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    lib = ctypes.CDLL(sfft.LIB_PATH)
+    for n in names:
+        getattr(lib, n)
+    assert sorted(sfft.EXPORTS) == names
+
+
+def test_struct_layouts_match_binding(tmp_path):
+    prog = tmp_path / "layout.c"
+    fields = {
+        "sfft_params_t": sfft.Params, "sfft_plan_info_t": sfft.PlanInfo, "sfft_stats_t": sfft.Stats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', "int main(void){"]
+    for cname, py in fields.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    prog.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-o", str(exe), str(prog)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    for line in out.splitlines():
+        cname, f, v = line.split()
+        py = fields[cname]
+        if f == "size":
+            assert ctypes.sizeof(py) == int(v), cname
+        else:
+            assert getattr(py, f).offset == int(v), (cname, f)
+
+
+def test_plan_factoring_matches_oracle():
+    p = sfft.Plan(10800, 10, 3, 2)
+    c = oracle.config(10800, 10, 3, 2)
+    assert p.info.kind == sfft.KIND_FFAST
+    assert [p.info.stage_B[j] for j in range(3)] == [c.stageB[j] for j in range(3)] == [16, 27, 25]
+    p = sfft.Plan(20, 5, 2, 3, stage_B=[4, 5])
+    assert [p.info.stage_B[j] for j in range(2)] == [4, 5]
+
+
+@pytest.mark.parametrize("N,K,R,seed,B0,ident", [
+    (2 ** 22, 1024, 4, 9000, 2048, 0), (2 ** 20, 256, 4, 1000, 0, 0), (2 ** 14, 8, 1, 7, 0, 1),
+    (2 ** 24, 4096, 4, 5000, 8192, 0), (2 ** 16, 100, 16, 3, 256, 1)])
+def test_plan_draws_match_oracle(N, K, R, seed, B0, ident):
+    p = sfft.Plan(N, K, R, 2, seed=seed, B0=B0, identity_round0=ident)
+    c = oracle.config(N, K, R, 2, seed=seed, B0=B0, identity_round0=bool(ident))
+    assert p.info.B0 == c.B0 and p.info.max_levels == c.max_levels
+    for r in range(R):
+        assert p.info.sigma[r] == c.sigma[r] and p.info.shift[r] == c.shift[r]
+
+
+@pytest.mark.parametrize("args,kw,code", [
+    ((10800, 10, 2, 2), {}, -2),           # three prime powers, two stages
+    ((1024, 10, 2, 1), {}, -1),            # exact mode needs >= 2 delays
+    ((1024, 0, 2, 2), {}, -1),             # K < 1
+    ((1024, 2000, 2, 2), {}, -1),          # K > N
+    ((1024, 10, 2, 2), {"B0": 24}, -1),    # B0 not a power of two
+    ((1024, 10, 2, 2), {"B0": 2048}, -1),  # B0 > N
+    ((2 ** 20, 10, 2, 2), {"B0": 16384}, -2),  # beyond the LDS FFT
+    ((60, 4, 2, 2), {"stage_B": [4, 6]}, -1),  # stages not co-prime
+    ((60, 4, 2, 2), {"stage_B": [7, 5]}, -1),  # stage does not divide N
+    ((1024, 10, 17, 2), {}, -1),           # too many rounds
+])
+def test_plan_validation(args, kw, code):
+    with pytest.raises(sfft.SfftError) as e:
+        sfft.Plan(*args, **kw)
+    assert e.value.code == code
+
+
+def test_noisy_plan_allows_one_delay_and_window():
+    p = sfft.Plan(2 ** 16, 32, 4, 1, seed=1, mode="noisy", window=16)
+    assert p.info.mode == sfft.NOISY and p.info.D == 1 and p.info.window == 16

@@ -1,0 +1,255 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Bar: recovered indices bit-exact (padding included), counts and status equal,
+values within relative L2 <= 1e-5 (FP32 bucketization, FP64 locate/value),
+level-0 bucket values within relative L2 <= 1e-5 of the oracle's.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import siggen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+VAL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def sfft():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    import paper_2011_05749_amd as m
+    return m
+
+
+def to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def oracle_cfg(N, K, stages, delays, seed=0, mode=0, B0=0, identity_round0=False,
+               stage_B=None, **ov):
+    return oracle.config(N, K, stages, delays, seed=seed, mode=mode, B0=B0,
+                         identity_round0=identity_round0, stageB=stage_B, **ov)
+
+
+def solve_both(sfft, x, N, K, stages, delays, seed=0, **kw):
+    ok = {k: v for k, v in kw.items() if k not in ("stage_B",)}
+    mode = kw.get("mode", 0)
+    plan = sfft.Plan(N, K, stages, delays, seed=seed, **kw)
+    ocfg_kw = {}
+    for k in ("window", "noise_var", "max_levels", "eps0", "eps1", "zero_k", "single_k"):
+        if k in ok:
+            ocfg_kw[k] = ok[k]
+    cfg = oracle_cfg(N, K, stages, delays, seed=seed, mode=mode, B0=kw.get("B0", 0),
+                     identity_round0=bool(kw.get("identity_round0", 0)),
+                     stage_B=kw.get("stage_B"), **ocfg_kw)
+    xd = to_dev(x)
+    gi, gv, gc = plan.exec(xd)
+    st = plan.stats()
+    gi, gv = gi.cpu().numpy(), gv.cpu().numpy()
+    oi, ov, oc, tr = oracle.solve(cfg, x)
+    return (gi, gv, gc, st), (oi, ov, oc, tr)
+
+
+def assert_parity(g, o, tol=VAL_TOL):
+    gi, gv, gc, st = g
+    oi, ov, oc, tr = o
+    assert gc == oc, (gc, oc)
+    np.testing.assert_array_equal(gi, oi)
+    assert st["status"] == tr.status
+    m = oi >= 0
+    if m.any():
+        assert rel_l2(gv[m].astype(np.complex128), ov[m]) <= tol
+
+
+# ------------------------------------------------------- bucketization (a2, a3)
+@pytest.mark.parametrize("N,K,R,D,B0,seed", [
+    (2 ** 14, 40, 4, 2, 128, 1), (2 ** 12, 8, 1, 2, 8, 2), (2 ** 16, 300, 3, 3, 1024, 3),
+    (2 ** 13, 5, 2, 2, 8192, 4), (2 ** 10, 3, 1, 2, 1, 5)])
+def test_bucketize_tree(sfft, N, K, R, D, B0, seed):
+    sp = siggen.make_spec(N, K, seed)
+    x = siggen.synth(sp)
+    plan = sfft.Plan(N, K, R, D, seed=seed, B0=B0)
+    Yg = plan.bucketize(to_dev(x)).cpu().numpy().astype(np.complex128)
+    Yo = oracle.level0(oracle_cfg(N, K, R, D, seed=seed, B0=B0), x)
+    assert Yg.shape == Yo.shape
+    assert rel_l2(Yg, Yo) <= VAL_TOL
+
+
+def test_bucketize_ffast(sfft):
+    sp = siggen.make_spec(10800, 10, 0)
+    x = siggen.synth(sp)
+    plan = sfft.Plan(10800, 10, 3, 2)
+    Yg = plan.bucketize(to_dev(x)).cpu().numpy().astype(np.complex128)
+    Yo = oracle.level0(oracle_cfg(10800, 10, 3, 2), x)
+    assert rel_l2(Yg, Yo) <= VAL_TOL
+
+
+# ----------------------------------------------------------- FFAST peeling (a6)
+@pytest.mark.parametrize("seed", range(40))
+def test_ffast_config1(sfft, seed):
+    sp = siggen.make_spec(10800, 10, seed)
+    x = siggen.synth(sp)
+    g, o = solve_both(sfft, x, 10800, 10, 3, 2)
+    assert_parity(g, o)
+    assert g[3]["levels"] == o[3].levels   # identification rounds
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_ffast_n20_example(sfft, D):
+    sup = [1, 3, 5, 10, 13]
+    x = siggen.synth(siggen.make_spec(20, 5, 1, support=sup))
+    g, o = solve_both(sfft, x, 20, 5, 2, D, stage_B=[4, 5])
+    assert_parity(g, o)
+    assert g[3]["levels"] == 3
+
+
+# ------------------------------------------------------------ tree search (a7)
+@pytest.mark.parametrize("N,K,R,B0,seed,ident", [
+    (2 ** 12, 8, 1, 8, 1, 1), (2 ** 14, 64, 2, 128, 2, 0), (2 ** 16, 300, 4, 512, 4, 0),
+    (2 ** 16, 100, 4, 256, 3, 0), (2 ** 10, 1, 1, 1, 5, 1), (2 ** 13, 7, 3, 16, 6, 0),
+    (2 ** 18, 200, 1, 256, 7, 1), (2 ** 20, 256, 4, 512, 8, 0), (2 ** 17, 37, 2, 64, 9, 0)])
+def test_tree_exact(sfft, N, K, R, B0, seed, ident):
+    sp = siggen.make_spec(N, K, seed)
+    x = siggen.synth(sp)
+    g, o = solve_both(sfft, x, N, K, R, 2, seed=seed, B0=B0, identity_round0=ident)
+    assert_parity(g, o)
+    assert g[3]["levels"] == o[3].levels
+    assert g[3]["samples"] == o[3].samples
+    np.testing.assert_array_equal(g[0], siggen.truth(sp)[0])
+
+
+def test_tree_worst_pair_full_depth(sfft):
+    N = 2 ** 12
+    x = siggen.synth(siggen.make_spec(N, 2, 4, support=[0, N // 2]))
+    g, o = solve_both(sfft, x, N, 2, 1, 2, B0=1, identity_round0=1)
+    assert_parity(g, o)
+    g, o = solve_both(sfft, x, N, 2, 1, 2, B0=1, identity_round0=1, max_levels=5)
+    assert_parity(g, o)
+    assert g[3]["status"] == 1 and g[2] == 0
+
+
+def test_tree_n64_example(sfft):
+    sup = [1, 6, 13, 20, 59]
+    x = siggen.synth(siggen.make_spec(64, 5, 2, support=sup))
+    g, o = solve_both(sfft, x, 64, 5, 1, 2, B0=1, identity_round0=1)
+    assert_parity(g, o)
+
+
+def test_edge_zero_signal_and_padding(sfft):
+    N = 2 ** 12
+    x = np.zeros(N, np.complex64)
+    g, o = solve_both(sfft, x, N, 5, 2, 2, B0=16)
+    assert_parity(g, o)
+    assert g[2] == 0 and np.all(g[0] == -1)
+    # fewer tones than K: padding after the found ones
+    x = siggen.synth(siggen.make_spec(N, 3, 9))
+    g, o = solve_both(sfft, x, N, 8, 2, 2, B0=16)
+    assert_parity(g, o)
+    assert g[2] == 3
+
+
+def test_edge_B0_equals_N(sfft):
+    N = 1024
+    x = siggen.synth(siggen.make_spec(N, 10, 11))
+    g, o = solve_both(sfft, x, N, 10, 2, 2, B0=N)
+    assert_parity(g, o)
+
+
+def test_more_than_K_topk(sfft):
+    N = 1024
+    sup = np.array([3, 100, 200, 900])
+    vals = np.array([1.0, 3.0, 2.0, 0.5]) * np.exp(1j * np.array([0.1, 0.2, 0.3, 0.4]))
+    x = siggen.synth(siggen.make_spec(N, 4, 0, support=sup, values=vals))
+    g, o = solve_both(sfft, x, N, 2, 1, 2, B0=64)
+    assert_parity(g, o)
+    np.testing.assert_array_equal(g[0], [100, 200])
+
+
+def test_determinism(sfft):
+    N, K = 2 ** 16, 300
+    x = siggen.synth(siggen.make_spec(N, K, 12))
+    plan = sfft.Plan(N, K, 4, 2, seed=12, B0=512)
+    xd = to_dev(x)
+    ref = None
+    for _ in range(5):
+        i, v, c = plan.exec(xd)
+        cur = (i.cpu().numpy().copy(), v.cpu().numpy().copy(), c)
+        if ref is None:
+            ref = cur
+        else:
+            np.testing.assert_array_equal(cur[0], ref[0])
+            assert cur[2] == ref[2]
+            assert rel_l2(cur[1], ref[1]) <= 1e-6
+
+
+# ------------------------------------------------------------------ noisy mode
+@pytest.mark.parametrize("window,seed", [(0, 31), (64, 32)])
+def test_noisy_tree(sfft, window, seed):
+    N, K = 2 ** 16, 32
+    sp = siggen.make_spec(N, K, seed, snr_db=20.0)
+    x = siggen.synth(sp)
+    g, o = solve_both(sfft, x, N, K, 4, 2, seed=8, mode=1, window=window)
+    assert_parity(g, o, tol=1e-4)
+    assert abs(g[3]["noise_var"] / o[3].noise_var - 1) < 1e-4
+
+
+# ------------------------------------------------------------- batched form (a9)
+def test_batch_uneven_matches_single_and_oracle(sfft):
+    rng = np.random.default_rng(2000)
+    plans, xs, specs, cfgs = [], [], [], []
+    for i in range(24):
+        e = int(rng.integers(10, 17))
+        K = int(round(np.exp(rng.uniform(np.log(4), np.log(64)))))
+        N = 2 ** e
+        B0 = 1
+        while B0 < K:
+            B0 *= 2
+        sp = siggen.make_spec(N, K, 2000 + i)
+        plans.append(sfft.Plan(N, K, 1, 2, seed=2000 + i, B0=B0, identity_round0=1))
+        cfgs.append(oracle_cfg(N, K, 1, 2, seed=2000 + i, B0=B0, identity_round0=True))
+        x = siggen.synth(sp)
+        specs.append(x)
+        xs.append(to_dev(x))
+    # add one FFAST signal to the mix
+    xf = siggen.synth(siggen.make_spec(10800, 10, 5))
+    plans.append(sfft.Plan(10800, 10, 3, 2))
+    cfgs.append(oracle_cfg(10800, 10, 3, 2))
+    specs.append(xf)
+    xs.append(to_dev(xf))
+    for graph in (False, True, True):
+        b = sfft.Batch(plans, xs)
+        b.run(graph=graph)
+        torch.cuda.synchronize()
+        counts = b.counts.cpu().numpy()
+        status = b.status.cpu().numpy()
+        for i, (p, x, cfg) in enumerate(zip(plans, specs, cfgs)):
+            oi, ov, oc, tr = oracle.solve(cfg, x)
+            gi = b.idxs[i].cpu().numpy()
+            gv = b.vals[i].cpu().numpy()
+            assert counts[i] == oc and status[i] == tr.status
+            np.testing.assert_array_equal(gi, oi)
+            m = oi >= 0
+            if m.any():
+                assert rel_l2(gv[m].astype(np.complex128), ov[m]) <= VAL_TOL
+        # eager work between replays
+        torch.cuda.synchronize()
+        _ = (xs[0].abs() * 2).sum().item()
+
+
+def test_headline_shape_sampled(sfft):
+    """Full size N = 2^22, K = 1024, B0 = 2048, 4 rounds x 2 delays, two signals."""
+    N, K = 2 ** 22, 1024
+    for seed in (9000, 9001):
+        sp = siggen.make_spec(N, K, seed)
+        x = siggen.synth(sp)
+        g, o = solve_both(sfft, x, N, K, 4, 2, seed=seed, B0=2048)
+        assert_parity(g, o)
+        np.testing.assert_array_equal(g[0], siggen.truth(sp)[0])

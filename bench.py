@@ -37,6 +37,10 @@ def pct(v, q):
     return v[f] + (v[c] - v[f]) * (k - f)
 
 
+def ilog2(v):
+    return int(v).bit_length() - 1
+
+
 def kernel_bytes(name, level, plans, stats):
     """Algorithmic bytes of one launch: signal samples it must read x 8 B."""
     tot = 0
@@ -49,10 +53,15 @@ def kernel_bytes(name, level, plans, stats):
         n = inf.R * inf.D
         if name == "k_level0":
             tot += n * inf.B0 * 8
+        elif name == "k_jump_pass" and level >= 1:
+            if (st["level_mask"] >> level) & 1 and (inf.N >> (ilog2(inf.B0) + level - 1)) <= inf.jump_L:
+                tot += inf.N * 8
         elif name in ("k_expand_fft", "k_expand_direct") and level >= 1:
             if not (st["level_mask"] >> level) & 1:
                 continue
             bp = inf.B0 << (level - 1)
+            if inf.jump_L > 0 and (inf.N // bp) <= inf.jump_L:
+                continue
             if (bp <= 8192) == (name == "k_expand_fft"):
                 tot += n * bp * 8
     return tot

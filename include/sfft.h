@@ -92,6 +92,12 @@ typedef struct {
                               number of explicit co-prime stage sizes below */
   int64_t stage_B[SFFT_MAX_STAGES];
   int32_t max_peel_rounds; /* FFAST: cap on peeling rounds (default 64) */
+  int32_t jump_L;          /* tree: once a level's stride L' <= jump_L (a power of two
+                              <= 64), resolve each open class's whole subtree from
+                              its L' coefficients, measured by one dense pass over x;
+                              every later level's class vectors are the same linear
+                              functionals of x as the level-by-level gathers.
+                              0 = level by level to the end (default 64) */
   double eps0;             /* exact: zero-ton if |Y|^2 <= eps0^2 sref^2 n (1e-4) */
   double eps1;             /* exact: single-ton if residual^2 <= eps1^2 |Y|^2 (1e-4) */
   double zero_k;           /* noisy: T0^2 = s_b^2 (n + zero_k sqrt(n))        (4) */
@@ -114,6 +120,7 @@ typedef struct {
   uint64_t shift[SFFT_MAX_ROUNDS];    /* shift per round */
   double eps0, eps1, zero_k, single_k, noise_var;
   int32_t max_peel_rounds;
+  int32_t jump_L;
   int32_t found_cap;       /* device list capacities per signal */
   int32_t multi_cap;
 } sfft_plan_info_t;
@@ -177,6 +184,8 @@ int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs,
 #define SFFT_KERNEL_EXPAND_DIRECT 4 /* odd-offset gather + per-bin partial sums */
 #define SFFT_KERNEL_CHILDREN 5
 #define SFFT_KERNEL_FINALIZE 6
+#define SFFT_KERNEL_JUMP_PASS 7     /* dense pass: L' coefficients of each open class */
+#define SFFT_KERNEL_JUMP_RESOLVE 8  /* subtree classification from the coefficients */
 int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
                                 int64_t *const *idx, void *const *vals, int64_t *d_counts,
                                 int32_t *d_status, int32_t n, float *ms, int32_t *kernel,

@@ -42,7 +42,7 @@ class Params(ctypes.Structure):
         ("max_levels", ctypes.c_int32), ("window", ctypes.c_int32),
         ("identity_round0", ctypes.c_int32), ("nstage_B", ctypes.c_int32),
         ("stage_B", ctypes.c_int64 * MAX_STAGES),
-        ("max_peel_rounds", ctypes.c_int32),
+        ("max_peel_rounds", ctypes.c_int32), ("jump_L", ctypes.c_int32),
         ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
@@ -62,7 +62,7 @@ class PlanInfo(ctypes.Structure):
         ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
-        ("max_peel_rounds", ctypes.c_int32),
+        ("max_peel_rounds", ctypes.c_int32), ("jump_L", ctypes.c_int32),
         ("found_cap", ctypes.c_int32), ("multi_cap", ctypes.c_int32),
     ]
 
@@ -77,7 +77,8 @@ class Stats(ctypes.Structure):
 
 
 KERNEL_NAMES = {0: "k_reset", 1: "k_level0", 2: "k_sched", 3: "k_expand_fft",
-                4: "k_expand_direct", 5: "k_children", 6: "k_finalize"}
+                4: "k_expand_direct", 5: "k_children", 6: "k_finalize", 7: "k_jump_pass",
+                8: "k_jump_resolve"}
 
 _vp = ctypes.c_void_p
 _lib.sfft_params_init.argtypes = [ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int64,
@@ -160,7 +161,7 @@ def _dev_ptr(t, dtype_name, n=None, what="tensor"):
 class Plan:
     """An sfft plan (immutable).  Keyword parameters map onto sfft_params_t:
     mode ('exact'|'noisy' or 0|1), B0, max_levels, window, identity_round0,
-    stage_B (explicit co-prime FFAST stages), max_peel_rounds, eps0, eps1,
+    stage_B (explicit co-prime FFAST stages), max_peel_rounds, jump_L, eps0, eps1,
     zero_k, single_k, noise_var."""
 
     def __init__(self, N: int, K: int, stages: int, delays: int, seed: int = 0, **kw):

@@ -117,16 +117,25 @@ hipError_t device_twiddles(int dev, const float2 **out) {
 }
 
 struct LevelLaunch {
-  bool fft, direct;
-  int grid_fft, grid_direct, grid_children;
+  bool fft, direct, children, jump;
+  int grid_fft, grid_direct, grid_children, grid_jump, grid_resolve;
 };
+
+// first tree level whose parents' stride N / (B0 2^{l-1}) is <= jump_L, or a
+// level beyond max_levels when the subtree resolution is off
+int jump_level(const SigDesc &d) {
+  if (d.jump_L <= 0) return d.max_levels + 1;
+  for (int l = 1; l <= d.max_levels; l++)
+    if ((d.N >> (d.log2B0 + l - 1)) <= d.jump_L) return l;
+  return d.max_levels + 1;
+}
 
 struct BatchCtx {
   int device = -1;
   std::vector<const sfft_plan_s *> plans;
   int nsig = 0;
   std::vector<SigDesc> desc;
-  DevBuf b_desc, b_io, b_st, b_lists, b_y0, b_fst, b_ff, b_fa, b_mc, b_my, b_mz, b_pre, b_out;
+  DevBuf b_desc, b_io, b_st, b_lists, b_y0, b_fst, b_ff, b_fa, b_mc, b_my, b_mz, b_pre, b_out, b_jacc;
   LaunchCtx lc{};
   std::vector<LevelLaunch> levels;
   std::vector<SigIO> io_last;
@@ -173,6 +182,7 @@ struct BatchCtx {
       d.max_peel_rounds = in.max_peel_rounds;
       d.found_cap = in.found_cap;
       d.multi_cap = in.multi_cap;
+      d.jump_L = in.kind == SFFT_KIND_TREE ? in.jump_L : 0;
       for (int j = 0; j < SFFT_MAX_STAGES; j++) d.stageB[j] = in.stage_B[j];
       for (int j = 0; j <= SFFT_MAX_STAGES; j++) d.stageOff[j] = p->stage_off[j];
       for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.shift[r] = in.shift[r];
@@ -206,6 +216,9 @@ struct BatchCtx {
       desc[s] = d;
     }
     mz = mc * (int64_t)nmax;  // multi-ton vectors use the batch-wide stride nmax
+    bool any_jump = false;
+    for (int s = 0; s < nsig; s++)
+      if (desc[s].kind == SFFT_KIND_TREE && jump_level(desc[s]) <= desc[s].max_levels) any_jump = true;
     // longest solves first (LPT order) for the persistent level-0 launches
     std::stable_sort(tree.begin(), tree.end(), [](auto &a, auto &b) { return a.first > b.first; });
     std::stable_sort(ffast.begin(), ffast.end(), [](auto &a, auto &b) { return a.first > b.first; });
@@ -219,7 +232,8 @@ struct BatchCtx {
         !ck(b_y0.alloc(sizeof(float2) * (size_t)y0)) || !ck(b_fst.alloc(sizeof(double2) * (size_t)fst)) ||
         !ck(b_ff.alloc(sizeof(int64_t) * (size_t)fc)) || !ck(b_fa.alloc(sizeof(double2) * (size_t)fc)) ||
         !ck(b_mc.alloc(2 * sizeof(int64_t) * (size_t)mc)) || !ck(b_my.alloc(2 * sizeof(float2) * (size_t)mz)) ||
-        !ck(b_mz.alloc(2 * sizeof(double2) * (size_t)mz)) || !ck(b_pre.alloc(3 * sizeof(int32_t) * (ns + 1))) ||
+        !ck(b_mz.alloc(2 * sizeof(double2) * (size_t)mz)) || !ck(b_pre.alloc(5 * sizeof(int32_t) * (ns + 1))) ||
+        !ck(b_jacc.alloc(sizeof(double2) * (size_t)(any_jump ? mc * kJumpMax : 1))) ||
         !ck(b_out.alloc((sizeof(int64_t) + sizeof(int32_t)) * 2)))
       return SFFT_ENOMEM;
     if (hipMemcpy(b_desc.p, desc.data(), sizeof(SigDesc) * ns, hipMemcpyHostToDevice) != hipSuccess ||
@@ -242,6 +256,7 @@ struct BatchCtx {
     c.A.multi_z[0] = (double2 *)b_mz.p;
     c.A.multi_z[1] = (double2 *)b_mz.p + mz;
     c.A.pre = (int32_t *)b_pre.p;
+    c.A.jacc = (double2 *)b_jacc.p;
     c.A.tw = tw;
     c.tree_list = (const int32_t *)b_lists.p;
     c.ffast_list = (const int32_t *)b_lists.p + tree.size();
@@ -252,14 +267,28 @@ struct BatchCtx {
     c.max_B0 = maxB0;
     c.max_stage_B = maxStage;
     c.max_found_cap = (int)npow2(maxFcap);
-    // static launch shape of every tree level
+    // static launch shape of every tree level: a signal gathers level by level
+    // before its jump level, runs the dense pass and the subtree resolution at
+    // it, and has no work after it
     levels.clear();
-    for (int l = 1; l <= maxLevels; l++) {
+    int last = 0;
+    for (int s = 0; s < nsig; s++)
+      if (desc[s].kind == SFFT_KIND_TREE)
+        last = std::max(last, std::min(desc[s].max_levels, jump_level(desc[s])));
+    (void)maxLevels;
+    for (int l = 1; l <= last; l++) {
       LevelLaunch L{};
-      int64_t nf = 0, nd = 0, nch = 0;
+      int64_t nf = 0, nd = 0, nch = 0, nj = 0, nr = 0;
       for (int s = 0; s < nsig; s++) {
         const SigDesc &d = desc[s];
         if (d.kind != SFFT_KIND_TREE || l > d.max_levels) continue;
+        const int jl = jump_level(d);
+        if (l > jl) continue;
+        if (l == jl) {
+          nj += (d.N + kJumpChunk - 1) / kJumpChunk;
+          nr += d.multi_cap;
+          continue;
+        }
         const int64_t Bp = d.B0 << (l - 1);
         if (Bp <= kFftMax) nf += d.R;
         else nd += (int64_t)d.R * ((Bp + kChunk - 1) / kChunk);
@@ -267,9 +296,13 @@ struct BatchCtx {
       }
       L.fft = nf > 0;
       L.direct = nd > 0;
+      L.children = nch > 0;
+      L.jump = nj > 0;
       L.grid_fft = (int)std::min<int64_t>(std::max<int64_t>(nf, 1), 4096);
       L.grid_direct = (int)std::min<int64_t>(std::max<int64_t>(nd, 1), 8192);
       L.grid_children = (int)std::min<int64_t>(std::max<int64_t>((nch + kThreads - 1) / kThreads, 1), 2048);
+      L.grid_jump = (int)std::min<int64_t>(std::max<int64_t>(nj, 1), 8192);
+      L.grid_resolve = (int)std::min<int64_t>(std::max<int64_t>(nr, 1), 4096);
       levels.push_back(L);
     }
     io_last.assign(ns, SigIO{});
@@ -306,8 +339,13 @@ struct BatchCtx {
       if (L.direct && ((e = launch_expand_direct(c, l, L.grid_direct, s)) != hipSuccess ||
                        (e = mark(SFFT_KERNEL_EXPAND_DIRECT | (l << 8))) != hipSuccess))
         return e;
-      if ((e = launch_children(c, l, L.grid_children, s)) != hipSuccess ||
-          (e = mark(SFFT_KERNEL_CHILDREN | (l << 8))) != hipSuccess)
+      if (L.children && ((e = launch_children(c, l, L.grid_children, s)) != hipSuccess ||
+                         (e = mark(SFFT_KERNEL_CHILDREN | (l << 8))) != hipSuccess))
+        return e;
+      if (L.jump && ((e = launch_jump_pass(c, l, L.grid_jump, s)) != hipSuccess ||
+                     (e = mark(SFFT_KERNEL_JUMP_PASS | (l << 8))) != hipSuccess ||
+                     (e = launch_jump_resolve(c, l, L.grid_resolve, s)) != hipSuccess ||
+                     (e = mark(SFFT_KERNEL_JUMP_RESOLVE | (l << 8))) != hipSuccess))
         return e;
     }
     if ((e = launch_finalize(c, s)) != hipSuccess) return e;
@@ -357,6 +395,8 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
   in.single_k = p.single_k;
   in.noise_var = p.noise_var;
   in.max_peel_rounds = p.max_peel_rounds > 0 ? p.max_peel_rounds : 64;
+  if (p.jump_L < 0 || p.jump_L > kJumpMax || (p.jump_L > 0 && !pow2(p.jump_L))) return SFFT_EINVAL;
+  in.jump_L = p.jump_L;
   in.found_cap = (int32_t)std::max<int64_t>(64, npow2(2 * p.K));
   in.multi_cap = (int32_t)std::max<int64_t>(64, p.K);
   memset(pl->stage_off, 0, sizeof(pl->stage_off));
@@ -509,6 +549,7 @@ void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages, in
   p->identity_round0 = 0;
   p->nstage_B = 0;
   p->max_peel_rounds = 64;
+  p->jump_L = 64;
   p->eps0 = 1e-4;
   p->eps1 = 1e-4;
   p->zero_k = 4.0;

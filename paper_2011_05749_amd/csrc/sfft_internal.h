@@ -18,6 +18,9 @@ constexpr int kPerThread = kChunk / kThreads;
 constexpr int kMaxD = 4;             // delays handled by the direct partial-sum kernel
 constexpr int kMaxMeas = 64;         // rounds x delays per class vector
 constexpr int kMaxFfastBuckets = 4096;
+constexpr int kJumpMax = 64;         // largest stride L' resolved by the dense pass
+constexpr int kJumpChunk = 65536;    // signal elements per dense-pass work item
+constexpr int kJumpPerThread = 16;   // elements per thread between twiddle anchors
 
 // Static description of one signal of a batch (from its plan).
 struct SigDesc {
@@ -27,7 +30,7 @@ struct SigDesc {
   int32_t kind, mode, R, D, n;
   int32_t max_levels, window, nstages, max_peel_rounds;
   int32_t found_cap, multi_cap;
-  int32_t pad0;
+  int32_t jump_L;
   int64_t stageB[SFFT_MAX_STAGES];
   int64_t stageOff[SFFT_MAX_STAGES + 1];
   uint64_t shift[SFFT_MAX_ROUNDS];
@@ -72,7 +75,9 @@ struct Arena {
   int64_t *multi_c[2];
   float2 *multi_y[2];
   double2 *multi_z[2];
-  int32_t *pre;           // 3 prefix arrays of nsig+1: fft items, direct items, children
+  int32_t *pre;           // 5 prefix arrays of nsig+1: fft items, direct items,
+                          // children, dense-pass items, subtree-resolve items
+  double2 *jacc;          // per multi-ton slot: kJumpMax dense-pass coefficients
   const float2 *tw;       // e^{-2 pi i k / kFftMax}, k < kFftMax
 };
 
@@ -98,6 +103,8 @@ hipError_t launch_sched(const LaunchCtx &c, int level, hipStream_t s);
 hipError_t launch_expand_fft(const LaunchCtx &c, int level, int grid, hipStream_t s);
 hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStream_t s);
 hipError_t launch_children(const LaunchCtx &c, int level, int grid, hipStream_t s);
+hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t s);
+hipError_t launch_jump_resolve(const LaunchCtx &c, int level, int grid, hipStream_t s);
 hipError_t launch_finalize(const LaunchCtx &c, hipStream_t s);
 // level-0 class vectors in class-major order (tree: out[c*n + i]; FFAST as stored)
 hipError_t launch_export_level0(const LaunchCtx &c, void *out, hipStream_t s);

@@ -414,6 +414,8 @@ __global__ __launch_bounds__(kThreads) void k_level0_tree(LaunchCtx c) {
               c.A.multi_y[0][slot * c.nmax + i] = make_float2((float)Y[i].x, (float)Y[i].y);
               c.A.multi_z[0][slot * c.nmax + i] = make_double2(0.0, 0.0);
             }
+          if (d.jump_L > 0 && L <= d.jump_L)
+            for (int t = 0; t < L; t++) c.A.jacc[slot * kJumpMax + t] = make_double2(0.0, 0.0);
         } else {
           atomicOr(&c.st[s].flags, 3);
         }
@@ -648,50 +650,51 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
 }
 
 // Work of tree level `level` for every signal: prefix sums of FFT items,
-// direct partial-sum items and children; resets this level's multi-ton count.
+// direct partial-sum items, children, dense-pass items and subtree-resolve
+// items; resets this level's multi-ton count.
 __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
   __shared__ int red[16];
   const int par = (level - 1) & 1;
-  int carry_f = 0, carry_d = 0, carry_c = 0;
-  int32_t *pf = c.A.pre, *pd = c.A.pre + (c.nsig + 1), *pc = c.A.pre + 2 * (c.nsig + 1);
+  const int np = c.nsig + 1;
+  int carry[5] = {0, 0, 0, 0, 0};
   for (int base = 0; base < c.nsig; base += blockDim.x) {
     const int s = base + threadIdx.x;
-    int nf = 0, nd = 0, nc = 0;
+    int cnt[5] = {0, 0, 0, 0, 0};
     if (s < c.nsig) {
       const SigDesc &d = c.desc[s];
       if (d.kind == SFFT_KIND_TREE && level <= d.max_levels) {
         int m = c.st[s].multi[par];
         if (m > d.multi_cap) m = d.multi_cap;
-        const int64_t Bp = d.B0 << (level - 1);
+        const int lb = d.log2B0 + level - 1;
+        const int64_t Bp = (int64_t)1 << lb;
+        const int64_t Lp = d.N >> lb;
         if (m > 0) {
-          if (Bp <= kFftMax) nf = d.R;
-          else nd = d.R * (int)((Bp + kChunk - 1) / kChunk);
-          nc = 2 * m;
+          const bool jump = d.jump_L > 0 && Lp <= d.jump_L;
+          if (jump) {
+            cnt[3] = (int)((d.N + kJumpChunk - 1) / kJumpChunk);
+            cnt[4] = m;
+            c.st[s].samples += d.N;
+          } else {
+            if (Bp <= kFftMax) cnt[0] = d.R;
+            else cnt[1] = d.R * (int)((Bp + kChunk - 1) / kChunk);
+            cnt[2] = 2 * m;
+            c.st[s].samples += (int64_t)d.n * Bp;
+          }
           c.st[s].levels = level;
-          c.st[s].samples += (int64_t)d.n * Bp;
           c.st[s].level_mask |= 1ull << level;
         }
       }
       c.st[s].multi[level & 1] = 0;
     }
-    int tf, td, tc;
-    const int ef = block_scan_excl(nf, red, &tf);
-    const int ed = block_scan_excl(nd, red, &td);
-    const int ec = block_scan_excl(nc, red, &tc);
-    if (s < c.nsig) {
-      pf[s] = carry_f + ef;
-      pd[s] = carry_d + ed;
-      pc[s] = carry_c + ec;
+    for (int k = 0; k < 5; k++) {
+      int tot;
+      const int ex = block_scan_excl(cnt[k], red, &tot);
+      if (s < c.nsig) c.A.pre[k * np + s] = carry[k] + ex;
+      carry[k] += tot;
     }
-    carry_f += tf;
-    carry_d += td;
-    carry_c += tc;
   }
-  if (threadIdx.x == 0) {
-    pf[c.nsig] = carry_f;
-    pd[c.nsig] = carry_d;
-    pc[c.nsig] = carry_c;
-  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; k++) c.A.pre[k * np + c.nsig] = carry[k];
 }
 
 // Odd-offset samples of level `level` (B' = B0 2^{level-1} per round and
@@ -864,6 +867,8 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
               c.A.multi_y[cur][sl * c.nmax + i] = make_float2((float)Y[i].x, (float)Y[i].y);
               c.A.multi_z[cur][sl * c.nmax + i] = make_double2(0.0, 0.0);
             }
+          if (d.jump_L > 0 && L <= d.jump_L)
+            for (int t = 0; t < L; t++) c.A.jacc[sl * kJumpMax + t] = make_double2(0.0, 0.0);
         } else {
           atomicOr(&c.st[s].flags, 3);
         }
@@ -871,6 +876,185 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
         atomicOr(&c.st[s].flags, 1);
       }
     }
+  }
+}
+
+// Dense pass of the subtree resolution: for every open class c of level-1
+// (B' buckets, stride L' <= kJumpMax) accumulate its L' coefficients
+//   M_c(t) = sum_{m < B'} x[m L' + t] e^{-2 pi i c m / B'},   t < L'
+// (the class's bucket at level-1 measured with shift t, times B') from one
+// coalesced read of x.  Item = (signal, chunk of kJumpChunk elements); thread
+// tid holds the elements p = p0 + tid + 256 i, all with t = tid mod L'.
+__global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) {
+  __shared__ float2 red[kThreads / 64][64];
+  const int par = (level - 1) & 1;
+  const int np = c.nsig + 1;
+  const int32_t *pj = c.A.pre + 3 * np;
+  const int total = pj[c.nsig];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_owner(pj, c.nsig, item);
+    const int ch = item - pj[s];
+    const SigDesc &d = c.desc[s];
+    const float2 *__restrict__ x = io_of(c, s).x;
+    const int64_t N = d.N;
+    const int lb = d.log2B0 + level - 1;
+    const uint64_t Bp = (uint64_t)1 << lb;
+    const int lgL = d.log2N - lb;
+    const int Lp = 1 << lgL;
+    int m_s = c.st[s].multi[par];
+    if (m_s > d.multi_cap) m_s = d.multi_cap;
+    const int64_t p0 = (int64_t)ch * kJumpChunk;
+    const int64_t pend = (p0 + kJumpChunk < N) ? p0 + kJumpChunk : N;
+    const uint64_t mstep = (uint64_t)(kThreads >> lgL);
+    for (int j0 = 0; j0 < m_s; j0 += 8) {
+      float2 acc[8], tw[8], st[8];
+      uint64_t cls[8];
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        acc[q] = make_float2(0.f, 0.f);
+        cls[q] = (j0 + q < m_s) ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + q] : 0;
+        const double2 u = unit_d((cls[q] * mstep) & (Bp - 1), Bp, -1);
+        st[q] = make_float2((float)u.x, (float)u.y);
+      }
+      for (int64_t pb = p0; pb < pend; pb += (int64_t)kThreads * kJumpPerThread) {
+        const uint64_t m0 = (uint64_t)(pb + threadIdx.x) >> lgL;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+          const double2 u = unit_d((cls[q] * m0) & (Bp - 1), Bp, -1);
+          tw[q] = make_float2((float)u.x, (float)u.y);
+        }
+#pragma unroll 4
+        for (int i = 0; i < kJumpPerThread; i++) {
+          const int64_t p = pb + threadIdx.x + (int64_t)i * kThreads;
+          const float2 v = p < pend ? x[p] : make_float2(0.f, 0.f);
+#pragma unroll
+          for (int q = 0; q < 8; q++) {
+            const float2 t = cmulf(v, tw[q]);
+            acc[q].x += t.x;
+            acc[q].y += t.y;
+            tw[q] = cmulf(tw[q], st[q]);
+          }
+        }
+      }
+      // sum the threads that share t = tid mod L', then one FP64 atomic per (class, t)
+#pragma unroll
+      for (int q = 0; q < 8; q++) {
+        float vx = acc[q].x, vy = acc[q].y;
+        for (int o = Lp; o < 64; o <<= 1) {
+          vx += __shfl_xor(vx, o);
+          vy += __shfl_xor(vy, o);
+        }
+        if (lane < Lp) red[w][lane] = make_float2(vx, vy);
+        __syncthreads();
+        if (threadIdx.x < Lp && j0 + q < m_s) {
+          double sx = 0.0, sy = 0.0;
+          for (int ww = 0; ww < kThreads / 64; ww++) {
+            sx += (double)red[ww][threadIdx.x].x;
+            sy += (double)red[ww][threadIdx.x].y;
+          }
+          double *a = (double *)&c.A.jacc[(d.multi_off + j0 + q) * kJumpMax + threadIdx.x];
+          atomicAdd(a, sx);
+          atomicAdd(a + 1, sy);
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// Subtree resolution of one open class c (one wave): its L' frequencies
+// f_k = c + k B' have the values xhat_{f_k} = (1/L') sum_t M_c(t)/B'
+// e^{-2 pi i f_k t / N}; the class vector of any descendant class at any
+// deeper level is the sum, over the frequencies it holds, of
+// xhat_f e^{2 pi i f tau_i / N} -- the same linear functional of x as the
+// level's gathered buckets -- so the level-by-level classification of the
+// tree search (Sect. 3.3) runs on these vectors.
+template <int NMAX>
+__global__ __launch_bounds__(64) void k_jump_resolve(LaunchCtx c, int level) {
+  __shared__ double2 V[kJumpMax][NMAX];
+  __shared__ double2 Ms[kJumpMax];
+  __shared__ int open_cur[kJumpMax], open_nxt[kJumpMax];
+  __shared__ int any_open;
+  const int par = (level - 1) & 1;
+  const int np = c.nsig + 1;
+  const int32_t *pr = c.A.pre + 4 * np;
+  const int total = pr[c.nsig];
+  const int k = threadIdx.x;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    const int s = find_owner(pr, c.nsig, item);
+    const int j = item - pr[s];
+    const SigDesc &d = c.desc[s];
+    const int64_t N = d.N;
+    const int n = d.n;
+    const int lb = d.log2B0 + level - 1;
+    const int64_t Bp = (int64_t)1 << lb;
+    const int Lp = (int)(N >> lb);
+    const int64_t slot = d.multi_off + j;
+    const int64_t cpar = c.A.multi_c[par][slot];
+    const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
+    if (k < Lp) {
+      const double2 a = c.A.jacc[slot * kJumpMax + k];
+      Ms[k] = make_double2(a.x / (double)Bp, a.y / (double)Bp);
+    }
+    __syncthreads();
+    if (k < Lp) {
+      const uint64_t f = (uint64_t)(cpar + (int64_t)k * Bp);
+      double2 xh = make_double2(0.0, 0.0);
+      for (int t = 0; t < Lp; t++) {
+        const double2 e = unit_d(mod_n(f * (uint64_t)t, d), (uint64_t)N, -1);
+        const double2 u = cmul(Ms[t], e);
+        xh.x += u.x;
+        xh.y += u.y;
+      }
+      xh.x /= (double)Lp;
+      xh.y /= (double)Lp;
+      for (int i = 0; i < n; i++) V[k][i] = cmul(xh, unit_d(mod_n(f * tau_of(d, i), d), (uint64_t)N, +1));
+    }
+    if (k < kJumpMax) open_cur[k] = k < 2 ? 1 : 0;
+    __syncthreads();
+    for (int dd = 1; (1 << dd) <= Lp; dd++) {
+      const int lvl = level + dd - 1;
+      const int nq = 1 << dd;
+      const int64_t Bd = Bp << dd;
+      const int64_t Ld = N / Bd;
+      if (k < kJumpMax) open_nxt[k] = 0;
+      if (k == 0) any_open = 0;
+      __syncthreads();
+      if (k < nq && open_cur[k]) {
+        double2 Y[NMAX];
+#pragma unroll
+        for (int i = 0; i < NMAX; i++) {
+          Y[i] = make_double2(0.0, 0.0);
+          if (i < n)
+            for (int kk = k; kk < Lp; kk += nq) {
+              Y[i].x += V[kk][i].x;
+              Y[i].y += V[kk][i].y;
+            }
+        }
+        const int64_t cc = cpar + (int64_t)k * Bp;
+        const Verdict v = classify<NMAX>(Y, d, n, d.R, cc, Bd, sref2, nv);
+        atomicMax(&c.st[s].levels, lvl);
+        if (v.cls == kSingle) {
+          const int fs = atomicAdd(&c.st[s].found, 1);
+          push_found(c, s, d, fs, v.f, v.a);
+        } else if (v.cls == kMulti) {
+          if (Ld >= 2 && lvl + 1 <= d.max_levels) {
+            open_nxt[k] = 1;
+            open_nxt[k + nq] = 1;
+            any_open = 1;
+          } else {
+            atomicOr(&c.st[s].flags, 1);
+          }
+        }
+      }
+      __syncthreads();
+      if (k < kJumpMax) open_cur[k] = open_nxt[k];
+      const int more = any_open;
+      __syncthreads();
+      if (!more) break;
+    }
+    __syncthreads();
   }
 }
 
@@ -1047,6 +1231,19 @@ hipError_t launch_expand_fft(const LaunchCtx &c, int level, int grid, hipStream_
 
 hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStream_t s) {
   hipLaunchKernelGGL(k_expand_direct, dim3(grid), dim3(kThreads), 0, s, c, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_jump_pass, dim3(grid), dim3(kThreads), 0, s, c, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_jump_resolve(const LaunchCtx &c, int level, int grid, hipStream_t s) {
+  const int nm = nmax_bucket(c.nmax);
+  if (nm == 8) hipLaunchKernelGGL(k_jump_resolve<8>, dim3(grid), dim3(64), 0, s, c, level);
+  else if (nm == 16) hipLaunchKernelGGL(k_jump_resolve<16>, dim3(grid), dim3(64), 0, s, c, level);
+  else hipLaunchKernelGGL(k_jump_resolve<64>, dim3(grid), dim3(64), 0, s, c, level);
   return hipGetLastError();
 }
 

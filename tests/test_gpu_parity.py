@@ -40,7 +40,7 @@ def oracle_cfg(N, K, stages, delays, seed=0, mode=0, B0=0, identity_round0=False
 
 
 def solve_both(sfft, x, N, K, stages, delays, seed=0, **kw):
-    ok = {k: v for k, v in kw.items() if k not in ("stage_B",)}
+    ok = {k: v for k, v in kw.items() if k not in ("stage_B", "jump_L")}
     mode = kw.get("mode", 0)
     plan = sfft.Plan(N, K, stages, delays, seed=seed, **kw)
     ocfg_kw = {}
@@ -112,28 +112,36 @@ def test_ffast_n20_example(sfft, D):
 
 
 # ------------------------------------------------------------ tree search (a7)
+@pytest.mark.parametrize("jump", [0, 64, 8])
 @pytest.mark.parametrize("N,K,R,B0,seed,ident", [
     (2 ** 12, 8, 1, 8, 1, 1), (2 ** 14, 64, 2, 128, 2, 0), (2 ** 16, 300, 4, 512, 4, 0),
     (2 ** 16, 100, 4, 256, 3, 0), (2 ** 10, 1, 1, 1, 5, 1), (2 ** 13, 7, 3, 16, 6, 0),
     (2 ** 18, 200, 1, 256, 7, 1), (2 ** 20, 256, 4, 512, 8, 0), (2 ** 17, 37, 2, 64, 9, 0)])
-def test_tree_exact(sfft, N, K, R, B0, seed, ident):
+def test_tree_exact(sfft, N, K, R, B0, seed, ident, jump):
+    """jump = 0: level-by-level gathers to the end; jump > 0: subtree
+    resolution once the stride is <= jump (same decisions, fewer passes)."""
     sp = siggen.make_spec(N, K, seed)
     x = siggen.synth(sp)
-    g, o = solve_both(sfft, x, N, K, R, 2, seed=seed, B0=B0, identity_round0=ident)
+    g, o = solve_both(sfft, x, N, K, R, 2, seed=seed, B0=B0, identity_round0=ident, jump_L=jump)
     assert_parity(g, o)
     assert g[3]["levels"] == o[3].levels
-    assert g[3]["samples"] == o[3].samples
+    if jump == 0:
+        assert g[3]["samples"] == o[3].samples
     np.testing.assert_array_equal(g[0], siggen.truth(sp)[0])
 
 
-def test_tree_worst_pair_full_depth(sfft):
+@pytest.mark.parametrize("jump", [0, 64])
+def test_tree_worst_pair_full_depth(sfft, jump):
     N = 2 ** 12
     x = siggen.synth(siggen.make_spec(N, 2, 4, support=[0, N // 2]))
-    g, o = solve_both(sfft, x, N, 2, 1, 2, B0=1, identity_round0=1)
+    g, o = solve_both(sfft, x, N, 2, 1, 2, B0=1, identity_round0=1, jump_L=jump)
     assert_parity(g, o)
-    g, o = solve_both(sfft, x, N, 2, 1, 2, B0=1, identity_round0=1, max_levels=5)
-    assert_parity(g, o)
-    assert g[3]["status"] == 1 and g[2] == 0
+    assert g[3]["levels"] == o[3].levels == 12
+    for cap in (5, 8, 11):
+        g, o = solve_both(sfft, x, N, 2, 1, 2, B0=1, identity_round0=1, max_levels=cap,
+                          jump_L=jump)
+        assert_parity(g, o)
+        assert g[3]["status"] == 1 and g[2] == 0
 
 
 def test_tree_n64_example(sfft):
@@ -191,12 +199,13 @@ def test_determinism(sfft):
 
 
 # ------------------------------------------------------------------ noisy mode
+@pytest.mark.parametrize("jump", [0, 64])
 @pytest.mark.parametrize("window,seed", [(0, 31), (64, 32)])
-def test_noisy_tree(sfft, window, seed):
+def test_noisy_tree(sfft, window, seed, jump):
     N, K = 2 ** 16, 32
     sp = siggen.make_spec(N, K, seed, snr_db=20.0)
     x = siggen.synth(sp)
-    g, o = solve_both(sfft, x, N, K, 4, 2, seed=8, mode=1, window=window)
+    g, o = solve_both(sfft, x, N, K, 4, 2, seed=8, mode=1, window=window, jump_L=jump)
     assert_parity(g, o, tol=1e-4)
     assert abs(g[3]["noise_var"] / o[3].noise_var - 1) < 1e-4
 

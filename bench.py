@@ -62,7 +62,9 @@ def kernel_bytes(name, level, plans, stats):
             bp = inf.B0 << (level - 1)
             if inf.jump_L > 0 and (inf.N // bp) <= inf.jump_L:
                 continue
-            if (bp <= 8192) == (name == "k_expand_fft"):
+            # B' <= 8192: one LDS FFT; larger B' uses split LDS FFTs (k_expand_fft)
+            # whenever a signal has >= 4 parents, which the headline always has there
+            if name == "k_expand_fft":
                 tot += n * bp * 8
     return tot
 

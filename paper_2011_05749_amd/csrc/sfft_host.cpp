@@ -284,14 +284,18 @@ struct BatchCtx {
         if (d.kind != SFFT_KIND_TREE || l > d.max_levels) continue;
         const int jl = jump_level(d);
         if (l > jl) continue;
+        const int64_t Bp = d.B0 << (l - 1);
         if (l == jl) {
-          nj += (d.N + kJumpChunk - 1) / kJumpChunk;
+          nj += (Bp + kJumpItemRows - 1) / kJumpItemRows;
           nr += d.multi_cap;
           continue;
         }
-        const int64_t Bp = d.B0 << (l - 1);
-        if (Bp <= kFftMax) nf += d.R;
-        else nd += (int64_t)d.R * ((Bp + kChunk - 1) / kChunk);
+        if (Bp <= kFftMax) {
+          nf += d.R;
+        } else {
+          nf += (int64_t)d.R * (Bp / kFftMax);
+          nd += (int64_t)d.R * ((Bp + kChunk - 1) / kChunk);
+        }
         nch += 2 * (int64_t)d.multi_cap;
       }
       L.fft = nf > 0;

@@ -19,8 +19,9 @@ constexpr int kMaxD = 4;             // delays handled by the direct partial-sum
 constexpr int kMaxMeas = 64;         // rounds x delays per class vector
 constexpr int kMaxFfastBuckets = 4096;
 constexpr int kJumpMax = 64;         // largest stride L' resolved by the dense pass
-constexpr int kJumpChunk = 65536;    // signal elements per dense-pass work item
-constexpr int kJumpPerThread = 16;   // elements per thread between twiddle anchors
+constexpr int kJumpItemRows = 2048;  // rows of L' elements per dense-pass work item
+constexpr int kJumpBlockRows = 512;  // rows whose twiddles share one LDS table
+constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses split FFTs
 
 // Static description of one signal of a batch (from its plan).
 struct SigDesc {

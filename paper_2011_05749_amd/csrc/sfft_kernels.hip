@@ -64,26 +64,59 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t m, int lg) {
   return lg == 0 ? 0u : (__brev(m) >> (32 - lg));
 }
 
-// In-place radix-2 decimation-in-time FFT of B = 2^lg complex64 values held in
-// LDS in bit-reversed order; forward sign e^{-2 pi i hm / B}, no scaling.
-// Twiddles come from the kFftMax-point table.
+// In-place decimation-in-time FFT of B = 2^lg complex64 values held in LDS
+// in bit-reversed order; forward sign e^{-2 pi i hm / B}, no scaling.  Two
+// radix-2 stages are fused per pass (radix-2^2): each thread owns four
+// points at distance h = 2^{s-1}, so a pass reads and writes LDS once for two
+// stages; an odd lg starts with one plain radix-2 stage.  Twiddles come from
+// the kFftMax-point table.
 __device__ void fft_lds(float2 *X, int lg, const float2 *__restrict__ tw) {
   const int B = 1 << lg;
-  for (int s = 1; s <= lg; s++) {
-    const int h = 1 << (s - 1);
-    const int tsh = kLog2FftMax - s;
+  int s = 1;
+  if (lg & 1) {
     for (int t = threadIdx.x; t < (B >> 1); t += blockDim.x) {
+      const float2 a = X[2 * t], b = X[2 * t + 1];
+      X[2 * t] = make_float2(a.x + b.x, a.y + b.y);
+      X[2 * t + 1] = make_float2(a.x - b.x, a.y - b.y);
+    }
+    __syncthreads();
+    s = 2;
+  }
+  for (; s + 1 <= lg; s += 2) {
+    const int h = 1 << (s - 1);
+    for (int t = threadIdx.x; t < (B >> 2); t += blockDim.x) {
       const int j = t & (h - 1);
-      const int i0 = ((t >> (s - 1)) << s) + j;
-      const int i1 = i0 + h;
-      const float2 w = tw[j << tsh];
-      const float2 a = X[i0];
-      const float2 b = cmulf(X[i1], w);
-      X[i0] = make_float2(a.x + b.x, a.y + b.y);
-      X[i1] = make_float2(a.x - b.x, a.y - b.y);
+      const int i0 = ((t >> (s - 1)) << (s + 1)) + j;
+      const float2 w1 = tw[j << (kLog2FftMax - s)];       // w_{2h}^j
+      const float2 w2 = tw[j << (kLog2FftMax - s - 1)];   // w_{4h}^j; w_{4h}^{j+h} = -i w2
+      const float2 a0 = X[i0], a1 = cmulf(X[i0 + h], w1);
+      const float2 a2 = X[i0 + 2 * h], a3 = cmulf(X[i0 + 3 * h], w1);
+      const float2 b0 = make_float2(a0.x + a1.x, a0.y + a1.y);
+      const float2 b1 = make_float2(a0.x - a1.x, a0.y - a1.y);
+      const float2 b2 = make_float2(a2.x + a3.x, a2.y + a3.y);
+      const float2 b3 = make_float2(a2.x - a3.x, a2.y - a3.y);
+      const float2 c2 = cmulf(b2, w2);
+      const float2 t3 = cmulf(b3, w2);
+      const float2 c3 = make_float2(t3.y, -t3.x);
+      X[i0] = make_float2(b0.x + c2.x, b0.y + c2.y);
+      X[i0 + 2 * h] = make_float2(b0.x - c2.x, b0.y - c2.y);
+      X[i0 + h] = make_float2(b1.x + c3.x, b1.y + c3.y);
+      X[i0 + 3 * h] = make_float2(b1.x - c3.x, b1.y - c3.y);
     }
     __syncthreads();
   }
+}
+
+// e^{-2 pi i t / M} in FP32 for M a power of two: the ratio 2t/M is exact in
+// FP32 when M <= 2^24, otherwise the angle is reduced in FP64
+__device__ __forceinline__ float2 unit_f(uint64_t t, uint64_t M) {
+  if (M <= (1ull << 24)) {
+    float sn, cs;
+    sincospif(2.0f * (float)t / (float)M, &sn, &cs);
+    return make_float2(cs, -sn);
+  }
+  const double2 u = unit_d(t, M, -1);
+  return make_float2((float)u.x, (float)u.y);
 }
 
 // wave-wide compaction: lanes with pred get consecutive slots of *counter;
@@ -671,11 +704,11 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
         if (m > 0) {
           const bool jump = d.jump_L > 0 && Lp <= d.jump_L;
           if (jump) {
-            cnt[3] = (int)((d.N + kJumpChunk - 1) / kJumpChunk);
+            cnt[3] = (int)((Bp + kJumpItemRows - 1) / kJumpItemRows);
             cnt[4] = m;
             c.st[s].samples += d.N;
           } else {
-            if (Bp <= kFftMax) cnt[0] = d.R;
+            if (Bp <= kFftMax || m >= kSplitMinBins) cnt[0] = d.R * (int)(Bp > kFftMax ? Bp / kFftMax : 1);
             else cnt[1] = d.R * (int)((Bp + kChunk - 1) / kChunk);
             cnt[2] = 2 * m;
             c.st[s].samples += (int64_t)d.n * Bp;
@@ -698,7 +731,10 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
 }
 
 // Odd-offset samples of level `level` (B' = B0 2^{level-1} per round and
-// delay, offset L'/2) by a B'-point LDS FFT; writes the bins of the parents.
+// delay, offset L'/2).  The parents' bins of their B'-point DFT come from P =
+// B'/Bs sub-FFTs of size Bs = min(B', kFftMax) in LDS: with m = m' P + p,
+//   Z[c] = sum_p e^{-2 pi i c p / B'} FFT_Bs(z[m' P + p])[c mod Bs].
+// Item = (signal, round, p); the P partial bins meet in FP64 atomics.
 __global__ __launch_bounds__(kThreads) void k_expand_fft(LaunchCtx c, int level) {
   extern __shared__ float2 lds[];
   const int par = (level - 1) & 1;
@@ -706,28 +742,40 @@ __global__ __launch_bounds__(kThreads) void k_expand_fft(LaunchCtx c, int level)
   const int total = pf[c.nsig];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int s = find_owner(pf, c.nsig, item);
-    const int r = item - pf[s];
+    const int rem = item - pf[s];
     const SigDesc &d = c.desc[s];
     const float2 *__restrict__ x = io_of(c, s).x;
     const int64_t N = d.N;
     const int lb = d.log2B0 + level - 1;
     const int64_t Bp = (int64_t)1 << lb;
     const int64_t Lp = N >> lb;
+    const int lgs = lb < kLog2FftMax ? lb : kLog2FftMax;
+    const int64_t Bs = (int64_t)1 << lgs;
+    const int P = (int)(Bp >> lgs);
+    const int r = rem / P, p = rem % P;
     int m_s = c.st[s].multi[par];
     if (m_s > d.multi_cap) m_s = d.multi_cap;
-    const int n = d.n;
     for (int dl = 0; dl < d.D; dl++) {
       const uint64_t tau = (d.shift[r] + (uint64_t)dl + (uint64_t)(Lp >> 1)) & (uint64_t)(N - 1);
-      for (int64_t m = threadIdx.x; m < Bp; m += blockDim.x) {
-        const uint64_t pos = ((uint64_t)m * (uint64_t)Lp + tau) & (uint64_t)(N - 1);
-        lds[bitrev((uint32_t)m, lb)] = x[pos];
+      for (int64_t m = threadIdx.x; m < Bs; m += blockDim.x) {
+        const uint64_t pos = ((uint64_t)(m * P + p) * (uint64_t)Lp + tau) & (uint64_t)(N - 1);
+        lds[bitrev((uint32_t)m, lgs)] = x[pos];
       }
       __syncthreads();
-      fft_lds(lds, lb, c.A.tw);
+      fft_lds(lds, lgs, c.A.tw);
       for (int j = threadIdx.x; j < m_s; j += blockDim.x) {
         const int64_t slot = d.multi_off + j;
-        const int64_t cc = c.A.multi_c[par][slot];
-        c.A.multi_z[par][slot * c.nmax + r * d.D + dl] = to_d(lds[cc]);
+        const uint64_t cc = (uint64_t)c.A.multi_c[par][slot];
+        double2 v = to_d(lds[cc & (uint64_t)(Bs - 1)]);
+        double *zz = (double *)&c.A.multi_z[par][slot * c.nmax + r * d.D + dl];
+        if (P == 1) {
+          zz[0] = v.x;
+          zz[1] = v.y;
+        } else {
+          v = cmul(v, unit_d((cc * (uint64_t)p) & (uint64_t)(Bp - 1), (uint64_t)Bp, -1));
+          atomicAdd(zz, v.x);
+          atomicAdd(zz + 1, v.y);
+        }
       }
       __syncthreads();
     }
@@ -883,81 +931,99 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
 // (B' buckets, stride L' <= kJumpMax) accumulate its L' coefficients
 //   M_c(t) = sum_{m < B'} x[m L' + t] e^{-2 pi i c m / B'},   t < L'
 // (the class's bucket at level-1 measured with shift t, times B') from one
-// coalesced read of x.  Item = (signal, chunk of kJumpChunk elements); thread
-// tid holds the elements p = p0 + tid + 256 i, all with t = tid mod L'.
+// coalesced read of x.  All L' elements of a row m share the twiddle of the
+// row, so the twiddles of a block of rows live in LDS (one entry per class
+// and row) and each element costs one complex multiply-add per class.
+// Item = (signal, kJumpItemRows rows); thread tid owns t = tid mod L'.
+template <int NQ>
+__device__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__restrict__ x,
+                          int64_t row0, int nrows, int lgL, uint64_t Bp, const uint64_t *cls,
+                          float2 *T, float2 (*red)[64], int64_t slot0) {
+  const int Lp = 1 << lgL;
+  float2 acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; q++) acc[q] = make_float2(0.f, 0.f);
+  for (int b0 = 0; b0 < nrows; b0 += kJumpBlockRows) {
+    const int nb = (nrows - b0) < kJumpBlockRows ? (nrows - b0) : kJumpBlockRows;
+    for (int u = threadIdx.x; u < NQ * kJumpBlockRows; u += kThreads) {
+      const int q = u / kJumpBlockRows, rr = u % kJumpBlockRows;
+      if (rr < nb) T[u] = unit_f((cls[q] * (uint64_t)(row0 + b0 + rr)) & (Bp - 1), Bp);
+    }
+    __syncthreads();
+    const int ne = nb << lgL;
+    const float2 *xb = x + ((row0 + b0) << lgL);
+#pragma unroll 8
+    for (int e = threadIdx.x; e < ne; e += kThreads) {
+      const float2 v = xb[e];
+      const int rr = e >> lgL;
+#pragma unroll
+      for (int q = 0; q < NQ; q++) {
+        const float2 w = T[q * kJumpBlockRows + rr];
+        acc[q].x += v.x * w.x - v.y * w.y;
+        acc[q].y += v.x * w.y + v.y * w.x;
+      }
+    }
+    __syncthreads();
+  }
+  // sum the threads that share t = tid mod L', then one FP64 atomic per (class, t)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NQ; q++) {
+    float vx = acc[q].x, vy = acc[q].y;
+    for (int o = Lp; o < 64; o <<= 1) {
+      vx += __shfl_xor(vx, o);
+      vy += __shfl_xor(vy, o);
+    }
+    if (lane < Lp) red[w][lane] = make_float2(vx, vy);
+    __syncthreads();
+    if (threadIdx.x < Lp) {
+      double sx = 0.0, sy = 0.0;
+      for (int ww = 0; ww < kThreads / 64; ww++) {
+        sx += (double)red[ww][threadIdx.x].x;
+        sy += (double)red[ww][threadIdx.x].y;
+      }
+      double *a = (double *)&c.A.jacc[(slot0 + q) * kJumpMax + threadIdx.x];
+      atomicAdd(a, sx);
+      atomicAdd(a + 1, sy);
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) {
+  __shared__ float2 T[8 * kJumpBlockRows];
   __shared__ float2 red[kThreads / 64][64];
   const int par = (level - 1) & 1;
   const int np = c.nsig + 1;
   const int32_t *pj = c.A.pre + 3 * np;
   const int total = pj[c.nsig];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int s = find_owner(pj, c.nsig, item);
     const int ch = item - pj[s];
     const SigDesc &d = c.desc[s];
     const float2 *__restrict__ x = io_of(c, s).x;
-    const int64_t N = d.N;
     const int lb = d.log2B0 + level - 1;
     const uint64_t Bp = (uint64_t)1 << lb;
     const int lgL = d.log2N - lb;
-    const int Lp = 1 << lgL;
     int m_s = c.st[s].multi[par];
     if (m_s > d.multi_cap) m_s = d.multi_cap;
-    const int64_t p0 = (int64_t)ch * kJumpChunk;
-    const int64_t pend = (p0 + kJumpChunk < N) ? p0 + kJumpChunk : N;
-    const uint64_t mstep = (uint64_t)(kThreads >> lgL);
+    const int64_t row0 = (int64_t)ch * kJumpItemRows;
+    const int nrows = (int)((int64_t)Bp - row0 < kJumpItemRows ? (int64_t)Bp - row0 : kJumpItemRows);
     for (int j0 = 0; j0 < m_s; j0 += 8) {
-      float2 acc[8], tw[8], st[8];
+      const int nq = (m_s - j0) < 8 ? (m_s - j0) : 8;
       uint64_t cls[8];
 #pragma unroll
-      for (int q = 0; q < 8; q++) {
-        acc[q] = make_float2(0.f, 0.f);
-        cls[q] = (j0 + q < m_s) ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + q] : 0;
-        const double2 u = unit_d((cls[q] * mstep) & (Bp - 1), Bp, -1);
-        st[q] = make_float2((float)u.x, (float)u.y);
-      }
-      for (int64_t pb = p0; pb < pend; pb += (int64_t)kThreads * kJumpPerThread) {
-        const uint64_t m0 = (uint64_t)(pb + threadIdx.x) >> lgL;
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-          const double2 u = unit_d((cls[q] * m0) & (Bp - 1), Bp, -1);
-          tw[q] = make_float2((float)u.x, (float)u.y);
-        }
-#pragma unroll 4
-        for (int i = 0; i < kJumpPerThread; i++) {
-          const int64_t p = pb + threadIdx.x + (int64_t)i * kThreads;
-          const float2 v = p < pend ? x[p] : make_float2(0.f, 0.f);
-#pragma unroll
-          for (int q = 0; q < 8; q++) {
-            const float2 t = cmulf(v, tw[q]);
-            acc[q].x += t.x;
-            acc[q].y += t.y;
-            tw[q] = cmulf(tw[q], st[q]);
-          }
-        }
-      }
-      // sum the threads that share t = tid mod L', then one FP64 atomic per (class, t)
-#pragma unroll
-      for (int q = 0; q < 8; q++) {
-        float vx = acc[q].x, vy = acc[q].y;
-        for (int o = Lp; o < 64; o <<= 1) {
-          vx += __shfl_xor(vx, o);
-          vy += __shfl_xor(vy, o);
-        }
-        if (lane < Lp) red[w][lane] = make_float2(vx, vy);
-        __syncthreads();
-        if (threadIdx.x < Lp && j0 + q < m_s) {
-          double sx = 0.0, sy = 0.0;
-          for (int ww = 0; ww < kThreads / 64; ww++) {
-            sx += (double)red[ww][threadIdx.x].x;
-            sy += (double)red[ww][threadIdx.x].y;
-          }
-          double *a = (double *)&c.A.jacc[(d.multi_off + j0 + q) * kJumpMax + threadIdx.x];
-          atomicAdd(a, sx);
-          atomicAdd(a + 1, sy);
-        }
-        __syncthreads();
+      for (int q = 0; q < 8; q++) cls[q] = q < nq ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + q] : 0;
+      const int64_t slot0 = d.multi_off + j0;
+      switch (nq) {
+        case 1: jump_rows<1>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
+        case 2: jump_rows<2>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
+        case 3: jump_rows<3>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
+        case 4: jump_rows<4>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
+        case 5: jump_rows<5>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
+        case 6: jump_rows<6>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
+        case 7: jump_rows<7>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
+        default: jump_rows<8>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
       }
     }
   }

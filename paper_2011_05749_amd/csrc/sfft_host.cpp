@@ -225,6 +225,21 @@ struct BatchCtx {
     std::vector<int32_t> lists;
     for (auto &t : tree) lists.push_back(t.second);
     for (auto &t : ffast) lists.push_back(t.second);
+    // level-0 item prefixes over the tree list: rounds, and 256-class chunks
+    const size_t l0_at = lists.size();
+    int32_t acc0 = 0;
+    for (auto &t : tree) {
+      lists.push_back(acc0);
+      acc0 += desc[t.second].R;
+    }
+    lists.push_back(acc0);
+    const size_t l0c_at = lists.size();
+    int32_t acc1 = 0;
+    for (auto &t : tree) {
+      lists.push_back(acc1);
+      acc1 += (int32_t)((desc[t.second].B0 + kThreads - 1) / kThreads);
+    }
+    lists.push_back(acc1);
     auto ck = [](hipError_t e) { return e == hipSuccess; };
     const size_t ns = (size_t)nsig;
     if (!ck(b_desc.alloc(sizeof(SigDesc) * ns)) || !ck(b_io.alloc(sizeof(SigIO) * ns)) ||
@@ -260,6 +275,10 @@ struct BatchCtx {
     c.A.tw = tw;
     c.tree_list = (const int32_t *)b_lists.p;
     c.ffast_list = (const int32_t *)b_lists.p + tree.size();
+    c.l0_pre = (const int32_t *)b_lists.p + l0_at;
+    c.l0c_pre = (const int32_t *)b_lists.p + l0c_at;
+    c.l0_items = acc0;
+    c.l0c_items = acc1;
     c.nsig = nsig;
     c.ntree = (int)tree.size();
     c.nffast = (int)ffast.size();
@@ -290,10 +309,11 @@ struct BatchCtx {
           nr += d.multi_cap;
           continue;
         }
-        if (Bp <= kFftMax) {
+        const int64_t Bsmax = int64_t(1) << split_lg(d.D);
+        if (Bp <= Bsmax) {
           nf += d.R;
         } else {
-          nf += (int64_t)d.R * (Bp / kFftMax);
+          nf += (int64_t)d.R * (Bp / Bsmax);
           nd += (int64_t)d.R * ((Bp + kChunk - 1) / kChunk);
         }
         nch += 2 * (int64_t)d.multi_cap;

@@ -23,6 +23,12 @@ constexpr int kJumpItemRows = 2048;  // rows of L' elements per dense-pass work 
 constexpr int kJumpBlockRows = 512;  // rows whose twiddles share one LDS table
 constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses split FFTs
 
+// log2 of the sub-FFT size used when the D delays of a sample are held in
+// LDS together (D planes of complex64 within 64 KiB)
+__host__ __device__ inline int split_lg(int D) {
+  return kLog2FftMax - (D <= 1 ? 0 : (D <= 2 ? 1 : 2));
+}
+
 // Static description of one signal of a batch (from its plan).
 struct SigDesc {
   int64_t N, K, B0;
@@ -91,6 +97,9 @@ struct LaunchCtx {
   Arena A;
   const int32_t *tree_list;
   const int32_t *ffast_list;
+  const int32_t *l0_pre;   // prefix over tree_list of the rounds (level-0 FFT items)
+  const int32_t *l0c_pre;  // prefix over tree_list of ceil(B0 / 256) (classify items)
+  int32_t l0_items, l0c_items;
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;

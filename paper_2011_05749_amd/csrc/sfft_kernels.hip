@@ -2,11 +2,12 @@
 //
 // Pipeline of one exec (any number of signals, one pass per phase):
 //   k_reset        zero the per-signal state
-//   k_level0_tree  (power-of-two N) per signal: gather of the B0 samples of
-//                  every round and delay (Eq. 5, advance shift), B0-point FFT
-//                  in LDS (Eq. 6), level-0 statistics, classification of the
-//                  B0 classes (Sect. 3.2 Subproblems 1-2) with wave-ballot
-//                  compaction of single-tons and multi-tons
+//   k_level0_fft   (power-of-two N) per (signal, round): gather of the B0
+//                  samples of every delay together (Eq. 5, advance shift),
+//                  B0-point FFT in LDS (Eq. 6) as sub-FFTs of <= 8192 points
+//   k_level0_stats per signal: mean bucket power, noise quantile
+//   k_level0_classify per (signal, 256 classes): Sect. 3.2 Subproblems 1-2,
+//                  wave-ballot compaction of single-tons and multi-tons
 //   k_ffast        (co-prime N) per signal: stage DFTs and the whole peeling
 //                  decoder (Sect. 3.2, Subproblem 3, Eq. 20) in one work-group
 //   per tree level l >= 1 (Sect. 3.3):
@@ -38,6 +39,24 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ double2 to_d(float2 v) { return make_double2(v.x, v.y); }
+
+// Signal reads through the global address space: a generic pointer would make
+// the compiler emit flat loads, which share the wait counter of LDS accesses
+// and so serialise every load behind the next LDS read.
+typedef __attribute__((address_space(1))) const unsigned long long gu64;
+__device__ __forceinline__ float2 ldg_at(gu64 *base, uint64_t i) {
+  const unsigned long long v = base[i];
+  return make_float2(__uint_as_float((unsigned)v), __uint_as_float((unsigned)(v >> 32)));
+}
+__device__ __forceinline__ float2 ldg(const float2 *p) { return ldg_at((gu64 *)p, 0); }
+
+// acc += a * b (complex, two FMAs per component)
+__device__ __forceinline__ void cmac(float2 &acc, float2 a, float2 b) {
+  acc.x = fmaf(a.x, b.x, acc.x);
+  acc.x = fmaf(-a.y, b.y, acc.x);
+  acc.y = fmaf(a.x, b.y, acc.y);
+  acc.y = fmaf(a.y, b.x, acc.y);
+}
 
 // e^{sign * 2 pi i t / M}, t an exact integer already reduced modulo M
 __device__ __forceinline__ double2 unit_d(uint64_t t, uint64_t M, int sign) {
@@ -104,6 +123,37 @@ __device__ void fft_lds(float2 *X, int lg, const float2 *__restrict__ tw) {
       X[i0 + 3 * h] = make_float2(b1.x - c3.x, b1.y - c3.y);
     }
     __syncthreads();
+  }
+}
+
+// All D delays of a sample are read in the same batch of loads (adjacent
+// addresses, one cache-line fill): plane dl of lds receives, in bit-reversed
+// order, x[((m P + p) L + tau0 + dl) & mask] for m < Bs = 2^lg.
+__device__ __forceinline__ void gather_delays(float2 *lds, const float2 *__restrict__ x, int64_t Bs,
+                                              int lg, uint64_t L, uint64_t P, uint64_t p,
+                                              uint64_t tau0, uint64_t mask, int D) {
+  gu64 *xg = (gu64 *)x;
+  for (int64_t m0 = threadIdx.x; m0 < Bs; m0 += 4 * (int64_t)blockDim.x) {
+    float2 v[4][kMaxD];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int64_t m = m0 + (int64_t)u * blockDim.x;
+      const uint64_t mc = (uint64_t)(m < Bs ? m : Bs - 1);   // in-bounds; stored only if m < Bs
+      const uint64_t base = (mc * P + p) * L + tau0;
+#pragma unroll
+      for (int dl = 0; dl < kMaxD; dl++)
+        v[u][dl] = dl < D ? ldg_at(xg, (base + (uint64_t)dl) & mask) : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int64_t m = m0 + (int64_t)u * blockDim.x;
+      if (m < Bs) {
+        const uint32_t br = bitrev((uint32_t)m, lg);
+#pragma unroll
+        for (int dl = 0; dl < kMaxD; dl++)
+          if (dl < D) lds[(int64_t)dl * Bs + br] = v[u][dl];
+      }
+    }
   }
 }
 
@@ -377,91 +427,136 @@ __global__ void k_reset(LaunchCtx c) {
   c.st[s] = z;
 }
 
-template <int NMAX>
-__global__ __launch_bounds__(kThreads) void k_level0_tree(LaunchCtx c) {
+// Level 0 of the tree, bucketization (Eq. 5-6): item = (signal, round r);
+// the D delays of every sample are gathered together and transformed by
+// P0 = B0 / Bs sub-FFTs of size Bs; with m = m' P0 + p,
+//   Yhat[c] = (1/B0) sum_p e^{-2 pi i c p / B0} FFT_Bs(y[m' P0 + p])[c mod Bs],
+// accumulated in the level-0 planes Y0[(r D + d) B0 + c] by this work-group
+// alone (fixed order, no atomics).
+__global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
   extern __shared__ float2 lds[];
-  __shared__ double red[16];
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t sel[2];
-  for (int li = blockIdx.x; li < c.ntree; li += gridDim.x) {
+  for (int item = blockIdx.x; item < c.l0_items; item += gridDim.x) {
+    const int li = find_owner(c.l0_pre, c.ntree, item);
     const int s = c.tree_list[li];
+    const int r = item - c.l0_pre[li];
     const SigDesc &d = c.desc[s];
     const float2 *__restrict__ x = io_of(c, s).x;
     const int64_t N = d.N;
     const int lb = d.log2B0;
     const int64_t B = d.B0;
     const int64_t L = N >> lb;
-    const int n = d.n;
-    float2 *Y0 = c.A.y0 + d.y0_off;
-    double psum = 0.0;
+    const int D = d.D;
+    const int lgs = lb < split_lg(D) ? lb : split_lg(D);
+    const int64_t Bs = (int64_t)1 << lgs;
+    const int P = (int)(B >> lgs);
     const float inv = 1.0f / (float)B;
-    for (int i = 0; i < n; i++) {
-      const uint64_t tau = tau_of(d, i);
-      for (int64_t m = threadIdx.x; m < B; m += blockDim.x) {
-        const uint64_t pos = ((uint64_t)m * (uint64_t)L + tau) & (uint64_t)(N - 1);
-        lds[bitrev((uint32_t)m, lb)] = x[pos];
-      }
+    float2 *Y0 = c.A.y0 + d.y0_off + (int64_t)r * D * B;
+    for (int p = 0; p < P; p++) {
+      gather_delays(lds, x, Bs, lgs, (uint64_t)L, (uint64_t)P, (uint64_t)p, d.shift[r],
+                    (uint64_t)(N - 1), D);
       __syncthreads();
-      fft_lds(lds, lb, c.A.tw);
-      for (int64_t m = threadIdx.x; m < B; m += blockDim.x) {
-        const float2 v = make_float2(lds[m].x * inv, lds[m].y * inv);
-        Y0[(int64_t)i * B + m] = v;
-        psum += (double)v.x * v.x + (double)v.y * v.y;
-      }
-      __syncthreads();
-    }
-    const double sref2 = block_sum_d(psum, red) / (double)(n * B);
-    double nv = d.noise_var;
-    if (d.mode == SFFT_NOISY && !(nv > 0.0)) {
-      const float q = select_kth_power(Y0, (int64_t)n * B, (float)B, d.noise_at, hist, sel);
-      nv = (double)q / d.noise_p_den;
-    }
-    for (int64_t base = 0; base < B; base += blockDim.x) {
-      const int64_t cc = base + threadIdx.x;
-      const bool valid = cc < B;
-      Verdict v;
-      v.cls = kZero;
-      double2 Y[NMAX];
-#pragma unroll
-      for (int i = 0; i < NMAX; i++) Y[i] = make_double2(0.0, 0.0);
-      if (valid) {
-#pragma unroll
-        for (int i = 0; i < NMAX; i++)
-          if (i < n) Y[i] = to_d(Y0[(int64_t)i * B + cc]);
-        v = classify<NMAX>(Y, d, n, d.R, cc, B, sref2, nv);
-      }
-      const bool single = valid && v.cls == kSingle;
-      const int fs = wave_append(&c.st[s].found, single);
-      if (single) push_found(c, s, d, fs, v.f, v.a);
-      const bool multi = valid && v.cls == kMulti;
-      const bool open = multi && L >= 2 && d.max_levels >= 1;
-      if (multi && !open) atomicOr(&c.st[s].flags, 1);
-      const int ms = wave_append(&c.st[s].multi[0], open);
-      if (open) {
-        if (ms < d.multi_cap) {
-          const int64_t slot = d.multi_off + ms;
-          c.A.multi_c[0][slot] = cc;
-#pragma unroll
-          for (int i = 0; i < NMAX; i++)
-            if (i < n) {
-              c.A.multi_y[0][slot * c.nmax + i] = make_float2((float)Y[i].x, (float)Y[i].y);
-              c.A.multi_z[0][slot * c.nmax + i] = make_double2(0.0, 0.0);
-            }
-          if (d.jump_L > 0 && L <= d.jump_L)
-            for (int t = 0; t < L; t++) c.A.jacc[slot * kJumpMax + t] = make_double2(0.0, 0.0);
-        } else {
-          atomicOr(&c.st[s].flags, 3);
+      for (int dl = 0; dl < D; dl++) fft_lds(lds + (int64_t)dl * Bs, lgs, c.A.tw);
+      for (int64_t cc = threadIdx.x; cc < B; cc += blockDim.x) {
+        float2 w = make_float2(inv, 0.f);
+        if (p > 0) {
+          const float2 u = unit_f(((uint64_t)cc * (uint64_t)p) & (uint64_t)(B - 1), (uint64_t)B);
+          w = make_float2(u.x * inv, u.y * inv);
+        }
+        for (int dl = 0; dl < D; dl++) {
+          const float2 v = cmulf(lds[(int64_t)dl * Bs + (cc & (Bs - 1))], w);
+          float2 *o = Y0 + (int64_t)dl * B + cc;
+          if (p == 0) *o = v;
+          else *o = make_float2(o->x + v.x, o->y + v.y);
         }
       }
+      __syncthreads();
+    }
+  }
+}
+
+// Level-0 statistics of every tree signal: mean bucket power and, in noisy
+// mode, the noise variance from a quantile of B0 |Yhat|^2.
+__global__ __launch_bounds__(kThreads) void k_level0_stats(LaunchCtx c) {
+  __shared__ double red[16];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t sel[2];
+  for (int li = blockIdx.x; li < c.ntree; li += gridDim.x) {
+    const int s = c.tree_list[li];
+    const SigDesc &d = c.desc[s];
+    const int64_t cnt = (int64_t)d.n * d.B0;
+    const float2 *Y0 = c.A.y0 + d.y0_off;
+    double psum = 0.0;
+    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
+      const float2 v = Y0[i];
+      psum += (double)v.x * v.x + (double)v.y * v.y;
+    }
+    const double sref2 = block_sum_d(psum, red) / (double)cnt;
+    double nv = d.noise_var;
+    if (d.mode == SFFT_NOISY && !(nv > 0.0)) {
+      const float q = select_kth_power(Y0, cnt, (float)d.B0, d.noise_at, hist, sel);
+      nv = (double)q / d.noise_p_den;
     }
     if (threadIdx.x == 0) {
       c.st[s].sref2 = sref2;
       c.st[s].noise_var = nv;
-      c.st[s].samples = (int64_t)n * B;
+      c.st[s].samples = cnt;
       c.st[s].level_mask = 1ull;
       c.st[s].levels = 0;
     }
     __syncthreads();
+  }
+}
+
+// Classification of the B0 level-0 classes (Sect. 3.2, Subproblems 1-2):
+// item = (signal, 256 classes); single-tons and multi-tons are compacted by
+// wave ballot + prefix, one atomic per wave and list.
+template <int NMAX>
+__global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
+  for (int item = blockIdx.x; item < c.l0c_items; item += gridDim.x) {
+    const int li = find_owner(c.l0c_pre, c.ntree, item);
+    const int s = c.tree_list[li];
+    const SigDesc &d = c.desc[s];
+    const int64_t B = d.B0;
+    const int64_t L = d.N >> d.log2B0;
+    const int n = d.n;
+    const float2 *Y0 = c.A.y0 + d.y0_off;
+    const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
+    const int64_t cc = (int64_t)(item - c.l0c_pre[li]) * kThreads + threadIdx.x;
+    const bool valid = cc < B;
+    Verdict v;
+    v.cls = kZero;
+    double2 Y[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; i++) Y[i] = make_double2(0.0, 0.0);
+    if (valid) {
+#pragma unroll
+      for (int i = 0; i < NMAX; i++)
+        if (i < n) Y[i] = to_d(Y0[(int64_t)i * B + cc]);
+      v = classify<NMAX>(Y, d, n, d.R, cc, B, sref2, nv);
+    }
+    const bool single = valid && v.cls == kSingle;
+    const int fs = wave_append(&c.st[s].found, single);
+    if (single) push_found(c, s, d, fs, v.f, v.a);
+    const bool multi = valid && v.cls == kMulti;
+    const bool open = multi && L >= 2 && d.max_levels >= 1;
+    if (multi && !open) atomicOr(&c.st[s].flags, 1);
+    const int ms = wave_append(&c.st[s].multi[0], open);
+    if (open) {
+      if (ms < d.multi_cap) {
+        const int64_t slot = d.multi_off + ms;
+        c.A.multi_c[0][slot] = cc;
+#pragma unroll
+        for (int i = 0; i < NMAX; i++)
+          if (i < n) {
+            c.A.multi_y[0][slot * c.nmax + i] = make_float2((float)Y[i].x, (float)Y[i].y);
+            c.A.multi_z[0][slot * c.nmax + i] = make_double2(0.0, 0.0);
+          }
+        if (d.jump_L > 0 && L <= d.jump_L)
+          for (int t = 0; t < L; t++) c.A.jacc[slot * kJumpMax + t] = make_double2(0.0, 0.0);
+      } else {
+        atomicOr(&c.st[s].flags, 3);
+      }
+    }
   }
 }
 
@@ -507,7 +602,7 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
       for (int dl = 0; dl < D; dl++) {
         for (int64_t m = threadIdx.x; m < B; m += blockDim.x) {
           const uint64_t pos = ((uint64_t)m * (uint64_t)L + (uint64_t)dl) % (uint64_t)N;
-          lds[lb >= 0 ? (int64_t)bitrev((uint32_t)m, lb) : m] = x[pos];
+          lds[lb >= 0 ? (int64_t)bitrev((uint32_t)m, lb) : m] = ldg(x + pos);
         }
         __syncthreads();
         float2 res[kDirectMax / kThreads];
@@ -708,7 +803,8 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
             cnt[4] = m;
             c.st[s].samples += d.N;
           } else {
-            if (Bp <= kFftMax || m >= kSplitMinBins) cnt[0] = d.R * (int)(Bp > kFftMax ? Bp / kFftMax : 1);
+            const int64_t Bsmax = (int64_t)1 << split_lg(d.D);
+            if (Bp <= Bsmax || m >= kSplitMinBins) cnt[0] = d.R * (int)(Bp > Bsmax ? Bp / Bsmax : 1);
             else cnt[1] = d.R * (int)((Bp + kChunk - 1) / kChunk);
             cnt[2] = 2 * m;
             c.st[s].samples += (int64_t)d.n * Bp;
@@ -749,36 +845,35 @@ __global__ __launch_bounds__(kThreads) void k_expand_fft(LaunchCtx c, int level)
     const int lb = d.log2B0 + level - 1;
     const int64_t Bp = (int64_t)1 << lb;
     const int64_t Lp = N >> lb;
-    const int lgs = lb < kLog2FftMax ? lb : kLog2FftMax;
+    const int D = d.D;
+    const int lgs = lb < split_lg(D) ? lb : split_lg(D);
     const int64_t Bs = (int64_t)1 << lgs;
     const int P = (int)(Bp >> lgs);
     const int r = rem / P, p = rem % P;
     int m_s = c.st[s].multi[par];
     if (m_s > d.multi_cap) m_s = d.multi_cap;
-    for (int dl = 0; dl < d.D; dl++) {
-      const uint64_t tau = (d.shift[r] + (uint64_t)dl + (uint64_t)(Lp >> 1)) & (uint64_t)(N - 1);
-      for (int64_t m = threadIdx.x; m < Bs; m += blockDim.x) {
-        const uint64_t pos = ((uint64_t)(m * P + p) * (uint64_t)Lp + tau) & (uint64_t)(N - 1);
-        lds[bitrev((uint32_t)m, lgs)] = x[pos];
-      }
-      __syncthreads();
-      fft_lds(lds, lgs, c.A.tw);
-      for (int j = threadIdx.x; j < m_s; j += blockDim.x) {
-        const int64_t slot = d.multi_off + j;
-        const uint64_t cc = (uint64_t)c.A.multi_c[par][slot];
-        double2 v = to_d(lds[cc & (uint64_t)(Bs - 1)]);
-        double *zz = (double *)&c.A.multi_z[par][slot * c.nmax + r * d.D + dl];
+    const uint64_t tau0 = (d.shift[r] + (uint64_t)(Lp >> 1)) & (uint64_t)(N - 1);
+    gather_delays(lds, x, Bs, lgs, (uint64_t)Lp, (uint64_t)P, (uint64_t)p, tau0, (uint64_t)(N - 1), D);
+    __syncthreads();
+    for (int dl = 0; dl < D; dl++) fft_lds(lds + (int64_t)dl * Bs, lgs, c.A.tw);
+    for (int j = threadIdx.x; j < m_s; j += blockDim.x) {
+      const int64_t slot = d.multi_off + j;
+      const uint64_t cc = (uint64_t)c.A.multi_c[par][slot];
+      double2 w = make_double2(1.0, 0.0);
+      if (P > 1) w = unit_d((cc * (uint64_t)p) & (uint64_t)(Bp - 1), (uint64_t)Bp, -1);
+      for (int dl = 0; dl < D; dl++) {
+        const double2 v = cmul(to_d(lds[(int64_t)dl * Bs + (cc & (uint64_t)(Bs - 1))]), w);
+        double *zz = (double *)&c.A.multi_z[par][slot * c.nmax + r * D + dl];
         if (P == 1) {
           zz[0] = v.x;
           zz[1] = v.y;
         } else {
-          v = cmul(v, unit_d((cc * (uint64_t)p) & (uint64_t)(Bp - 1), (uint64_t)Bp, -1));
           atomicAdd(zz, v.x);
           atomicAdd(zz + 1, v.y);
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
   }
 }
 
@@ -815,7 +910,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_direct(LaunchCtx c, int lev
 #pragma unroll
       for (int dl = 0; dl < kMaxD; dl++) {
         z[q][dl] = make_float2(0.f, 0.f);
-        if (dl < D && m < Bp) z[q][dl] = x[(p0 + (uint64_t)dl) & (uint64_t)(N - 1)];
+        if (dl < D && m < Bp) z[q][dl] = ldg(x + ((p0 + (uint64_t)dl) & (uint64_t)(N - 1)));
       }
     }
     for (int j = 0; j < m_s; j++) {
@@ -952,15 +1047,21 @@ __device__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__
     __syncthreads();
     const int ne = nb << lgL;
     const float2 *xb = x + ((row0 + b0) << lgL);
-#pragma unroll 8
-    for (int e = threadIdx.x; e < ne; e += kThreads) {
-      const float2 v = xb[e];
-      const int rr = e >> lgL;
+    gu64 *xg = (gu64 *)xb;
+    for (int e0 = threadIdx.x; e0 < ne; e0 += 8 * kThreads) {
+      float2 v[8];
 #pragma unroll
-      for (int q = 0; q < NQ; q++) {
-        const float2 w = T[q * kJumpBlockRows + rr];
-        acc[q].x += v.x * w.x - v.y * w.y;
-        acc[q].y += v.x * w.y + v.y * w.x;
+      for (int u = 0; u < 8; u++) {
+        const int e = e0 + u * kThreads;
+        v[u] = ldg_at(xg, (uint64_t)(e < ne ? e : ne - 1));   // rows past nb are skipped below
+      }
+#pragma unroll
+      for (int u = 0; u < 8; u++) {
+        const int rr = (e0 + u * kThreads) >> lgL;
+        if (rr < nb) {
+#pragma unroll
+          for (int q = 0; q < NQ; q++) cmac(acc[q], v[u], T[q * kJumpBlockRows + rr]);
+        }
       }
     }
     __syncthreads();
@@ -1264,13 +1365,18 @@ hipError_t launch_reset(const LaunchCtx &c, hipStream_t s) {
 hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
   const int nm = nmax_bucket(c.nmax);
   if (c.ntree > 0) {
-    const int grid = c.ntree < 4096 ? c.ntree : 4096;
-    const size_t lds = sizeof(float2) * (size_t)c.max_B0;
-    if (nm == 8) hipLaunchKernelGGL(k_level0_tree<8>, dim3(grid), dim3(kThreads), lds, s, c);
-    else if (nm == 16) hipLaunchKernelGGL(k_level0_tree<16>, dim3(grid), dim3(kThreads), lds, s, c);
-    else hipLaunchKernelGGL(k_level0_tree<64>, dim3(grid), dim3(kThreads), lds, s, c);
+    const size_t lds = 64 * 1024;
+    hipLaunchKernelGGL(k_level0_fft, dim3(c.l0_items < 8192 ? c.l0_items : 8192), dim3(kThreads),
+                       lds, s, c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_level0_stats, dim3(c.ntree < 4096 ? c.ntree : 4096), dim3(kThreads), 0, s, c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int g = c.l0c_items < 8192 ? c.l0c_items : 8192;
+    if (nm == 8) hipLaunchKernelGGL(k_level0_classify<8>, dim3(g), dim3(kThreads), 0, s, c);
+    else if (nm == 16) hipLaunchKernelGGL(k_level0_classify<16>, dim3(g), dim3(kThreads), 0, s, c);
+    else hipLaunchKernelGGL(k_level0_classify<64>, dim3(g), dim3(kThreads), 0, s, c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (c.nffast > 0) {
     const int grid = c.nffast < 4096 ? c.nffast : 4096;
@@ -1290,7 +1396,7 @@ hipError_t launch_sched(const LaunchCtx &c, int level, hipStream_t s) {
 }
 
 hipError_t launch_expand_fft(const LaunchCtx &c, int level, int grid, hipStream_t s) {
-  const size_t lds = sizeof(float2) * (size_t)kFftMax;
+  const size_t lds = 64 * 1024;
   hipLaunchKernelGGL(k_expand_fft, dim3(grid), dim3(kThreads), lds, s, c, level);
   return hipGetLastError();
 }

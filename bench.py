@@ -54,13 +54,16 @@ def kernel_bytes(name, level, plans, stats):
         if name == "k_level0":
             tot += n * inf.B0 * 8
         elif name == "k_jump_pass" and level >= 1:
-            if (st["level_mask"] >> level) & 1 and (inf.N >> (ilog2(inf.B0) + level - 1)) <= inf.jump_L:
+            # a signal's dense pass runs once, at the deepest level it opened
+            deepest = int(st["level_mask"]).bit_length() - 1
+            if deepest == level and (inf.N >> (ilog2(inf.B0) + level - 1)) <= inf.jump_L:
                 tot += inf.N * 8
         elif name in ("k_expand_fft", "k_expand_direct") and level >= 1:
             if not (st["level_mask"] >> level) & 1:
                 continue
             bp = inf.B0 << (level - 1)
-            if inf.jump_L > 0 and (inf.N // bp) <= inf.jump_L:
+            deepest = int(st["level_mask"]).bit_length() - 1
+            if inf.jump_L > 0 and (inf.N // bp) <= inf.jump_L and level == deepest:
                 continue
             # B' <= 8192: one LDS FFT; larger B' uses split LDS FFTs (k_expand_fft)
             # whenever a signal has >= 4 parents, which the headline always has there
@@ -78,6 +81,8 @@ def main():
     ap.add_argument("--plain", type=int, default=256, help="signals in the plain pass")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--jump-L", type=int, default=None,
+                    help="override the plans' subtree-resolution stride (0 = level by level)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -109,7 +114,8 @@ def main():
     specs = [siggen.make_spec(N, K, s) for s in seeds]
     xs = [siggen.synth_torch(sp, dev) for sp in specs]
     torch.cuda.synchronize()
-    plans = [sfft.Plan(N, K, R, D, seed=s, B0=B0) for s in seeds]
+    extra = {} if args.jump_L is None else {"jump_L": args.jump_L}
+    plans = [sfft.Plan(N, K, R, D, seed=s, B0=B0, **extra) for s in seeds]
     batch = sfft.Batch(plans, xs)
 
     # ---------------------------------------------------------------- batched

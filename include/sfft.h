@@ -93,7 +93,7 @@ typedef struct {
   int64_t stage_B[SFFT_MAX_STAGES];
   int32_t max_peel_rounds; /* FFAST: cap on peeling rounds (default 64) */
   int32_t jump_L;          /* tree: once a level's stride L' <= jump_L (a power of two
-                              <= 64), resolve each open class's whole subtree from
+                              <= 128), resolve each open class's whole subtree from
                               its L' coefficients, measured by one dense pass over x;
                               every later level's class vectors are the same linear
                               functionals of x as the level-by-level gathers.

@@ -293,7 +293,7 @@ struct BatchCtx {
     int last = 0;
     for (int s = 0; s < nsig; s++)
       if (desc[s].kind == SFFT_KIND_TREE)
-        last = std::max(last, std::min(desc[s].max_levels, jump_level(desc[s])));
+        last = std::max(last, std::min(desc[s].max_levels, jump_level(desc[s]) + 1));
     (void)maxLevels;
     for (int l = 1; l <= last; l++) {
       LevelLaunch L{};
@@ -302,13 +302,13 @@ struct BatchCtx {
         const SigDesc &d = desc[s];
         if (d.kind != SFFT_KIND_TREE || l > d.max_levels) continue;
         const int jl = jump_level(d);
-        if (l > jl) continue;
+        if (l > jl + 1) continue;
         const int64_t Bp = d.B0 << (l - 1);
-        if (l == jl) {
+        if (l >= jl) {  // the dense pass may run at jl (few classes) and runs at jl + 1
           nj += (Bp + kJumpItemRows - 1) / kJumpItemRows;
           nr += d.multi_cap;
-          continue;
         }
+        if (l > jl) continue;
         const int64_t Bsmax = int64_t(1) << split_lg(d.D);
         if (Bp <= Bsmax) {
           nf += d.R;

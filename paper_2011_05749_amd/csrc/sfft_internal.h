@@ -18,9 +18,11 @@ constexpr int kPerThread = kChunk / kThreads;
 constexpr int kMaxD = 4;             // delays handled by the direct partial-sum kernel
 constexpr int kMaxMeas = 64;         // rounds x delays per class vector
 constexpr int kMaxFfastBuckets = 4096;
-constexpr int kJumpMax = 64;         // largest stride L' resolved by the dense pass
-constexpr int kJumpItemRows = 2048;  // rows of L' elements per dense-pass work item
-constexpr int kJumpBlockRows = 512;  // rows whose twiddles share one LDS table
+constexpr int kJumpMax = 128;        // largest stride L' resolved by the dense pass
+constexpr int kJumpItemRows = 4096;  // rows of L' elements per dense-pass work item
+constexpr int kJumpBlockRows = 512;  // rows whose twiddles share one LDS table (L' < 32)
+constexpr int kJumpMfmaRows = 256;   // rows per LDS twiddle table on the MFMA path (L' >= 32)
+constexpr int kJumpMfmaClasses = 16; // classes per MFMA pass (32 output rows: re, im)
 constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses split FFTs
 
 // log2 of the sub-FFT size used when the D delays of a sample are held in

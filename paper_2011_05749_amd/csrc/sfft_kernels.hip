@@ -797,7 +797,11 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
         const int64_t Bp = (int64_t)1 << lb;
         const int64_t Lp = d.N >> lb;
         if (m > 0) {
-          const bool jump = d.jump_L > 0 && Lp <= d.jump_L;
+          // a dense pass over x serves a bounded number of open classes: at the
+          // first stride <= jump_L it is taken when they are at most
+          // kJumpMfmaClasses, one level later always
+          const bool jump = d.jump_L > 0 && Lp <= d.jump_L &&
+                            (m <= kJumpMfmaClasses || 2 * Lp <= d.jump_L);
           if (jump) {
             cnt[3] = (int)((Bp + kJumpItemRows - 1) / kJumpItemRows);
             cnt[4] = m;
@@ -1091,9 +1095,109 @@ __device__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__
   }
 }
 
+// MFMA form of the dense pass for L' = 32 NT (NT = 1, 2, 4): the coefficients
+// of up to 16 classes are one complex product M (classes x L') += W (classes
+// x rows) X (rows x L'), written as a real product with 32 output rows (re,
+// im of each class) and K = 2 per row (re, im of x):
+//   [Re M_c]   [ Re W  -Im W ] [Re X]
+//   [Im M_c] = [ Im W   Re W ] [Im X]
+// and fed to v_mfma_f32_32x32x2f32, one instruction per row and 32 columns.
+// Lane l supplies A[l % 32][l / 32] and B[l / 32][l % 32]; accumulator
+// register r of lane l holds row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int NT>
+__device__ void jump_rows_mfma(const LaunchCtx &c, const float2 *__restrict__ x, int64_t row0,
+                               int nrows, int lgL, uint64_t Bp, const uint64_t *cls /* LDS */, int nq,
+                               float *TA, float *red, int64_t slot0) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, k = lane >> 5;
+  floatx16 acc[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; nt++)
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[nt][r] = 0.f;
+  // lane l supplies B[k][m] = (k ? Im : Re) x[row][32 nt + m]: one float per lane,
+  // 256 contiguous bytes per wave and row
+  typedef __attribute__((address_space(1))) const float gf32;
+  gf32 *xs = (gf32 *)x;
+  for (int b0 = 0; b0 < nrows; b0 += kJumpMfmaRows) {
+    const int nb = (nrows - b0) < kJumpMfmaRows ? (nrows - b0) : kJumpMfmaRows;
+    // A operands in lane order: TA[rr][2 mm + kk], mm = 2 q + o
+    for (int u = threadIdx.x; u < kJumpMfmaRows * kJumpMfmaClasses; u += kThreads) {
+      const int rr = u / kJumpMfmaClasses, q = u % kJumpMfmaClasses;
+      float2 v = make_float2(0.f, 0.f);
+      if (rr < nb && q < nq) v = unit_f((cls[q] * (uint64_t)(row0 + b0 + rr)) & (Bp - 1), Bp);
+      float *t = TA + rr * 64 + q * 4;
+      t[0] = v.x;   // o = 0, k = 0:  Re W
+      t[1] = -v.y;  // o = 0, k = 1: -Im W
+      t[2] = v.y;   // o = 1, k = 0:  Im W
+      t[3] = v.x;   // o = 1, k = 1:  Re W
+    }
+    __syncthreads();
+    // wave w takes rows w, w + 4, ...; the loads of the next four rows are in
+    // flight while the MFMAs of the current four run
+    auto load4 = [&](int rr0, float (&bv)[4][NT]) {
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int rr = rr0 + 4 * u;
+        const uint64_t rg = (uint64_t)(row0 + b0 + (rr < nb ? rr : nb - 1));
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++)
+          bv[u][nt] = xs[(((rg << lgL) + (uint64_t)(nt * 32 + m)) << 1) + (uint64_t)k];
+      }
+    };
+    float bcur[4][NT], bnxt[4][NT];
+    load4(w, bcur);
+    for (int rr0 = w; rr0 < nb; rr0 += 16) {
+      if (rr0 + 16 < nb) load4(rr0 + 16, bnxt);
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int rr = rr0 + 4 * u;
+        if (rr < nb) {
+          const float a = TA[rr * 64 + 2 * m + k];
+#pragma unroll
+          for (int nt = 0; nt < NT; nt++)
+            acc[nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bcur[u][nt], acc[nt], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int nt = 0; nt < NT; nt++) bcur[u][nt] = bnxt[u][nt];
+    }
+    __syncthreads();
+  }
+  // sum the four waves' tiles in LDS, then one FP64 atomic per (class, re|im, t)
+#pragma unroll
+  for (int nt = 0; nt < NT; nt++) {
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      const int row = 8 * (r >> 2) + 4 * k + (r & 3);
+      red[(w * 32 + row) * 32 + m] = acc[nt][r];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 32 * 32; e += kThreads) {
+      const int row = e >> 5, col = e & 31;
+      const float v = red[row * 32 + col] + red[(32 + row) * 32 + col] +
+                      red[(64 + row) * 32 + col] + red[(96 + row) * 32 + col];
+      const int q = row >> 1;
+      if (q < nq) {
+        double *a = (double *)&c.A.jacc[(slot0 + q) * kJumpMax + nt * 32 + col];
+        atomicAdd(a + (row & 1), (double)v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) {
-  __shared__ float2 T[8 * kJumpBlockRows];
-  __shared__ float2 red[kThreads / 64][64];
+  // twiddle table (64 KiB: VALU path 8 classes x 512 rows of complex64, MFMA
+  // path 256 rows x 64 A-operand floats); the MFMA path's 16 KiB reduction
+  // scratch reuses it after the row loop, the VALU path's 2 KiB sits past it
+  __shared__ float2 T[8192];
+  __shared__ uint64_t cls[kJumpMfmaClasses];
+  float *red = (float *)(T + 4096);
   const int par = (level - 1) & 1;
   const int np = c.nsig + 1;
   const int32_t *pj = c.A.pre + 3 * np;
@@ -1110,27 +1214,46 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
     if (m_s > d.multi_cap) m_s = d.multi_cap;
     const int64_t row0 = (int64_t)ch * kJumpItemRows;
     const int nrows = (int)((int64_t)Bp - row0 < kJumpItemRows ? (int64_t)Bp - row0 : kJumpItemRows);
-    for (int j0 = 0; j0 < m_s; j0 += 8) {
-      const int nq = (m_s - j0) < 8 ? (m_s - j0) : 8;
-      uint64_t cls[8];
-#pragma unroll
-      for (int q = 0; q < 8; q++) cls[q] = q < nq ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + q] : 0;
-      const int64_t slot0 = d.multi_off + j0;
-      switch (nq) {
-        case 1: jump_rows<1>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
-        case 2: jump_rows<2>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
-        case 3: jump_rows<3>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
-        case 4: jump_rows<4>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
-        case 5: jump_rows<5>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
-        case 6: jump_rows<6>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
-        case 7: jump_rows<7>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
-        default: jump_rows<8>(c, d, x, row0, nrows, lgL, Bp, cls, T, red, slot0); break;
+    // L' <= 64: one complex FMA per element and class on the VALU, eight
+    // classes per pass (measured faster than the MFMA form at these widths);
+    // L' = 128: the contraction on the matrix cores, sixteen classes per pass
+    if (lgL >= 7) {
+      for (int j0 = 0; j0 < m_s; j0 += kJumpMfmaClasses) {
+        const int nq = (m_s - j0) < kJumpMfmaClasses ? (m_s - j0) : kJumpMfmaClasses;
+        if (threadIdx.x < kJumpMfmaClasses)
+          cls[threadIdx.x] = (int)threadIdx.x < nq ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + threadIdx.x] : 0;
+        __syncthreads();
+        const int64_t slot0 = d.multi_off + j0;
+        float *TA = (float *)T;
+        if (lgL == 5) jump_rows_mfma<1>(c, x, row0, nrows, lgL, Bp, cls, nq, TA, TA, slot0);
+        else if (lgL == 6) jump_rows_mfma<2>(c, x, row0, nrows, lgL, Bp, cls, nq, TA, TA, slot0);
+        else jump_rows_mfma<4>(c, x, row0, nrows, lgL, Bp, cls, nq, TA, TA, slot0);
+      }
+    } else {
+      float2 (*redv)[64] = (float2 (*)[64])red;
+      for (int j0 = 0; j0 < m_s; j0 += 8) {
+        const int nq = (m_s - j0) < 8 ? (m_s - j0) : 8;
+        if (threadIdx.x < 8)
+          cls[threadIdx.x] = (int)threadIdx.x < nq ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + threadIdx.x] : 0;
+        __syncthreads();
+        const int64_t slot0 = d.multi_off + j0;
+        switch (nq) {
+          case 1: jump_rows<1>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 2: jump_rows<2>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 3: jump_rows<3>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 4: jump_rows<4>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 5: jump_rows<5>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 6: jump_rows<6>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 7: jump_rows<7>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          default: jump_rows<8>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+        }
       }
     }
   }
 }
 
-// Subtree resolution of one open class c (one wave): its L' frequencies
+// Subtree resolution of one open class c (one work-group of kJumpMax
+// threads, thread k owning frequency k at first and class k of a depth after): its L' frequencies
 // f_k = c + k B' have the values xhat_{f_k} = (1/L') sum_t M_c(t)/B'
 // e^{-2 pi i f_k t / N}; the class vector of any descendant class at any
 // deeper level is the sum, over the frequencies it holds, of
@@ -1138,7 +1261,7 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
 // level's gathered buckets -- so the level-by-level classification of the
 // tree search (Sect. 3.3) runs on these vectors.
 template <int NMAX>
-__global__ __launch_bounds__(64) void k_jump_resolve(LaunchCtx c, int level) {
+__global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int level) {
   __shared__ double2 V[kJumpMax][NMAX];
   __shared__ double2 Ms[kJumpMax];
   __shared__ int open_cur[kJumpMax], open_nxt[kJumpMax];
@@ -1413,9 +1536,9 @@ hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t
 
 hipError_t launch_jump_resolve(const LaunchCtx &c, int level, int grid, hipStream_t s) {
   const int nm = nmax_bucket(c.nmax);
-  if (nm == 8) hipLaunchKernelGGL(k_jump_resolve<8>, dim3(grid), dim3(64), 0, s, c, level);
-  else if (nm == 16) hipLaunchKernelGGL(k_jump_resolve<16>, dim3(grid), dim3(64), 0, s, c, level);
-  else hipLaunchKernelGGL(k_jump_resolve<64>, dim3(grid), dim3(64), 0, s, c, level);
+  if (nm == 8) hipLaunchKernelGGL(k_jump_resolve<8>, dim3(grid), dim3(kJumpMax), 0, s, c, level);
+  else if (nm == 16) hipLaunchKernelGGL(k_jump_resolve<16>, dim3(grid), dim3(kJumpMax), 0, s, c, level);
+  else hipLaunchKernelGGL(k_jump_resolve<64>, dim3(grid), dim3(kJumpMax), 0, s, c, level);
   return hipGetLastError();
 }
 

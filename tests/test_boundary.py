@@ -91,7 +91,7 @@ def test_plan_draws_match_oracle(N, K, R, seed, B0, ident):
     ((60, 4, 2, 2), {"stage_B": [7, 5]}, -1),  # stage does not divide N
     ((1024, 10, 17, 2), {}, -1),           # too many rounds
     ((1024, 10, 2, 2), {"jump_L": 48}, -1),   # subtree stride not a power of two
-    ((1024, 10, 2, 2), {"jump_L": 128}, -1),  # beyond the dense-pass width
+    ((1024, 10, 2, 2), {"jump_L": 256}, -1),  # beyond the dense-pass width
 ])
 def test_plan_validation(args, kw, code):
     with pytest.raises(sfft.SfftError) as e:

@@ -112,7 +112,7 @@ def test_ffast_n20_example(sfft, D):
 
 
 # ------------------------------------------------------------ tree search (a7)
-@pytest.mark.parametrize("jump", [0, 64, 8])
+@pytest.mark.parametrize("jump", [0, 8, 32, 64, 128])
 @pytest.mark.parametrize("N,K,R,B0,seed,ident", [
     (2 ** 12, 8, 1, 8, 1, 1), (2 ** 14, 64, 2, 128, 2, 0), (2 ** 16, 300, 4, 512, 4, 0),
     (2 ** 16, 100, 4, 256, 3, 0), (2 ** 10, 1, 1, 1, 5, 1), (2 ** 13, 7, 3, 16, 6, 0),
@@ -130,7 +130,7 @@ def test_tree_exact(sfft, N, K, R, B0, seed, ident, jump):
     np.testing.assert_array_equal(g[0], siggen.truth(sp)[0])
 
 
-@pytest.mark.parametrize("jump", [0, 64])
+@pytest.mark.parametrize("jump", [0, 16, 64, 128])
 def test_tree_worst_pair_full_depth(sfft, jump):
     N = 2 ** 12
     x = siggen.synth(siggen.make_spec(N, 2, 4, support=[0, N // 2]))
@@ -199,7 +199,7 @@ def test_determinism(sfft):
 
 
 # ------------------------------------------------------------------ noisy mode
-@pytest.mark.parametrize("jump", [0, 64])
+@pytest.mark.parametrize("jump", [0, 32, 128])
 @pytest.mark.parametrize("window,seed", [(0, 31), (64, 32)])
 def test_noisy_tree(sfft, window, seed, jump):
     N, K = 2 ** 16, 32

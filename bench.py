@@ -16,7 +16,6 @@ from __future__ import annotations
 import argparse
 import json
 import os
-import statistics
 import sys
 import time
 
@@ -70,6 +69,30 @@ def kernel_bytes(name, level, plans, stats):
             if name == "k_expand_fft":
                 tot += n * bp * 8
     return tot
+
+
+def run_plain(plans, xs, npl, K, dev, torch):
+    """One sfft_exec_async per signal on the current stream; per-solve HIP
+    event latency and overall throughput."""
+    print("bench: plain", file=sys.stderr, flush=True)
+    oi = torch.empty(K, dtype=torch.int64, device=dev)
+    ov = torch.empty(K, dtype=torch.complex64, device=dev)
+    dc = torch.zeros(1, dtype=torch.int64, device=dev)
+    ds = torch.zeros(1, dtype=torch.int32, device=dev)
+    for i in range(min(2, npl)):
+        plans[i].exec_async(xs[i], oi, ov, dc, ds)
+    torch.cuda.synchronize()
+    pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(npl)]
+    t0 = time.perf_counter()
+    for i in range(npl):
+        a, b = pev[i]
+        a.record()
+        plans[i].exec_async(xs[i], oi, ov, dc, ds)
+        b.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return npl / (t1 - t0), [a.elapsed_time(b) for a, b in pev]
 
 
 def main():
@@ -150,27 +173,10 @@ def main():
     levels = [int(s["levels"]) for s in stats]
 
     # ------------------------------------------------------------------ plain
-    print("bench: plain", file=sys.stderr, flush=True)
     npl = min(args.plain, nb)
-    oi = torch.empty(K, dtype=torch.int64, device=dev)
-    ov = torch.empty(K, dtype=torch.complex64, device=dev)
-    dc = torch.zeros(1, dtype=torch.int64, device=dev)
-    ds = torch.zeros(1, dtype=torch.int32, device=dev)
-    for i in range(min(2, npl)):
-        plans[i].exec_async(xs[i], oi, ov, dc, ds)
-    torch.cuda.synchronize()
-    pev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(npl)]
-    t0 = time.perf_counter()
-    for i in range(npl):
-        a, b = pev[i]
-        a.record()
-        plans[i].exec_async(xs[i], oi, ov, dc, ds)
-        b.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    plain_lat = [a.elapsed_time(b) for a, b in pev]
-    plain_value = npl / (t1 - t0)
+    plain_value, plain_lat = None, []
+    if npl > 0:
+        plain_value, plain_lat = run_plain(plans, xs, npl, K, dev, torch)
 
     # ------------------------------------------------ per-kernel event profile
     prof = batch.profile()
@@ -242,9 +248,10 @@ def main():
         "batched": {"value": round(value, 2), "unit": "spectra/s",
                     "batch_p50_ms": round(pct(step_ms, 0.5), 4),
                     "batch_p99_ms": round(pct(step_ms, 0.99), 4)},
-        "plain": {"value": round(plain_value, 2), "unit": "spectra/s", "signals": npl,
-                  "p50_ms": round(pct(plain_lat, 0.5), 4), "p99_ms": round(pct(plain_lat, 0.99), 4)},
-        "batched_over_plain": round(value / plain_value, 3),
+        "plain": None if plain_value is None else {
+            "value": round(plain_value, 2), "unit": "spectra/s", "signals": npl,
+            "p50_ms": round(pct(plain_lat, 0.5), 4), "p99_ms": round(pct(plain_lat, 0.99), 4)},
+        "batched_over_plain": None if plain_value is None else round(value / plain_value, 3),
         "verified": f"{ok}/{nb} signals: exact support, count K, status OK",
         "samples_per_solve": samples,
         "fraction_sampled": round(samples / N, 4),

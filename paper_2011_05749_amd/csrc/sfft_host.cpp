@@ -279,6 +279,9 @@ struct BatchCtx {
     c.l0c_pre = (const int32_t *)b_lists.p + l0c_at;
     c.l0_items = acc0;
     c.l0c_items = acc1;
+    c.any_wide_jump = 0;
+    for (int s = 0; s < nsig; s++)
+      if (desc[s].kind == SFFT_KIND_TREE && desc[s].jump_L >= 128) c.any_wide_jump = 1;
     c.nsig = nsig;
     c.ntree = (int)tree.size();
     c.nffast = (int)ffast.size();

@@ -102,6 +102,7 @@ struct LaunchCtx {
   const int32_t *l0_pre;   // prefix over tree_list of the rounds (level-0 FFT items)
   const int32_t *l0c_pre;  // prefix over tree_list of ceil(B0 / 256) (classify items)
   int32_t l0_items, l0c_items;
+  int32_t any_wide_jump;   // some signal may run the dense pass at L' = 128
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;

@@ -1191,13 +1191,15 @@ __device__ void jump_rows_mfma(const LaunchCtx &c, const float2 *__restrict__ x,
   }
 }
 
+// Dense pass, L' <= 64 (VALU form) or L' = 128 (MFMA form): two kernels so
+// that each keeps its own register budget; each takes the items of its width.
+template <bool MFMA>
 __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) {
-  // twiddle table (64 KiB: VALU path 8 classes x 512 rows of complex64, MFMA
-  // path 256 rows x 64 A-operand floats); the MFMA path's 16 KiB reduction
-  // scratch reuses it after the row loop, the VALU path's 2 KiB sits past it
-  __shared__ float2 T[8192];
+  // twiddle table (32 KiB as 8 classes x 512 rows of complex64 for the VALU
+  // form, 64 KiB as 256 rows x 64 A-operand floats for the MFMA form, whose
+  // 16 KiB reduction scratch reuses it after the row loop)
+  __shared__ float2 T[MFMA ? 8192 : 4096 + 512];
   __shared__ uint64_t cls[kJumpMfmaClasses];
-  float *red = (float *)(T + 4096);
   const int par = (level - 1) & 1;
   const int np = c.nsig + 1;
   const int32_t *pj = c.A.pre + 3 * np;
@@ -1206,37 +1208,28 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
     const int s = find_owner(pj, c.nsig, item);
     const int ch = item - pj[s];
     const SigDesc &d = c.desc[s];
-    const float2 *__restrict__ x = io_of(c, s).x;
     const int lb = d.log2B0 + level - 1;
-    const uint64_t Bp = (uint64_t)1 << lb;
     const int lgL = d.log2N - lb;
+    if ((lgL >= 7) != MFMA) continue;
+    const float2 *__restrict__ x = io_of(c, s).x;
+    const uint64_t Bp = (uint64_t)1 << lb;
     int m_s = c.st[s].multi[par];
     if (m_s > d.multi_cap) m_s = d.multi_cap;
     const int64_t row0 = (int64_t)ch * kJumpItemRows;
     const int nrows = (int)((int64_t)Bp - row0 < kJumpItemRows ? (int64_t)Bp - row0 : kJumpItemRows);
-    // L' <= 64: one complex FMA per element and class on the VALU, eight
-    // classes per pass (measured faster than the MFMA form at these widths);
-    // L' = 128: the contraction on the matrix cores, sixteen classes per pass
-    if (lgL >= 7) {
-      for (int j0 = 0; j0 < m_s; j0 += kJumpMfmaClasses) {
-        const int nq = (m_s - j0) < kJumpMfmaClasses ? (m_s - j0) : kJumpMfmaClasses;
-        if (threadIdx.x < kJumpMfmaClasses)
-          cls[threadIdx.x] = (int)threadIdx.x < nq ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + threadIdx.x] : 0;
-        __syncthreads();
-        const int64_t slot0 = d.multi_off + j0;
+    const int G = MFMA ? kJumpMfmaClasses : 8;
+    for (int j0 = 0; j0 < m_s; j0 += G) {
+      const int nq = (m_s - j0) < G ? (m_s - j0) : G;
+      __syncthreads();
+      if (threadIdx.x < G)
+        cls[threadIdx.x] = (int)threadIdx.x < nq ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + threadIdx.x] : 0;
+      __syncthreads();
+      const int64_t slot0 = d.multi_off + j0;
+      if constexpr (MFMA) {
         float *TA = (float *)T;
-        if (lgL == 5) jump_rows_mfma<1>(c, x, row0, nrows, lgL, Bp, cls, nq, TA, TA, slot0);
-        else if (lgL == 6) jump_rows_mfma<2>(c, x, row0, nrows, lgL, Bp, cls, nq, TA, TA, slot0);
-        else jump_rows_mfma<4>(c, x, row0, nrows, lgL, Bp, cls, nq, TA, TA, slot0);
-      }
-    } else {
-      float2 (*redv)[64] = (float2 (*)[64])red;
-      for (int j0 = 0; j0 < m_s; j0 += 8) {
-        const int nq = (m_s - j0) < 8 ? (m_s - j0) : 8;
-        if (threadIdx.x < 8)
-          cls[threadIdx.x] = (int)threadIdx.x < nq ? (uint64_t)c.A.multi_c[par][d.multi_off + j0 + threadIdx.x] : 0;
-        __syncthreads();
-        const int64_t slot0 = d.multi_off + j0;
+        jump_rows_mfma<4>(c, x, row0, nrows, lgL, Bp, cls, nq, TA, TA, slot0);
+      } else {
+        float2 (*redv)[64] = (float2 (*)[64])(T + 4096);
         switch (nq) {
           case 1: jump_rows<1>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
           case 2: jump_rows<2>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
@@ -1530,7 +1523,10 @@ hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStre
 }
 
 hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_jump_pass, dim3(grid), dim3(kThreads), 0, s, c, level);
+  hipLaunchKernelGGL(k_jump_pass<false>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !c.any_wide_jump) return e;
+  hipLaunchKernelGGL(k_jump_pass<true>, dim3(grid), dim3(kThreads), 0, s, c, level);
   return hipGetLastError();
 }
 

@@ -76,6 +76,7 @@ struct sfft_plan_s {
 namespace {
 
 constexpr int64_t kMaxN = int64_t(1) << 30;
+constexpr int32_t kBatchPrepareOnly = 1 << 16;  // internal flag of sfft_exec_batch_ex
 
 // ------------------------------------------------------------ device buffers
 struct DevBuf {
@@ -698,7 +699,9 @@ int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs, int6
   }
   LaunchCtx c = b->lc;
   c.io = (const SigIO *)b->b_io.p;
-  if (flags & SFFT_BATCH_NO_GRAPH) {
+  if (flags & kBatchPrepareOnly) {
+    // nothing launched: the caller runs the pipeline on the batch's stream
+  } else if (flags & SFFT_BATCH_NO_GRAPH) {
     if (b->launch_all(c, b->stream) != hipSuccess) return fail(SFFT_EDEVICE);
   } else {
     if (!b->gexec) {
@@ -730,9 +733,9 @@ int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
                                 int64_t *const *idx, void *const *vals, int64_t *d_counts,
                                 int32_t *d_status, int32_t n, float *ms, int32_t *kernel,
                                 int32_t cap) {
-  // make sure the batch context exists and holds these pointers
+  // make sure the batch context exists and holds these pointers (no launch)
   int32_t rc = sfft_exec_batch_ex(plans, xs, idx, vals, d_counts, d_status, n, nullptr,
-                                  SFFT_BATCH_NO_GRAPH);
+                                  SFFT_BATCH_NO_GRAPH | kBatchPrepareOnly);
   if (rc != SFFT_OK) return rc;
   std::lock_guard<std::mutex> lk(g_batch_mu);
   std::vector<const sfft_plan_s *> key(plans, plans + n);

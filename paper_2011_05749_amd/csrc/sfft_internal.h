@@ -20,7 +20,7 @@ constexpr int kMaxMeas = 64;         // rounds x delays per class vector
 constexpr int kMaxFfastBuckets = 4096;
 constexpr int kJumpMax = 128;        // largest stride L' resolved by the dense pass
 constexpr int kJumpItemRows = 4096;  // rows of L' elements per dense-pass work item
-constexpr int kJumpBlockRows = 512;  // rows whose twiddles share one LDS table (L' < 32)
+constexpr int kJumpBlockRows = 256;  // rows whose twiddles share one LDS table (VALU form)
 constexpr int kJumpMfmaRows = 256;   // rows per LDS twiddle table on the MFMA path (L' >= 32)
 constexpr int kJumpMfmaClasses = 16; // classes per MFMA pass (32 output rows: re, im)
 constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses split FFTs

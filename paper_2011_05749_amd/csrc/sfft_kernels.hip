@@ -1035,7 +1035,7 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
 // and row) and each element costs one complex multiply-add per class.
 // Item = (signal, kJumpItemRows rows); thread tid owns t = tid mod L'.
 template <int NQ>
-__device__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__restrict__ x,
+__device__ __forceinline__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__restrict__ x,
                           int64_t row0, int nrows, int lgL, uint64_t Bp, const uint64_t *cls,
                           float2 *T, float2 (*red)[64], int64_t slot0) {
   const int Lp = 1 << lgL;
@@ -1059,6 +1059,8 @@ __device__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__
         const int e = e0 + u * kThreads;
         v[u] = ldg_at(xg, (uint64_t)(e < ne ? e : ne - 1));   // rows past nb are skipped below
       }
+      // one row's twiddles live at a time: the scheduling barrier keeps the
+      // compiler from hoisting every row's LDS reads (register pressure)
 #pragma unroll
       for (int u = 0; u < 8; u++) {
         const int rr = (e0 + u * kThreads) >> lgL;
@@ -1066,6 +1068,7 @@ __device__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__
 #pragma unroll
           for (int q = 0; q < NQ; q++) cmac(acc[q], v[u], T[q * kJumpBlockRows + rr]);
         }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     __syncthreads();
@@ -1107,7 +1110,7 @@ __device__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 template <int NT>
-__device__ void jump_rows_mfma(const LaunchCtx &c, const float2 *__restrict__ x, int64_t row0,
+__device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const float2 *__restrict__ x, int64_t row0,
                                int nrows, int lgL, uint64_t Bp, const uint64_t *cls /* LDS */, int nq,
                                float *TA, float *red, int64_t slot0) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1195,7 +1198,7 @@ __device__ void jump_rows_mfma(const LaunchCtx &c, const float2 *__restrict__ x,
 // that each keeps its own register budget; each takes the items of its width.
 template <bool MFMA>
 __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) {
-  // twiddle table (32 KiB as 8 classes x 512 rows of complex64 for the VALU
+  // twiddle table (32 KiB as 16 classes x 256 rows of complex64 for the VALU
   // form, 64 KiB as 256 rows x 64 A-operand floats for the MFMA form, whose
   // 16 KiB reduction scratch reuses it after the row loop)
   __shared__ float2 T[MFMA ? 8192 : 4096 + 512];
@@ -1217,7 +1220,7 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
     if (m_s > d.multi_cap) m_s = d.multi_cap;
     const int64_t row0 = (int64_t)ch * kJumpItemRows;
     const int nrows = (int)((int64_t)Bp - row0 < kJumpItemRows ? (int64_t)Bp - row0 : kJumpItemRows);
-    const int G = MFMA ? kJumpMfmaClasses : 8;
+    const int G = kJumpMfmaClasses;
     for (int j0 = 0; j0 < m_s; j0 += G) {
       const int nq = (m_s - j0) < G ? (m_s - j0) : G;
       __syncthreads();
@@ -1238,7 +1241,15 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
           case 5: jump_rows<5>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
           case 6: jump_rows<6>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
           case 7: jump_rows<7>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          default: jump_rows<8>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 8: jump_rows<8>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 9: jump_rows<9>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 10: jump_rows<10>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 11: jump_rows<11>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 12: jump_rows<12>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 13: jump_rows<13>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 14: jump_rows<14>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 15: jump_rows<15>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          default: jump_rows<16>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
         }
       }
     }

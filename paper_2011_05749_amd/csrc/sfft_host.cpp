@@ -218,8 +218,12 @@ struct BatchCtx {
     }
     mz = mc * (int64_t)nmax;  // multi-ton vectors use the batch-wide stride nmax
     bool any_jump = false;
+    int jstride = 1;
     for (int s = 0; s < nsig; s++)
-      if (desc[s].kind == SFFT_KIND_TREE && jump_level(desc[s]) <= desc[s].max_levels) any_jump = true;
+      if (desc[s].kind == SFFT_KIND_TREE && jump_level(desc[s]) <= desc[s].max_levels) {
+        any_jump = true;
+        jstride = std::max(jstride, desc[s].jump_L);
+      }
     // longest solves first (LPT order) for the persistent level-0 launches
     std::stable_sort(tree.begin(), tree.end(), [](auto &a, auto &b) { return a.first > b.first; });
     std::stable_sort(ffast.begin(), ffast.end(), [](auto &a, auto &b) { return a.first > b.first; });
@@ -249,7 +253,7 @@ struct BatchCtx {
         !ck(b_ff.alloc(sizeof(int64_t) * (size_t)fc)) || !ck(b_fa.alloc(sizeof(double2) * (size_t)fc)) ||
         !ck(b_mc.alloc(2 * sizeof(int64_t) * (size_t)mc)) || !ck(b_my.alloc(2 * sizeof(float2) * (size_t)mz)) ||
         !ck(b_mz.alloc(2 * sizeof(double2) * (size_t)mz)) || !ck(b_pre.alloc(5 * sizeof(int32_t) * (ns + 1))) ||
-        !ck(b_jacc.alloc(sizeof(double2) * (size_t)(any_jump ? mc * kJumpMax : 1))) ||
+        !ck(b_jacc.alloc(sizeof(double2) * (size_t)(any_jump ? mc * jstride : 1))) ||
         !ck(b_out.alloc((sizeof(int64_t) + sizeof(int32_t)) * 2)))
       return SFFT_ENOMEM;
     if (hipMemcpy(b_desc.p, desc.data(), sizeof(SigDesc) * ns, hipMemcpyHostToDevice) != hipSuccess ||
@@ -280,6 +284,7 @@ struct BatchCtx {
     c.l0c_pre = (const int32_t *)b_lists.p + l0c_at;
     c.l0_items = acc0;
     c.l0c_items = acc1;
+    c.jstride = jstride;
     c.any_wide_jump = 0;
     for (int s = 0; s < nsig; s++)
       if (desc[s].kind == SFFT_KIND_TREE && desc[s].jump_L >= 128) c.any_wide_jump = 1;

@@ -86,7 +86,7 @@ struct Arena {
   double2 *multi_z[2];
   int32_t *pre;           // 5 prefix arrays of nsig+1: fft items, direct items,
                           // children, dense-pass items, subtree-resolve items
-  double2 *jacc;          // per multi-ton slot: kJumpMax dense-pass coefficients
+  double2 *jacc;          // per multi-ton slot: jstride dense-pass coefficients
   const float2 *tw;       // e^{-2 pi i k / kFftMax}, k < kFftMax
 };
 
@@ -103,6 +103,7 @@ struct LaunchCtx {
   const int32_t *l0c_pre;  // prefix over tree_list of ceil(B0 / 256) (classify items)
   int32_t l0_items, l0c_items;
   int32_t any_wide_jump;   // some signal may run the dense pass at L' = 128
+  int32_t jstride;         // dense-pass coefficients per multi-ton slot (max jump_L)
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;

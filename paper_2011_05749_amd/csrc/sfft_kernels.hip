@@ -552,7 +552,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
             c.A.multi_z[0][slot * c.nmax + i] = make_double2(0.0, 0.0);
           }
         if (d.jump_L > 0 && L <= d.jump_L)
-          for (int t = 0; t < L; t++) c.A.jacc[slot * kJumpMax + t] = make_double2(0.0, 0.0);
+          for (int t = 0; t < L; t++) c.A.jacc[slot * c.jstride + t] = make_double2(0.0, 0.0);
       } else {
         atomicOr(&c.st[s].flags, 3);
       }
@@ -1015,7 +1015,7 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
               c.A.multi_z[cur][sl * c.nmax + i] = make_double2(0.0, 0.0);
             }
           if (d.jump_L > 0 && L <= d.jump_L)
-            for (int t = 0; t < L; t++) c.A.jacc[sl * kJumpMax + t] = make_double2(0.0, 0.0);
+            for (int t = 0; t < L; t++) c.A.jacc[sl * c.jstride + t] = make_double2(0.0, 0.0);
         } else {
           atomicOr(&c.st[s].flags, 3);
         }
@@ -1090,7 +1090,7 @@ __device__ __forceinline__ void jump_rows(const LaunchCtx &c, const SigDesc &d, 
         sx += (double)red[ww][threadIdx.x].x;
         sy += (double)red[ww][threadIdx.x].y;
       }
-      double *a = (double *)&c.A.jacc[(slot0 + q) * kJumpMax + threadIdx.x];
+      double *a = (double *)&c.A.jacc[(slot0 + q) * c.jstride + threadIdx.x];
       atomicAdd(a, sx);
       atomicAdd(a + 1, sy);
     }
@@ -1186,7 +1186,7 @@ __device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const float2 
                       red[(64 + row) * 32 + col] + red[(96 + row) * 32 + col];
       const int q = row >> 1;
       if (q < nq) {
-        double *a = (double *)&c.A.jacc[(slot0 + q) * kJumpMax + nt * 32 + col];
+        double *a = (double *)&c.A.jacc[(slot0 + q) * c.jstride + nt * 32 + col];
         atomicAdd(a + (row & 1), (double)v);
       }
     }
@@ -1288,7 +1288,7 @@ __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int leve
     const int64_t cpar = c.A.multi_c[par][slot];
     const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
     if (k < Lp) {
-      const double2 a = c.A.jacc[slot * kJumpMax + k];
+      const double2 a = c.A.jacc[slot * c.jstride + k];
       Ms[k] = make_double2(a.x / (double)Bp, a.y / (double)Bp);
     }
     __syncthreads();

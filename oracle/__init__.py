@@ -21,7 +21,7 @@ _LIB = os.path.join(_HERE, "_build", "liborc.so")
 
 EXACT, NOISY = 0, 1
 TREE, FFAST = 0, 1
-ZERO, SINGLE, MULTI = 0, 1, 2
+ZERO, SINGLE, MULTI, DOUBLE = 0, 1, 2, 3
 OK, PARTIAL = 0, 1
 
 MAX_ROUNDS = 16
@@ -43,6 +43,7 @@ class Cfg(ctypes.Structure):
         ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
+        ("mpp", ctypes.c_int32),
     ]
 
 
@@ -58,6 +59,7 @@ class Trace(ctypes.Structure):
         ("sref2", ctypes.c_double), ("noise_var", ctypes.c_double),
         ("n_found", ctypes.c_int64),
         ("order", ctypes.c_int64 * 4096),
+        ("n_double", ctypes.c_int32 * MAX_LEVELS),
     ]
 
 

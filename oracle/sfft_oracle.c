@@ -1,7 +1,8 @@
 /*
  * sfft_oracle.c -- plain, slow FP64 CPU oracle of the aliasing-filter sparse
  * FFT hot path: frequency bucketization, singleton test, phase-to-index
- * location, FFAST peeling and binary-tree search, as described in
+ * location, two-ton moment preserving solve, FFAST peeling and binary-tree
+ * search, as described in
  * Li, Jiang & Chen, "On Performance of Sparse Fast Fourier Transform
  * Algorithms Using the Aliasing Filter" (2020).
  *
@@ -20,7 +21,8 @@
  * Parity status: every function below is pinned by a CPU test (aliasing
  * identity against a brute-force DFT, exact recovery of planted spectra, the
  * N=20 peeling example of Sect. 3.2, the N=64 tree example and the
- * small-support case of Sect. 3.3, Table 1 by Monte Carlo), except the
+ * small-support case of Sect. 3.3, Table 1 by Monte Carlo; the two-ton
+ * solve by the residue structure of the tree and the N=64 example), except the
  * noisy-mode thresholds (parity unpinned: the paper gives no values for T0,
  * T1; they are checked only through their noiseless limit and statistics).
  */
@@ -204,6 +206,8 @@ typedef struct {
   int cls;
   int64_t f;
   cplx a;
+  int64_t f2;   /* two-ton: the second position and value */
+  cplx a2;
 } verdict;
 
 typedef struct {
@@ -215,23 +219,27 @@ typedef struct {
   double noise_var;   /* noisy mode, time domain */
 } cls_ctx;
 
-/* phase of sum over rounds and adjacent delays of Y[d+1] conj(Y[d]) mapped
-   to u = phi N / 2 pi, snapped to the lattice c + k B (Subproblem 2, exact
-   case, with the advance-shift sign) */
-static int64_t snap_index(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
-  const orc_cfg *cf = x->c;
-  int64_t N = cf->N, L = N / B;
-  cplx P = 0;
-  for (int r = 0; r < x->rounds; r++)
-    for (int d = 0; d + 1 < cf->D; d++)
-      P += Y[r * cf->D + d + 1] * conj(Y[r * cf->D + d]);
-  double phi = atan2(cimag(P), creal(P));
+/* phase phi of a position estimate e^{2 pi i f / N} mapped to u = phi N / 2 pi
+   and snapped to the lattice c + k B of class c (Subproblem 2, exact case) */
+static int64_t lattice_of_phase(int64_t N, int64_t B, int64_t c, double phi) {
+  int64_t L = N / B;
   if (phi < 0) phi += TWO_PI;
   double u = phi * (double)N / TWO_PI;
   double kf = floor((u - (double)c) / (double)B + 0.5);
   int64_t k = (int64_t)kf % L;
   if (k < 0) k += L;
   return k;
+}
+
+/* phase of sum over rounds and adjacent delays of Y[d+1] conj(Y[d]), with the
+   advance-shift sign, snapped to the class lattice */
+static int64_t snap_index(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
+  const orc_cfg *cf = x->c;
+  cplx P = 0;
+  for (int r = 0; r < x->rounds; r++)
+    for (int d = 0; d + 1 < cf->D; d++)
+      P += Y[r * cf->D + d + 1] * conj(Y[r * cf->D + d]);
+  return lattice_of_phase(cf->N, B, c, atan2(cimag(P), creal(P)));
 }
 
 /* matched filter |sum_i Y_i e^{-2 pi i f tau_i / N}|^2 */
@@ -245,6 +253,79 @@ static double match2(const cls_ctx *x, const cplx *Y, int64_t f) {
   return creal(g) * creal(g) + cimag(g) * cimag(g);
 }
 
+/* Two-ton solve of a class that failed the singleton test: the moment
+   preserving problem of Sect. 3.1 with a = 2 (Steps 2-3, Method 1).  Within
+   round r the delays give the moments m_d = Y[r][d] = sum_j p_j z_j^d with
+   z_j = e^{2 pi i f_j / N} (p_j absorbs the round's shift), so the monic
+   polynomial z^2 + c1 z + c0 with roots z_0, z_1 (Eq. 12) satisfies
+   c0 m_d + c1 m_{d+1} = -m_{d+2} (Eq. 14) for every d <= D-3.  The equations
+   of all rounds share C = (c0, c1) and are solved together in least squares
+   (one round with D = 4 is Eq. 14 itself).  The roots of Method 1 give the
+   two positions, each snapped to the class lattice c + kB; the values are
+   the least-squares solution of the Vandermonde system (Eq. 9, Eq. 18) over
+   every measurement of the class.  Accepted when the positions differ, both
+   values clear the zero-ton level and the residual passes the single-ton
+   bound. */
+static void two_ton(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B, double T0sq,
+                    double T1sq, verdict *v) {
+  const orc_cfg *cf = x->c;
+  int64_t N = cf->N;
+  int n = x->n, D = cf->D;
+  cplx g00 = 0, g01 = 0, g11 = 0, h0 = 0, h1 = 0;
+  for (int r = 0; r < x->rounds; r++)
+    for (int d = 0; d + 2 < D; d++) {
+      cplx m0 = Y[r * D + d], m1 = Y[r * D + d + 1], rhs = -Y[r * D + d + 2];
+      g00 += conj(m0) * m0;
+      g01 += conj(m0) * m1;
+      g11 += conj(m1) * m1;
+      h0 += conj(m0) * rhs;
+      h1 += conj(m1) * rhs;
+    }
+  double det = creal(g00) * creal(g11) - (creal(g01) * creal(g01) + cimag(g01) * cimag(g01));
+  if (!(det > 1e-13 * creal(g00) * creal(g11))) return;
+  cplx c0 = (g11 * h0 - g01 * h1) / det;
+  cplx c1 = (g00 * h1 - conj(g01) * h0) / det;
+  cplx disc = csqrt(c1 * c1 - 4.0 * c0);
+  cplx z0 = (-c1 - disc) / 2.0, z1 = (-c1 + disc) / 2.0;
+  int64_t f0 = c + lattice_of_phase(N, B, c, carg(z0)) * B;
+  int64_t f1 = c + lattice_of_phase(N, B, c, carg(z1)) * B;
+  if (f0 == f1) return;
+  if (f1 < f0) {
+    int64_t t = f0;
+    f0 = f1;
+    f1 = t;
+  }
+  /* values: normal equations of the two columns e^{+2 pi i f_j tau_i / N} */
+  cplx s01 = 0, q0 = 0, q1 = 0;
+  for (int i = 0; i < n; i++) {
+    cplx e0 = unit((int64_t)mulmod((uint64_t)f0, x->tau[i], (uint64_t)N), N, +1);
+    cplx e1 = unit((int64_t)mulmod((uint64_t)f1, x->tau[i], (uint64_t)N), N, +1);
+    s01 += conj(e0) * e1;
+    q0 += conj(e0) * Y[i];
+    q1 += conj(e1) * Y[i];
+  }
+  double nn = (double)n;
+  double dv = nn * nn - (creal(s01) * creal(s01) + cimag(s01) * cimag(s01));
+  if (!(dv > 1e-9 * nn * nn)) return;
+  cplx a0 = (nn * q0 - s01 * q1) / dv;
+  cplx a1 = (nn * q1 - conj(s01) * q0) / dv;
+  if (nn * (creal(a0) * creal(a0) + cimag(a0) * cimag(a0)) <= T0sq) return;
+  if (nn * (creal(a1) * creal(a1) + cimag(a1) * cimag(a1)) <= T0sq) return;
+  double rho2 = 0;
+  for (int i = 0; i < n; i++) {
+    cplx e0 = unit((int64_t)mulmod((uint64_t)f0, x->tau[i], (uint64_t)N), N, +1);
+    cplx e1 = unit((int64_t)mulmod((uint64_t)f1, x->tau[i], (uint64_t)N), N, +1);
+    cplx e = Y[i] - a0 * e0 - a1 * e1;
+    rho2 += creal(e) * creal(e) + cimag(e) * cimag(e);
+  }
+  if (!(rho2 <= T1sq)) return;
+  v->cls = ORC_DOUBLE;
+  v->f = f0;
+  v->a = a0;
+  v->f2 = f1;
+  v->a2 = a1;
+}
+
 static verdict classify(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
   const orc_cfg *cf = x->c;
   int64_t N = cf->N, L = N / B;
@@ -253,6 +334,8 @@ static verdict classify(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
   v.cls = ORC_ZERO;
   v.f = -1;
   v.a = 0;
+  v.f2 = -1;
+  v.a2 = 0;
   double E2 = 0;
   for (int i = 0; i < n; i++) E2 += creal(Y[i]) * creal(Y[i]) + cimag(Y[i]) * cimag(Y[i]);
   double T0sq, T1sq;
@@ -307,6 +390,7 @@ static verdict classify(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
   v.f = f;
   v.a = a;
   v.cls = (rho2 <= T1sq) ? ORC_SINGLE : ORC_MULTI;
+  if (v.cls == ORC_MULTI && cf->mpp == 2) two_ton(x, Y, c, B, T0sq, T1sq, &v);
   return v;
 }
 
@@ -492,7 +576,7 @@ static int64_t solve_tree(const orc_cfg *c, const float *x, int64_t *out_idx,
     int64_t L = c->N / B;
     int64_t *next = (int64_t *)malloc(sizeof(int64_t) * (size_t)(2 * ncls + 1));
     int64_t nnext = 0;
-    int nz = 0, ns = 0, nm = 0;
+    int nz = 0, ns = 0, nm = 0, nd = 0;
     for (int64_t q = 0; q < ncls; q++) {
       verdict v = classify(&cx, Y + q * n, cls[q], B);
       if (v.cls == ORC_ZERO) {
@@ -500,6 +584,10 @@ static int64_t solve_tree(const orc_cfg *c, const float *x, int64_t *out_idx,
       } else if (v.cls == ORC_SINGLE) {
         ns++;
         found_push(&fl, v.f, v.a);
+      } else if (v.cls == ORC_DOUBLE) {
+        nd++;
+        found_push(&fl, v.f, v.a);
+        found_push(&fl, v.f2, v.a2);
       } else {
         nm++;
         if (L >= 2 && level + 1 <= c->max_levels) {
@@ -514,6 +602,7 @@ static int64_t solve_tree(const orc_cfg *c, const float *x, int64_t *out_idx,
       tr->n_zero[level] = nz;
       tr->n_single[level] = ns;
       tr->n_multi[level] = nm;
+      tr->n_double[level] = nd;
       /* nodes of the full layer holding energy: classes found non-empty here
          plus one node for each frequency resolved at a shallower level */
       tr->occupied[level] = (int32_t)(fl.n + nm);
@@ -681,6 +770,11 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
 int64_t orc_solve(const orc_cfg *c, const float *x, int64_t *out_idx,
                   double *out_val, orc_trace *tr) {
   if (tr) memset(tr, 0, sizeof(*tr));
+  /* the two-ton solve needs the tree, exact mode and at least two moment
+     equations: rounds x (delays - 2) >= 2 */
+  if (c->mpp != 0 && (c->mpp != 2 || c->kind != ORC_TREE || c->mode != ORC_EXACT ||
+                      c->R * (c->D - 2) < 2))
+    return -1;
   if (c->kind == ORC_TREE) return solve_tree(c, x, out_idx, out_val, tr);
   return solve_ffast(c, x, out_idx, out_val, tr);
 }

@@ -18,7 +18,7 @@
 
 enum { ORC_EXACT = 0, ORC_NOISY = 1 };
 enum { ORC_TREE = 0, ORC_FFAST = 1 };
-enum { ORC_ZERO = 0, ORC_SINGLE = 1, ORC_MULTI = 2 };
+enum { ORC_ZERO = 0, ORC_SINGLE = 1, ORC_MULTI = 2, ORC_DOUBLE = 3 };
 enum { ORC_OK = 0, ORC_PARTIAL = 1 };
 
 typedef struct {
@@ -37,6 +37,8 @@ typedef struct {
   double eps0, eps1;   /* exact-mode relative thresholds */
   double zero_k, single_k;  /* noisy-mode threshold widths (in noise std units) */
   double noise_var;    /* > 0: time-domain noise variance given, else estimated */
+  int32_t mpp;         /* tree, exact mode: 2 = resolve two-tons by the moment
+                          preserving solve (Sect. 3.1, a_m = 2); 0 = off */
 } orc_cfg;
 
 typedef struct {
@@ -52,6 +54,7 @@ typedef struct {
   double noise_var;                    /* time-domain noise variance used */
   int64_t n_found;                     /* before the top-K cut */
   int64_t order[4096];                 /* discovery order of the first frequencies found */
+  int32_t n_double[ORC_MAX_LEVELS];    /* tree: classes resolved as two-tons per level */
 } orc_trace;
 
 int orc_config(orc_cfg *c, int64_t N, int64_t K, int32_t stages, int32_t delays,

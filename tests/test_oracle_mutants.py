@@ -34,6 +34,12 @@ MUTANTS = {
     "splitmix_constant": ("0xBF58476D1CE4E5B9ULL", "0xBF58476D1CE4E5B8ULL"),
     "topk_order": ("return a->mag2 > b->mag2 ? -1 : 1;", "return a->mag2 > b->mag2 ? 1 : -1;"),
     "noise_quantile": ("return pw[at] / -log(1.0 - p / phi);", "return pw[at] / log(4.0 / 3.0);"),
+    "mpp_moment_index": ("rhs = -Y[r * D + d + 2];", "rhs = -Y[r * D + d + 1];"),
+    "mpp_gram_unconjugated": ("g01 += conj(m0) * m1;", "g01 += m0 * m1;"),
+    "mpp_root_sign": ("cplx z0 = (-c1 - disc) / 2.0, z1 = (-c1 + disc) / 2.0;",
+                      "cplx z0 = (c1 - disc) / 2.0, z1 = (c1 + disc) / 2.0;"),
+    "mpp_value_cross_term": ("cplx a0 = (nn * q0 - s01 * q1) / dv;",
+                             "cplx a0 = (nn * q0 + s01 * q1) / dv;"),
 }
 
 
@@ -109,8 +115,22 @@ def battery(libpath):
         return (np.array_equal(idx, siggen.truth(sp)[0])
                 and abs(tr.noise_var / sp.noise_var - 1) < 0.25)
 
+    def two_tons():
+        sup = [1, 6, 13, 20, 59]
+        sp = siggen.make_spec(64, 5, 2, support=sup)
+        x = siggen.synth(sp)
+        ok = True
+        for B0, want in ((4, [(3, 1, 0)]), (2, [(0, 1, 1), (1, 1, 0)])):
+            cfg = oracle.config(64, 5, 1, 4, B0=B0, identity_round0=True, mpp=2, libpath=libpath)
+            idx, val, cnt, tr = oracle.solve(cfg, x, libpath=libpath)
+            got = [(tr.n_single[l], tr.n_double[l], tr.n_multi[l]) for l in range(tr.levels + 1)]
+            ok = ok and got == want and np.array_equal(idx, sup)
+            ok = ok and np.max(np.abs(val - sp.values)) < 1e-6
+        return ok
+
     for name, fn in [("aliasing", aliasing), ("exact_tree", exact_tree), ("n20", n20),
-                     ("n64", n64), ("splitmix", splitmix), ("topk", topk), ("noisy", noisy)]:
+                     ("n64", n64), ("splitmix", splitmix), ("topk", topk), ("noisy", noisy),
+                     ("two_tons", two_tons)]:
         check(name, fn)
     return failed
 

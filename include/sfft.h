@@ -15,7 +15,8 @@
  * is a product of co-prime prime powers the library runs the FFAST peeling
  * decoder (Sect. 3.2, Eq. 19-20); when N is a power of two it runs the binary
  * tree search (Sect. 3.3, Eq. 23), opening the two children c and c + B of
- * every multi-ton at the next level.
+ * every multi-ton at the next level; optionally a multi-ton is first tried as
+ * a two-ton by the moment preserving solve of Sect. 3.1.
  *
  * Conventions.  Samples use an advance shift, y[m] = x[(sigma m L + s + d)
  * mod N]; bucket c then holds sum_{f = c mod B} xhat_f e^{+2 pi i f (s+d)/N}
@@ -103,6 +104,13 @@ typedef struct {
   double zero_k;           /* noisy: T0^2 = s_b^2 (n + zero_k sqrt(n))        (4) */
   double single_k;         /* noisy: T1^2 = s_b^2 (n-1 + single_k sqrt(n-1)) (4) */
   double noise_var;        /* noisy: time-domain noise variance; 0 = estimate */
+  int32_t mpp;             /* tree, exact mode: 2 = a class that fails the single-ton
+                              test is tried as a two-ton by the moment preserving
+                              solve (Sect. 3.1 with a = 2: Eq. 12-14 pooled over the
+                              rounds, Method 1 roots, Eq. 9 values) and closed when
+                              it fits; needs rounds x (delays - 2) >= 2, else
+                              SFFT_EINVAL; noisy mode or FFAST: SFFT_EUNSUPPORTED.
+                              0 = off (default) */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -123,6 +131,7 @@ typedef struct {
   int32_t jump_L;
   int32_t found_cap;       /* device list capacities per signal */
   int32_t multi_cap;
+  int32_t mpp;             /* two-ton solve (2) or off (0) */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */

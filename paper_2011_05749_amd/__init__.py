@@ -21,6 +21,12 @@ if not os.path.exists(LIB_PATH):
         f"libsfft.so not found at {LIB_PATH}: build it with "
         "`python paper_2011_05749_amd/build.py` (hipcc, gfx950); there is no fallback")
 
+# torch is loaded first so that the library's libamdhip64.so.7 dependency binds
+# to the HIP runtime torch already holds: a process must not carry two HIP/HSA
+# runtimes (torch's and /opt/rocm's), which would each open the device and not
+# know the other's allocations.
+import torch  # noqa: E402,F401  (device memory and streams come from torch)
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 MAX_ROUNDS = 16
@@ -46,6 +52,7 @@ class Params(ctypes.Structure):
         ("eps0", ctypes.c_double), ("eps1", ctypes.c_double),
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
+        ("mpp", ctypes.c_int32),
     ]
 
 
@@ -64,6 +71,7 @@ class PlanInfo(ctypes.Structure):
         ("noise_var", ctypes.c_double),
         ("max_peel_rounds", ctypes.c_int32), ("jump_L", ctypes.c_int32),
         ("found_cap", ctypes.c_int32), ("multi_cap", ctypes.c_int32),
+        ("mpp", ctypes.c_int32),
     ]
 
 
@@ -162,7 +170,7 @@ class Plan:
     """An sfft plan (immutable).  Keyword parameters map onto sfft_params_t:
     mode ('exact'|'noisy' or 0|1), B0, max_levels, window, identity_round0,
     stage_B (explicit co-prime FFAST stages), max_peel_rounds, jump_L, eps0, eps1,
-    zero_k, single_k, noise_var."""
+    zero_k, single_k, noise_var, mpp (2 = two-ton moment preserving solve)."""
 
     def __init__(self, N: int, K: int, stages: int, delays: int, seed: int = 0, **kw):
         p = Params()

@@ -184,6 +184,7 @@ struct BatchCtx {
       d.found_cap = in.found_cap;
       d.multi_cap = in.multi_cap;
       d.jump_L = in.kind == SFFT_KIND_TREE ? in.jump_L : 0;
+      d.mpp = in.mpp;
       for (int j = 0; j < SFFT_MAX_STAGES; j++) d.stageB[j] = in.stage_B[j];
       for (int j = 0; j <= SFFT_MAX_STAGES; j++) d.stageOff[j] = p->stage_off[j];
       for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.shift[r] = in.shift[r];
@@ -218,12 +219,10 @@ struct BatchCtx {
     }
     mz = mc * (int64_t)nmax;  // multi-ton vectors use the batch-wide stride nmax
     bool any_jump = false;
-    int jstride = 1;
     for (int s = 0; s < nsig; s++)
-      if (desc[s].kind == SFFT_KIND_TREE && jump_level(desc[s]) <= desc[s].max_levels) {
-        any_jump = true;
-        jstride = std::max(jstride, desc[s].jump_L);
-      }
+      if (desc[s].kind == SFFT_KIND_TREE && jump_level(desc[s]) <= desc[s].max_levels) any_jump = true;
+    // dense-pass coefficients per multi-ton slot: the widest stride any plan may use
+    const int jstride = kJumpMax;
     // longest solves first (LPT order) for the persistent level-0 launches
     std::stable_sort(tree.begin(), tree.end(), [](auto &a, auto &b) { return a.first > b.first; });
     std::stable_sort(ffast.begin(), ffast.end(), [](auto &a, auto &b) { return a.first > b.first; });
@@ -430,6 +429,8 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
   in.max_peel_rounds = p.max_peel_rounds > 0 ? p.max_peel_rounds : 64;
   if (p.jump_L < 0 || p.jump_L > kJumpMax || (p.jump_L > 0 && !pow2(p.jump_L))) return SFFT_EINVAL;
   in.jump_L = p.jump_L;
+  if (p.mpp != 0 && p.mpp != 2) return SFFT_EINVAL;
+  in.mpp = p.mpp;
   in.found_cap = (int32_t)std::max<int64_t>(64, npow2(2 * p.K));
   in.multi_cap = (int32_t)std::max<int64_t>(64, p.K);
   memset(pl->stage_off, 0, sizeof(pl->stage_off));
@@ -444,6 +445,8 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     if (B0 <= 0) B0 = std::min<int64_t>(npow2(2 * p.K), p.N);
     if (!pow2(B0) || B0 > p.N) return SFFT_EINVAL;
     if (B0 > kFftMax) return SFFT_EUNSUPPORTED;
+    if (p.mpp == 2 && p.mode != SFFT_EXACT) return SFFT_EUNSUPPORTED;
+    if (p.mpp == 2 && (int64_t)p.stages * (p.delays - 2) < 2) return SFFT_EINVAL;
     in.kind = SFFT_KIND_TREE;
     in.R = p.stages;
     in.B0 = B0;
@@ -492,6 +495,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
       if ((int)st.size() != p.stages) return SFFT_EUNSUPPORTED;
     }
     if ((int)st.size() > SFFT_MAX_STAGES) return SFFT_EUNSUPPORTED;
+    if (p.mpp != 0) return SFFT_EUNSUPPORTED;
     if (p.delays > kMaxMeas || p.N >= (int64_t(1) << 31)) return SFFT_EUNSUPPORTED;
     in.kind = SFFT_KIND_FFAST;
     in.R = (int32_t)st.size();
@@ -588,6 +592,7 @@ void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages, in
   p->zero_k = 4.0;
   p->single_k = 4.0;
   p->noise_var = 0.0;
+  p->mpp = 0;
 }
 
 sfft_plan_t sfft_plan_ex(const sfft_params_t *p) {

@@ -40,6 +40,7 @@ struct SigDesc {
   int32_t max_levels, window, nstages, max_peel_rounds;
   int32_t found_cap, multi_cap;
   int32_t jump_L;
+  int32_t mpp;            // 2: two-ton moment preserving solve of multi-tons
   int64_t stageB[SFFT_MAX_STAGES];
   int64_t stageOff[SFFT_MAX_STAGES + 1];
   uint64_t shift[SFFT_MAX_ROUNDS];
@@ -103,7 +104,7 @@ struct LaunchCtx {
   const int32_t *l0c_pre;  // prefix over tree_list of ceil(B0 / 256) (classify items)
   int32_t l0_items, l0c_items;
   int32_t any_wide_jump;   // some signal may run the dense pass at L' = 128
-  int32_t jstride;         // dense-pass coefficients per multi-ton slot (max jump_L)
+  int32_t jstride;         // dense-pass coefficients per multi-ton slot (kJumpMax)
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;

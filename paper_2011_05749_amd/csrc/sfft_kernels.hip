@@ -30,7 +30,7 @@ namespace sfft {
 
 namespace {
 
-constexpr int kZero = 0, kSingle = 1, kMulti = 2;
+constexpr int kZero = 0, kSingle = 1, kMulti = 2, kDouble = 3;
 
 __device__ __forceinline__ float2 cmulf(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -182,6 +182,19 @@ __device__ __forceinline__ int wave_append(int32_t *counter, bool pred) {
   return base + (int)__popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// as wave_append, for lanes that append 0, 1 or 2 entries
+__device__ __forceinline__ int wave_append_n(int32_t *counter, int cnt) {
+  const unsigned long long m1 = __ballot(cnt >= 1), m2 = __ballot(cnt >= 2);
+  if (m1 == 0ull) return -1;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m1) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, (int)(__popcll(m1) + __popcll(m2)));
+  base = __shfl(base, leader);
+  const unsigned long long below = (1ull << lane) - 1ull;
+  return base + (int)(__popcll(m1 & below) + __popcll(m2 & below));
+}
+
 __device__ double block_sum_d(double v, double *red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int w = threadIdx.x >> 6;
@@ -265,17 +278,128 @@ struct Verdict {
   int cls;
   int64_t f;
   double2 a;
+  int64_t f2;  // two-ton: second position and value
+  double2 a2;
 };
+
+// lattice index k of class c whose position estimate has phase phi
+// (u = phi N / 2 pi snapped to c + k B, Sect. 3.2 Subproblem 2)
+__device__ __forceinline__ int64_t lattice_k(double phi, int64_t N, int64_t B, int64_t c) {
+  const double two_pi = 6.283185307179586476925286766559;
+  if (phi < 0) phi += two_pi;
+  const double u = phi * (double)N / two_pi;
+  const double kf = floor((u - (double)c) / (double)B + 0.5);
+  const int64_t L = N / B;
+  int64_t k = (int64_t)kf % L;
+  if (k < 0) k += L;
+  return k;
+}
+
+// principal square root of a complex number (Kahan's form, no cancellation)
+__device__ __forceinline__ double2 csqrt_d(double2 z) {
+  const double r = hypot(z.x, z.y);
+  if (r == 0.0) return make_double2(0.0, 0.0);
+  const double t = sqrt(0.5 * (r + fabs(z.x)));
+  if (z.x >= 0.0) return make_double2(t, z.y / (2.0 * t));
+  return make_double2(fabs(z.y) / (2.0 * t), copysign(t, z.y));
+}
+
+__device__ __forceinline__ double2 cdiv_r(double2 a, double r) { return make_double2(a.x / r, a.y / r); }
+__device__ __forceinline__ double2 conj_mul(double2 a, double2 b) {  // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Two-ton solve of a class that failed the single-ton test (Sect. 3.1, the
+// moment preserving problem with a = 2).  In round r the delays are moments
+// m_d = sum_j p_j z_j^d, z_j = e^{2 pi i f_j / N}; the monic z^2 + c1 z + c0
+// with roots z_0, z_1 (Eq. 12) gives c0 m_d + c1 m_{d+1} = -m_{d+2} (Eq. 14)
+// for d <= D-3, pooled over the rounds by 2x2 normal equations.  The roots
+// (Method 1) are snapped to the class lattice; the two values solve the
+// Vandermonde system of all measurements in least squares (Eq. 9).  FP64.
+template <int NMAX>
+__device__ __forceinline__ void two_ton(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
+                                     int64_t c, int64_t B, double T0sq, double T1sq, Verdict &v) {
+  const int D = d.D;
+  const int64_t N = d.N;
+  double g00 = 0.0, g11 = 0.0;
+  double2 g01 = make_double2(0.0, 0.0), h0 = g01, h1 = g01;
+#pragma unroll
+  for (int i = 0; i + 2 < NMAX; i++) {
+    if (i + 2 < n && (i % D) + 2 < D && (i / D) < rounds) {
+      const double2 m0 = Y[i], m1 = Y[i + 1];
+      const double2 rhs = make_double2(-Y[i + 2].x, -Y[i + 2].y);
+      g00 += m0.x * m0.x + m0.y * m0.y;
+      g11 += m1.x * m1.x + m1.y * m1.y;
+      const double2 a = conj_mul(m0, m1), b = conj_mul(m0, rhs), e = conj_mul(m1, rhs);
+      g01.x += a.x; g01.y += a.y;
+      h0.x += b.x; h0.y += b.y;
+      h1.x += e.x; h1.y += e.y;
+    }
+  }
+  const double det = g00 * g11 - (g01.x * g01.x + g01.y * g01.y);
+  if (!(det > 1e-13 * g00 * g11)) return;
+  // C = G^{-1} h with G = [[g00, g01], [conj(g01), g11]]
+  const double2 t0 = cmul(g01, h1), t1 = conj_mul(g01, h0);
+  const double2 c0 = cdiv_r(make_double2(g11 * h0.x - t0.x, g11 * h0.y - t0.y), det);
+  const double2 c1 = cdiv_r(make_double2(g00 * h1.x - t1.x, g00 * h1.y - t1.y), det);
+  const double2 c1sq = cmul(c1, c1);
+  const double2 sq = csqrt_d(make_double2(c1sq.x - 4.0 * c0.x, c1sq.y - 4.0 * c0.y));
+  const double2 z0 = make_double2(0.5 * (-c1.x - sq.x), 0.5 * (-c1.y - sq.y));
+  const double2 z1 = make_double2(0.5 * (-c1.x + sq.x), 0.5 * (-c1.y + sq.y));
+  int64_t f0 = c + lattice_k(atan2(z0.y, z0.x), N, B, c) * B;
+  int64_t f1 = c + lattice_k(atan2(z1.y, z1.x), N, B, c) * B;
+  if (f0 == f1) return;
+  if (f1 < f0) {
+    const int64_t t = f0;
+    f0 = f1;
+    f1 = t;
+  }
+  double2 s01 = make_double2(0.0, 0.0), q0 = s01, q1 = s01;
+  double E2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < NMAX; i++) {
+    if (i < n) {
+      const uint64_t ti = tau_of(d, i);
+      const double2 e0 = unit_d(mod_n((uint64_t)f0 * ti, d), (uint64_t)N, +1);
+      const double2 e1 = unit_d(mod_n((uint64_t)f1 * ti, d), (uint64_t)N, +1);
+      const double2 a = conj_mul(e0, e1), b = conj_mul(e0, Y[i]), e = conj_mul(e1, Y[i]);
+      s01.x += a.x; s01.y += a.y;
+      q0.x += b.x; q0.y += b.y;
+      q1.x += e.x; q1.y += e.y;
+      E2 += Y[i].x * Y[i].x + Y[i].y * Y[i].y;
+    }
+  }
+  const double nn = (double)n;
+  const double dv = nn * nn - (s01.x * s01.x + s01.y * s01.y);
+  if (!(dv > 1e-9 * nn * nn)) return;
+  const double2 u0 = cmul(s01, q1);
+  const double2 u1 = conj_mul(s01, q0);
+  const double2 a0 = cdiv_r(make_double2(nn * q0.x - u0.x, nn * q0.y - u0.y), dv);
+  const double2 a1 = cdiv_r(make_double2(nn * q1.x - u1.x, nn * q1.y - u1.y), dv);
+  if (nn * (a0.x * a0.x + a0.y * a0.y) <= T0sq) return;
+  if (nn * (a1.x * a1.x + a1.y * a1.y) <= T0sq) return;
+  // least-squares residual |Y - V a|^2 = |Y|^2 - Re(a^H V^H Y); its rounding
+  // error (~1e-16 |Y|^2) is far below the single-ton bound eps1^2 |Y|^2
+  const double rho2 = E2 - (a0.x * q0.x + a0.y * q0.y + a1.x * q1.x + a1.y * q1.y);
+  if (!(rho2 <= T1sq)) return;
+  v.cls = kDouble;
+  v.f = f0;
+  v.a = a0;
+  v.f2 = f1;
+  v.a2 = a1;
+}
 
 // Singleton test (Sect. 3.2, Subproblems 1-2) of one class vector Y (n values,
 // rounds x D layout) of class c among B buckets.
-template <int NMAX>
+template <int NMAX, bool TWO = true>
 __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
                             int64_t c, int64_t B, double sref2, double noise_var) {
   Verdict v;
   v.cls = kZero;
   v.f = -1;
   v.a = make_double2(0.0, 0.0);
+  v.f2 = -1;
+  v.a2 = make_double2(0.0, 0.0);
   const int64_t N = d.N;
   const int64_t L = N / B;
   const int D = d.D;
@@ -306,14 +430,7 @@ __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, i
         P.y += a.y * b.x - a.x * b.y;
       }
     }
-    double phi = atan2(P.y, P.x);
-    const double two_pi = 6.283185307179586476925286766559;
-    if (phi < 0) phi += two_pi;
-    const double u = phi * (double)N / two_pi;
-    const double kf = floor((u - (double)c) / (double)B + 0.5);
-    int64_t k = (int64_t)kf % L;
-    if (k < 0) k += L;
-    ksnap = k;
+    ksnap = lattice_k(atan2(P.y, P.x), N, B, c);
   }
   int64_t k = ksnap;
   if (d.mode == SFFT_NOISY) {
@@ -395,6 +512,7 @@ __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, i
   v.f = f;
   v.a = a;
   v.cls = (rho2 <= T1sq) ? kSingle : kMulti;
+  if (TWO && v.cls == kMulti && d.mpp == 2) two_ton<NMAX>(Y, d, n, rounds, c, B, T0sq, T1sq, v);
   return v;
 }
 
@@ -534,9 +652,10 @@ __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
         if (i < n) Y[i] = to_d(Y0[(int64_t)i * B + cc]);
       v = classify<NMAX>(Y, d, n, d.R, cc, B, sref2, nv);
     }
-    const bool single = valid && v.cls == kSingle;
-    const int fs = wave_append(&c.st[s].found, single);
-    if (single) push_found(c, s, d, fs, v.f, v.a);
+    const int nf = !valid ? 0 : (v.cls == kSingle ? 1 : (v.cls == kDouble ? 2 : 0));
+    const int fs = wave_append_n(&c.st[s].found, nf);
+    if (nf >= 1) push_found(c, s, d, fs, v.f, v.a);
+    if (nf == 2) push_found(c, s, d, fs + 1, v.f2, v.a2);
     const bool multi = valid && v.cls == kMulti;
     const bool open = multi && L >= 2 && d.max_levels >= 1;
     if (multi && !open) atomicOr(&c.st[s].flags, 1);
@@ -681,7 +800,7 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
         double2 Y[NMAX];
 #pragma unroll
         for (int i = 0; i < NMAX; i++) Y[i] = i < D ? Yf[(int64_t)b * D + i] : make_double2(0.0, 0.0);
-        const Verdict v = classify<NMAX>(Y, d, D, 1, h, d.stageB[j], sref2, nv);
+        const Verdict v = classify<NMAX, false>(Y, d, D, 1, h, d.stageB[j], sref2, nv);
         cls[b] = (uint8_t)v.cls;
         if (v.cls == kSingle) {
           det[b] = 1;
@@ -1002,6 +1121,10 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
     if (v.cls == kSingle) {
       const int fs = atomicAdd(&c.st[s].found, 1);
       push_found(c, s, d, fs, v.f, v.a);
+    } else if (v.cls == kDouble) {
+      const int fs = atomicAdd(&c.st[s].found, 2);
+      push_found(c, s, d, fs, v.f, v.a);
+      push_found(c, s, d, fs + 1, v.f2, v.a2);
     } else if (v.cls == kMulti) {
       if (L >= 2 && level + 1 <= d.max_levels) {
         const int ms = atomicAdd(&c.st[s].multi[cur], 1);
@@ -1332,6 +1455,10 @@ __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int leve
         if (v.cls == kSingle) {
           const int fs = atomicAdd(&c.st[s].found, 1);
           push_found(c, s, d, fs, v.f, v.a);
+        } else if (v.cls == kDouble) {
+          const int fs = atomicAdd(&c.st[s].found, 2);
+          push_found(c, s, d, fs, v.f, v.a);
+          push_found(c, s, d, fs + 1, v.f2, v.a2);
         } else if (v.cls == kMulti) {
           if (Ld >= 2 && lvl + 1 <= d.max_levels) {
             open_nxt[k] = 1;

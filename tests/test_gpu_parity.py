@@ -44,7 +44,7 @@ def solve_both(sfft, x, N, K, stages, delays, seed=0, **kw):
     mode = kw.get("mode", 0)
     plan = sfft.Plan(N, K, stages, delays, seed=seed, **kw)
     ocfg_kw = {}
-    for k in ("window", "noise_var", "max_levels", "eps0", "eps1", "zero_k", "single_k"):
+    for k in ("window", "noise_var", "max_levels", "eps0", "eps1", "zero_k", "single_k", "mpp"):
         if k in ok:
             ocfg_kw[k] = ok[k]
     cfg = oracle_cfg(N, K, stages, delays, seed=seed, mode=mode, B0=kw.get("B0", 0),

@@ -8,7 +8,9 @@ Workload (synthetic, shaped like the paper's Sect. 5.1 signals): K = 1024
 tones at distinct uniform positions, magnitude 1, uniform phase, exactly
 sparse, complex64; plan: power-of-two tree search with B0 = 2048 buckets,
 4 rounds (random odd sigma and shift per round) x 2 delays, exact mode.
-Every signal's result is checked against its planted support.
+Every signal's result is checked against its planted support.  A second
+plan shape of the same signals -- 2 rounds x 4 delays with the two-ton moment
+preserving solve (Sect. 3.1) inside the tree -- is timed as "variants".
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -95,6 +97,33 @@ def run_plain(plans, xs, npl, K, dev, torch):
     return npl / (t1 - t0), [a.elapsed_time(b) for a, b in pev]
 
 
+def run_variant(sfft, torch, np, xs, specs, seeds, N, K, B0, R, D, steps, warmup, **kw):
+    """Same signals, another plan shape: spectra/s from a captured batch and
+    the number of signals whose result is exactly the planted spectrum."""
+    import siggen
+    plans = [sfft.Plan(N, K, R, D, seed=s, B0=B0, **kw) for s in seeds]
+    b = sfft.Batch(plans, xs)
+    for _ in range(warmup):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    counts = b.counts.cpu().numpy()
+    ok = sum(int(counts[i] == K and np.array_equal(b.idxs[i].cpu().numpy(), siggen.truth(sp)[0]))
+             for i, sp in enumerate(specs))
+    st = [b.stats(i) for i in range(len(seeds))]
+    out = {"value": round(len(seeds) / dt, 2), "unit": "spectra/s", "ms_per_batch": round(dt * 1e3, 4),
+           "rounds": R, "delays": D, **kw,
+           "verified": f"{ok}/{len(seeds)} signals: exact support, count K",
+           "samples_per_solve": float(np.mean([s["samples"] for s in st]))}
+    del b
+    sfft.release_batches()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +135,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jump-L", type=int, default=None,
                     help="override the plans' subtree-resolution stride (0 = level by level)")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the two-ton (moment preserving) plan variant")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -211,6 +242,13 @@ def main():
                    "GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
                for k, v in per.items()}
 
+    # --------------------------- two-ton solve variant (same signals, D = 4)
+    variants = None
+    if not args.no_variants:
+        print("bench: two-ton variant", file=sys.stderr, flush=True)
+        variants = {"two_ton_r2_d4": run_variant(sfft, torch, np, xs, specs, seeds, N, K, B0, 2, 4,
+                                                 args.steps, args.warmup, mpp=2, jump_L=0)}
+
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
@@ -259,6 +297,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(out), flush=True)
 

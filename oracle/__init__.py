@@ -27,6 +27,7 @@ OK, PARTIAL = 0, 1
 MAX_ROUNDS = 16
 MAX_STAGES = 8
 MAX_LEVELS = 64
+MAX_STARTS = 64
 
 
 class Cfg(ctypes.Structure):
@@ -44,6 +45,8 @@ class Cfg(ctypes.Structure):
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
         ("mpp", ctypes.c_int32),
+        ("n_starts", ctypes.c_int32),
+        ("start_f", ctypes.c_int64 * MAX_STARTS),
     ]
 
 
@@ -96,6 +99,8 @@ def lib(path: str | None = None):
         L.orc_config_stages.restype = ctypes.c_int
         L.orc_splitmix64_next.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
         L.orc_splitmix64_next.restype = ctypes.c_uint64
+        L.orc_draw_starts.argtypes = [ctypes.POINTER(Cfg), ctypes.c_uint64, ctypes.c_int32]
+        L.orc_draw_starts.restype = ctypes.c_int
         L.orc_bin.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                               ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]
         L.orc_bin.restype = None
@@ -123,6 +128,15 @@ def config(N, K, stages, delays, seed=0, mode=EXACT, B0=0, identity_round0=False
         raise ValueError(f"oracle config rejected (rc={rc}) N={N} K={K} stages={stages} "
                          f"delays={delays} mode={mode} B0={B0}")
     for k, v in overrides.items():
+        if k == "start_f":
+            c.n_starts = len(v)
+            for i, f in enumerate(v):
+                c.start_f[i] = int(f)
+            continue
+        if k == "peel_starts":
+            if L.orc_draw_starts(ctypes.byref(c), seed, int(v)) != 0:
+                raise ValueError("too many start frequencies")
+            continue
         setattr(c, k, v)
     return c
 

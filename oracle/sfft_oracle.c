@@ -68,6 +68,14 @@ static void cfg_defaults(orc_cfg *c) {
   c->window = 0;
 }
 
+int orc_draw_starts(orc_cfg *c, uint64_t seed, int32_t count) {
+  if (count < 0 || count > ORC_MAX_STARTS) return -1;
+  uint64_t st = seed;
+  c->n_starts = count;
+  for (int i = 0; i < count; i++) c->start_f[i] = (int64_t)(orc_splitmix64_next(&st) % (uint64_t)c->N);
+  return 0;
+}
+
 /* Plan of the tree (N a power of two) or of FFAST (N a product of co-prime
    prime powers, Sect. 3.2: B_i = p_i^e_i, L_i = N / B_i, ascending prime). */
 int orc_config(orc_cfg *c, int64_t N, int64_t K, int32_t stages, int32_t delays,
@@ -636,12 +644,17 @@ static int64_t solve_tree(const orc_cfg *c, const float *x, int64_t *out_idx,
 }
 
 /* ------------------------------------------------------------------ */
-/* FFAST peeling decoder (Sect. 3.2, Subproblem 3, method 1, Eq. 20), in
-   Jacobi rounds: identify the active buckets on the state at the start of
-   the round, keep each new frequency once (lowest stage, then lowest
-   bucket), subtract every new frequency from its bucket in every stage,
-   and make active the buckets that changed, minus those in which a
-   singleton was identified this round.                              */
+/* FFAST peeling decoder (Sect. 3.2, Subproblem 3, Eq. 20), in Jacobi
+   rounds: identify the active buckets on the state at the start of the
+   round, keep each new frequency once (lowest stage, then lowest bucket),
+   subtract every new frequency from its bucket in every stage, and make
+   active the buckets that changed, minus those in which a singleton was
+   identified this round.  Method 1 starts with every bucket active.
+   Method 2 (the packet-erasure schedule) starts with the buckets of its
+   start frequencies, so that the active set of round p is the frontier of
+   the depth-(2p-1) trees grown from them in lock-step, and stops once K
+   frequencies are identified; if the trees die out before that, the
+   buckets they never reached join the next round.                    */
 
 static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
                            double *out_val, orc_trace *tr) {
@@ -681,17 +694,34 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
   char *active = (char *)malloc((size_t)nb);
   char *modified = (char *)malloc((size_t)nb);
   char *detected = (char *)malloc((size_t)nb);
+  char *seen = (char *)malloc((size_t)nb);
   int64_t *nf = (int64_t *)malloc(sizeof(int64_t) * (size_t)nb);
   cplx *na = (cplx *)malloc(sizeof(cplx) * (size_t)nb);
+  /* method 1 (genie-assisted peeling) identifies every bucket in the first
+     peeling; method 2 (packet-erasure schedule) starts from the d buckets of
+     each start frequency -- the trees N_V^1 of its start points -- and grows
+     them along the buckets that the frequencies found change */
+  int schedule = c->n_starts > 0;
   for (int64_t b = 0; b < nb; b++) {
     last[b] = -1;
-    active[b] = 1;
+    active[b] = !schedule;
+    seen[b] = 0;
   }
+  for (int i = 0; i < c->n_starts; i++)
+    for (int j = 0; j < S; j++) active[off[j] + c->start_f[i] % c->stageB[j]] = 1;
   found_list fl = {0, 0, 0, 0};
-  int round = 0, partial = 0;
+  int round = 0, partial = 0, complete = 0;
   for (;;) {
     int any = 0;
     for (int64_t b = 0; b < nb && !any; b++) any = active[b];
+    if (!any && schedule && fl.n < c->K) {
+      /* the trees stopped short of K frequencies: every bucket none of them
+         has reached joins the next peeling */
+      for (int64_t b = 0; b < nb; b++) {
+        active[b] = !seen[b];
+        any |= active[b];
+      }
+    }
     if (!any) break;
     if (round == c->max_peel_rounds) {
       partial = 1;
@@ -705,6 +735,7 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
         int64_t b = off[j] + h;
         if (!active[b]) continue;
         ident++;
+        seen[b] = 1;
         verdict v = classify(&cx, Y + b * D, h, c->stageB[j]);
         last[b] = v.cls;
         if (v.cls == ORC_ZERO) nz++;
@@ -729,7 +760,11 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
       tr->levels = round + 1;
     }
     round++;
-    if (nnew == 0) break;
+    if (nnew == 0) {
+      if (!schedule) break;
+      memset(active, 0, (size_t)nb); /* the trees died out: fall back as above */
+      continue;
+    }
     memset(modified, 0, (size_t)nb);
     for (int64_t i = 0; i < nnew; i++) {
       found_push(&fl, nf[i], na[i]);
@@ -743,8 +778,13 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
       }
     }
     for (int64_t b = 0; b < nb; b++) active[b] = modified[b] && !detected[b];
+    /* the schedule ends once K frequencies are identified */
+    if (schedule && fl.n >= c->K) {
+      complete = 1;
+      break;
+    }
   }
-  for (int64_t b = 0; b < nb && !partial; b++)
+  for (int64_t b = 0; b < nb && !partial && !complete; b++)
     if (last[b] == ORC_MULTI) partial = 1;
   if (tr) {
     int64_t tot = 0;
@@ -761,6 +801,7 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
   free(active);
   free(modified);
   free(detected);
+  free(seen);
   free(nf);
   free(na);
   free(Y);

@@ -15,6 +15,7 @@
 #define ORC_MAX_ROUNDS 16
 #define ORC_MAX_STAGES 8
 #define ORC_MAX_LEVELS 64
+#define ORC_MAX_STARTS 64
 
 enum { ORC_EXACT = 0, ORC_NOISY = 1 };
 enum { ORC_TREE = 0, ORC_FFAST = 1 };
@@ -39,6 +40,10 @@ typedef struct {
   double noise_var;    /* > 0: time-domain noise variance given, else estimated */
   int32_t mpp;         /* tree, exact mode: 2 = resolve two-tons by the moment
                           preserving solve (Sect. 3.1, a_m = 2); 0 = off */
+  int32_t n_starts;    /* FFAST: 0 = every bucket in the first peeling (method 1);
+                          > 0 = packet-erasure schedule (method 2) grown from the
+                          buckets of these start frequencies */
+  int64_t start_f[ORC_MAX_STARTS];
 } orc_cfg;
 
 typedef struct {
@@ -62,6 +67,9 @@ int orc_config(orc_cfg *c, int64_t N, int64_t K, int32_t stages, int32_t delays,
 int orc_config_stages(orc_cfg *c, int64_t N, int64_t K, int32_t nstages,
                       const int64_t *stageB, int32_t delays, int32_t mode);
 uint64_t orc_splitmix64_next(uint64_t *state);
+/* start frequencies of the packet-erasure schedule: count SplitMix64 draws
+   from seed, each reduced modulo N */
+int orc_draw_starts(orc_cfg *c, uint64_t seed, int32_t count);
 
 /* One bin of the B-point filtered spectrum of Eq. 5-6 (advance shift tau). */
 void orc_bin(const float *x, int64_t N, int64_t B, uint64_t sigma, uint64_t tau,

@@ -38,6 +38,9 @@ MUTANTS = {
     "mpp_gram_unconjugated": ("g01 += conj(m0) * m1;", "g01 += m0 * m1;"),
     "mpp_root_sign": ("cplx z0 = (-c1 - disc) / 2.0, z1 = (-c1 + disc) / 2.0;",
                       "cplx z0 = (c1 - disc) / 2.0, z1 = (c1 + disc) / 2.0;"),
+    "schedule_start_stage": ("active[off[j] + c->start_f[i] % c->stageB[j]] = 1;",
+                             "active[off[j] + c->start_f[i] % c->stageB[0]] = 1;"),
+    "schedule_no_stop_at_K": ("if (schedule && fl.n >= c->K) {", "if (schedule && fl.n > c->K) {"),
     "mpp_value_cross_term": ("cplx a0 = (nn * q0 - s01 * q1) / dv;",
                              "cplx a0 = (nn * q0 + s01 * q1) / dv;"),
 }
@@ -128,7 +131,14 @@ def battery(libpath):
             ok = ok and np.max(np.abs(val - sp.values)) < 1e-6
         return ok
 
-    for name, fn in [("aliasing", aliasing), ("exact_tree", exact_tree), ("n20", n20),
+    def packet_erasure():
+        sup = [1, 3, 5, 10, 13]
+        x = siggen.synth(siggen.make_spec(20, 5, 1, support=sup))
+        cfg = oracle.config(20, 5, 2, 2, stageB=[4, 5], start_f=[2, 7], libpath=libpath)
+        idx, val, cnt, tr = oracle.solve(cfg, x, libpath=libpath)
+        return [tr.ident[r] for r in range(tr.levels)] == [3, 2, 1] and np.array_equal(idx, sup)
+
+    for name, fn in [("packet_erasure", packet_erasure), ("aliasing", aliasing), ("exact_tree", exact_tree), ("n20", n20),
                      ("n64", n64), ("splitmix", splitmix), ("topk", topk), ("noisy", noisy),
                      ("two_tons", two_tons)]:
         check(name, fn)

@@ -48,6 +48,7 @@ extern "C" {
 
 #define SFFT_MAX_ROUNDS 16
 #define SFFT_MAX_STAGES 8
+#define SFFT_MAX_PEEL_STARTS 64
 
 /* error codes (negative returns) */
 #define SFFT_OK 0
@@ -111,6 +112,18 @@ typedef struct {
                               it fits; needs rounds x (delays - 2) >= 2, else
                               SFFT_EINVAL; noisy mode or FFAST: SFFT_EUNSUPPORTED.
                               0 = off (default) */
+  int32_t peel_starts;     /* FFAST: 0 = genie-assisted peeling, every bucket identified
+                              in the first peeling (Sect. 3.2, Subproblem 3, method 1;
+                              default).  S in 1..SFFT_MAX_PEEL_STARTS = packet-erasure
+                              schedule (method 2): peeling grows from the buckets of S
+                              start frequencies, one depth of their trees per round, and
+                              stops once K frequencies are found; if the trees die out
+                              first, the buckets they never reached join the next round.
+                              Tree plans: SFFT_EUNSUPPORTED. */
+  int64_t peel_start_f[SFFT_MAX_PEEL_STARTS];
+                           /* the S start frequencies (each in [0, N)); all -1 (the
+                              default) = S SplitMix64 draws from `seed`, each mod N;
+                              a mix of given and -1 entries: SFFT_EINVAL */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -132,6 +145,8 @@ typedef struct {
   int32_t found_cap;       /* device list capacities per signal */
   int32_t multi_cap;
   int32_t mpp;             /* two-ton solve (2) or off (0) */
+  int32_t peel_starts;     /* FFAST schedule: start frequencies (0 = method 1) */
+  int64_t peel_start_f[SFFT_MAX_PEEL_STARTS];
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */
@@ -144,6 +159,7 @@ typedef struct {
   double noise_var;        /* noise variance used (noisy mode) */
   double sref2;            /* mean level-0 bucket power */
   uint64_t level_mask;     /* tree: bit l set when level l gathered samples */
+  int64_t ident;           /* FFAST: bucket identifications over all peeling rounds */
 } sfft_stats_t;
 
 /* Defaults for (N, K, stages, delays, seed). */

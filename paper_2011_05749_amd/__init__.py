@@ -31,6 +31,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 MAX_ROUNDS = 16
 MAX_STAGES = 8
+MAX_PEEL_STARTS = 64
 EXACT, NOISY = 0, 1
 KIND_TREE, KIND_FFAST = 0, 1
 STATUS_OK, STATUS_PARTIAL = 0, 1
@@ -53,6 +54,8 @@ class Params(ctypes.Structure):
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
         ("mpp", ctypes.c_int32),
+        ("peel_starts", ctypes.c_int32),
+        ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
     ]
 
 
@@ -72,6 +75,8 @@ class PlanInfo(ctypes.Structure):
         ("max_peel_rounds", ctypes.c_int32), ("jump_L", ctypes.c_int32),
         ("found_cap", ctypes.c_int32), ("multi_cap", ctypes.c_int32),
         ("mpp", ctypes.c_int32),
+        ("peel_starts", ctypes.c_int32),
+        ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
     ]
 
 
@@ -80,7 +85,7 @@ class Stats(ctypes.Structure):
         ("count", ctypes.c_int64), ("status", ctypes.c_int32), ("levels", ctypes.c_int32),
         ("samples", ctypes.c_int64), ("found", ctypes.c_int64),
         ("noise_var", ctypes.c_double), ("sref2", ctypes.c_double),
-        ("level_mask", ctypes.c_uint64),
+        ("level_mask", ctypes.c_uint64), ("ident", ctypes.c_int64),
     ]
 
 
@@ -170,7 +175,9 @@ class Plan:
     """An sfft plan (immutable).  Keyword parameters map onto sfft_params_t:
     mode ('exact'|'noisy' or 0|1), B0, max_levels, window, identity_round0,
     stage_B (explicit co-prime FFAST stages), max_peel_rounds, jump_L, eps0, eps1,
-    zero_k, single_k, noise_var, mpp (2 = two-ton moment preserving solve)."""
+    zero_k, single_k, noise_var, mpp (2 = two-ton moment preserving solve), peel_starts
+    (FFAST packet-erasure schedule: number of drawn start frequencies) or peel_start_f
+    (explicit start frequencies)."""
 
     def __init__(self, N: int, K: int, stages: int, delays: int, seed: int = 0, **kw):
         p = Params()
@@ -182,6 +189,11 @@ class Plan:
                 p.nstage_B = len(v)
                 for j, b in enumerate(v):
                     p.stage_B[j] = int(b)
+                continue
+            if k == "peel_start_f":
+                p.peel_starts = len(v)
+                for j, f in enumerate(v):
+                    p.peel_start_f[j] = int(f)
                 continue
             if not hasattr(p, k):
                 raise TypeError(f"unknown plan parameter {k}")

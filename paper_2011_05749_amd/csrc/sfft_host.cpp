@@ -185,6 +185,8 @@ struct BatchCtx {
       d.multi_cap = in.multi_cap;
       d.jump_L = in.kind == SFFT_KIND_TREE ? in.jump_L : 0;
       d.mpp = in.mpp;
+      d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
+      for (int i = 0; i < SFFT_MAX_PEEL_STARTS; i++) d.start_f[i] = in.peel_start_f[i];
       for (int j = 0; j < SFFT_MAX_STAGES; j++) d.stageB[j] = in.stage_B[j];
       for (int j = 0; j <= SFFT_MAX_STAGES; j++) d.stageOff[j] = p->stage_off[j];
       for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.shift[r] = in.shift[r];
@@ -445,6 +447,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     if (B0 <= 0) B0 = std::min<int64_t>(npow2(2 * p.K), p.N);
     if (!pow2(B0) || B0 > p.N) return SFFT_EINVAL;
     if (B0 > kFftMax) return SFFT_EUNSUPPORTED;
+    if (p.peel_starts != 0) return SFFT_EUNSUPPORTED;
     if (p.mpp == 2 && p.mode != SFFT_EXACT) return SFFT_EUNSUPPORTED;
     if (p.mpp == 2 && (int64_t)p.stages * (p.delays - 2) < 2) return SFFT_EINVAL;
     in.kind = SFFT_KIND_TREE;
@@ -496,6 +499,19 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     }
     if ((int)st.size() > SFFT_MAX_STAGES) return SFFT_EUNSUPPORTED;
     if (p.mpp != 0) return SFFT_EUNSUPPORTED;
+    if (p.peel_starts < 0 || p.peel_starts > SFFT_MAX_PEEL_STARTS) return SFFT_EINVAL;
+    in.peel_starts = p.peel_starts;
+    if (p.peel_starts > 0) {
+      int given = 0;
+      for (int i = 0; i < p.peel_starts; i++) {
+        if (p.peel_start_f[i] >= p.N) return SFFT_EINVAL;
+        given += p.peel_start_f[i] >= 0;
+      }
+      if (given != 0 && given != p.peel_starts) return SFFT_EINVAL;
+      SplitMix64 g{p.seed};
+      for (int i = 0; i < p.peel_starts; i++)
+        in.peel_start_f[i] = given ? p.peel_start_f[i] : (int64_t)(g.next() % (uint64_t)p.N);
+    }
     if (p.delays > kMaxMeas || p.N >= (int64_t(1) << 31)) return SFFT_EUNSUPPORTED;
     in.kind = SFFT_KIND_FFAST;
     in.R = (int32_t)st.size();
@@ -593,6 +609,8 @@ void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages, in
   p->single_k = 4.0;
   p->noise_var = 0.0;
   p->mpp = 0;
+  p->peel_starts = 0;
+  for (int i = 0; i < SFFT_MAX_PEEL_STARTS; i++) p->peel_start_f[i] = -1;
 }
 
 sfft_plan_t sfft_plan_ex(const sfft_params_t *p) {
@@ -803,7 +821,7 @@ static void fill_stats(const SigState &st, const SigDesc &d, int64_t count, int3
   out->noise_var = st.noise_var;
   out->sref2 = st.sref2;
   out->level_mask = st.level_mask;
-  (void)d;
+  out->ident = d.kind == SFFT_KIND_FFAST ? st.ident : 0;
 }
 
 int32_t sfft_exec_stats(sfft_plan_t plan, sfft_stats_t *out) {

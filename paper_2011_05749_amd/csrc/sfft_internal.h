@@ -41,6 +41,8 @@ struct SigDesc {
   int32_t found_cap, multi_cap;
   int32_t jump_L;
   int32_t mpp;            // 2: two-ton moment preserving solve of multi-tons
+  int32_t n_starts;       // FFAST packet-erasure schedule: start frequencies (0: method 1)
+  int64_t start_f[SFFT_MAX_PEEL_STARTS];
   int64_t stageB[SFFT_MAX_STAGES];
   int64_t stageOff[SFFT_MAX_STAGES + 1];
   uint64_t shift[SFFT_MAX_ROUNDS];
@@ -70,7 +72,7 @@ struct SigState {
   int32_t multi[2];       // multi-tons per level parity
   int32_t flags;          // bit 0: unresolved multi-ton / cap; bit 1: list overflow
   int32_t levels;         // deepest tree level opened / peeling rounds
-  int32_t pad;
+  int32_t ident;          // FFAST: bucket identifications
   int64_t samples;
   uint64_t level_mask;    // bit l set when tree level l gathered samples
   double sref2;

@@ -537,7 +537,7 @@ __global__ void k_reset(LaunchCtx c) {
   z.multi[1] = 0;
   z.flags = 0;
   z.levels = 0;
-  z.pad = 0;
+  z.ident = 0;
   z.samples = 0;
   z.level_mask = 0;
   z.sref2 = 0.0;
@@ -689,6 +689,7 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
   uint8_t *modf = det + kMaxFfastBuckets;
   uint8_t *cls = modf + kMaxFfastBuckets;
   uint8_t *isnew = cls + kMaxFfastBuckets;
+  uint8_t *seen = isnew + kMaxFfastBuckets;
   __shared__ double red[16];
   __shared__ int ired[16];
   __shared__ uint32_t hist[256];
@@ -776,24 +777,54 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
       const float q = select_kth_power(tmp, (int64_t)nb * D, 1.0f, d.noise_at, hist, sel);
       nv = (double)q / d.noise_p_den;
     }
+    // method 1 activates every bucket; the packet-erasure schedule (method 2)
+    // activates the buckets of its start frequencies (their depth-1 trees)
+    const bool schedule = d.n_starts > 0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-      active[b] = 1;
+      active[b] = schedule ? 0 : 1;
       cls[b] = kZero;
+      seen[b] = 0;
     }
+    __syncthreads();
+    if (schedule)
+      for (int q = threadIdx.x; q < d.n_starts * S; q += blockDim.x) {
+        const int i = q / S, j = q % S;
+        active[d.stageOff[j] + (int)(d.start_f[i] % d.stageB[j])] = 1;
+      }
     if (threadIdx.x == 0) flag_any = 1;
     __syncthreads();
-    int nfound = 0, round = 0, partial = 0;
+    int nfound = 0, round = 0, partial = 0, complete = 0, ident = 0;
     const int per = (nb + (int)blockDim.x - 1) / (int)blockDim.x;
     for (;;) {
+      if (schedule && nfound < d.K) {
+        // the trees died out short of K: the buckets never reached join in
+        if (threadIdx.x == 0) flag_any = 0;
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+          if (active[b]) flag_any = 1;
+        __syncthreads();
+        const int live = flag_any;
+        __syncthreads();
+        if (!live) {
+          for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            active[b] = !seen[b];
+            if (active[b]) flag_any = 1;
+          }
+        }
+        __syncthreads();
+      }
       if (!flag_any) break;
       if (round == d.max_peel_rounds) {
         partial = 1;
         break;
       }
       // 1. identify every active bucket on the state at the start of the round
+      int nid = 0;
       for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         det[b] = 0;
         if (!active[b]) continue;
+        seen[b] = 1;
+        nid++;
         int j = 0;
         while (j + 1 < S && d.stageOff[j + 1] <= b) j++;
         const int64_t h = b - d.stageOff[j];
@@ -838,9 +869,18 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
           c.A.found_a[d.found_off + slot] = va[b];
         }
       }
+      int nid_tot = 0;
+      (void)block_scan_excl(nid, ired, &nid_tot);
+      ident += nid_tot;
       __syncthreads();
       round++;
-      if (total == 0) break;
+      if (total == 0) {
+        if (!schedule) break;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) active[b] = 0;
+        if (threadIdx.x == 0) flag_any = 0;
+        __syncthreads();
+        continue;
+      }
       int nnew = total;
       if (nfound + nnew > d.found_cap) {
         nnew = d.found_cap - nfound;
@@ -877,17 +917,24 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
       }
       __syncthreads();
       if (partial) break;
+      // the schedule ends once K frequencies are identified
+      if (schedule && nfound >= d.K) {
+        complete = 1;
+        break;
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) flag_any = 0;
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x)
-      if (cls[b] == kMulti) flag_any = 1;
+    if (!complete)
+      for (int b = threadIdx.x; b < nb; b += blockDim.x)
+        if (cls[b] == kMulti) flag_any = 1;
     __syncthreads();
     if (threadIdx.x == 0) {
       c.st[s].found = nfound;
       c.st[s].flags = (partial || flag_any) ? 1 : 0;
       c.st[s].levels = round;
+      c.st[s].ident = ident;
       c.st[s].samples = (int64_t)nb * D;
       c.st[s].sref2 = sref2;
       c.st[s].noise_var = nv;
@@ -1634,7 +1681,7 @@ hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
   }
   if (c.nffast > 0) {
     const int grid = c.nffast < 4096 ? c.nffast : 4096;
-    const size_t lds = sizeof(float2) * (kFftMax + kDirectMax) + 5 * kMaxFfastBuckets;
+    const size_t lds = sizeof(float2) * (kFftMax + kDirectMax) + 6 * kMaxFfastBuckets;
     if (nm == 8) hipLaunchKernelGGL(k_ffast<8>, dim3(grid), dim3(kThreads), lds, s, c);
     else if (nm == 16) hipLaunchKernelGGL(k_ffast<16>, dim3(grid), dim3(kThreads), lds, s, c);
     else hipLaunchKernelGGL(k_ffast<64>, dim3(grid), dim3(kThreads), lds, s, c);

@@ -99,6 +99,40 @@ def test_plan_validation(args, kw, code):
     assert e.value.code == code
 
 
+@pytest.mark.parametrize("S,seed", [(1, 0), (4, 77), (64, 1234567)])
+def test_peel_start_draws_match_oracle(S, seed):
+    p = sfft.Plan(10800, 10, 3, 2, seed=seed, peel_starts=S)
+    c = oracle.config(10800, 10, 3, 2, seed=seed, peel_starts=S)
+    assert p.info.peel_starts == c.n_starts == S
+    assert [p.info.peel_start_f[i] for i in range(S)] == [c.start_f[i] for i in range(S)]
+    q = sfft.Plan(20, 5, 2, 2, stage_B=[4, 5], peel_start_f=[2, 7])
+    assert q.info.peel_starts == 2 and list(q.info.peel_start_f[:2]) == [2, 7]
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({"peel_starts": 3}, -2),                                   # tree plan: no schedule
+])
+def test_peel_schedule_tree_unsupported(kw, code):
+    with pytest.raises(sfft.SfftError) as e:
+        sfft.Plan(1024, 10, 2, 2, **kw)
+    assert e.value.code == code
+
+
+def test_peel_schedule_validation():
+    for kw in ({"peel_starts": 65}, {"peel_starts": -1}, {"peel_start_f": [2, 25]}):
+        with pytest.raises(sfft.SfftError) as e:
+            sfft.Plan(20, 5, 2, 2, stage_B=[4, 5], **kw)
+        assert e.value.code == -1
+    p = sfft.Params()
+    sfft._lib.sfft_params_init(ctypes.byref(p), 20, 5, 2, 2, 0)
+    p.nstage_B = 2
+    p.stage_B[0], p.stage_B[1] = 4, 5
+    p.peel_starts = 2
+    p.peel_start_f[0] = 3      # one given, one drawn: rejected
+    assert not sfft._lib.sfft_plan_ex(ctypes.byref(p))
+    assert sfft._lib.sfft_last_error() == -1
+
+
 def test_noisy_plan_allows_one_delay_and_window():
     p = sfft.Plan(2 ** 16, 32, 4, 1, seed=1, mode="noisy", window=16)
     assert p.info.mode == sfft.NOISY and p.info.D == 1 and p.info.window == 16

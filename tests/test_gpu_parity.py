@@ -44,9 +44,12 @@ def solve_both(sfft, x, N, K, stages, delays, seed=0, **kw):
     mode = kw.get("mode", 0)
     plan = sfft.Plan(N, K, stages, delays, seed=seed, **kw)
     ocfg_kw = {}
-    for k in ("window", "noise_var", "max_levels", "eps0", "eps1", "zero_k", "single_k", "mpp"):
+    for k in ("window", "noise_var", "max_levels", "eps0", "eps1", "zero_k", "single_k", "mpp",
+              "peel_starts"):
         if k in ok:
             ocfg_kw[k] = ok[k]
+    if "peel_start_f" in ok:
+        ocfg_kw["start_f"] = ok["peel_start_f"]
     cfg = oracle_cfg(N, K, stages, delays, seed=seed, mode=mode, B0=kw.get("B0", 0),
                      identity_round0=bool(kw.get("identity_round0", 0)),
                      stage_B=kw.get("stage_B"), **ocfg_kw)

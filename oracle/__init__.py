@@ -45,6 +45,8 @@ class Cfg(ctypes.Structure):
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
         ("mpp", ctypes.c_int32),
+        ("rf_iters", ctypes.c_int32), ("rf_m", ctypes.c_int32),
+        ("rf_off", ctypes.c_uint64 * MAX_ROUNDS),
         ("n_starts", ctypes.c_int32),
         ("start_f", ctypes.c_int64 * MAX_STARTS),
     ]
@@ -101,6 +103,11 @@ def lib(path: str | None = None):
         L.orc_splitmix64_next.restype = ctypes.c_uint64
         L.orc_draw_starts.argtypes = [ctypes.POINTER(Cfg), ctypes.c_uint64, ctypes.c_int32]
         L.orc_draw_starts.restype = ctypes.c_int
+        L.orc_set_rffast.argtypes = [ctypes.POINTER(Cfg), ctypes.c_uint64, ctypes.c_int32,
+                                     ctypes.c_int32]
+        L.orc_set_rffast.restype = ctypes.c_int
+        L.orc_kay_phase.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.orc_kay_phase.restype = ctypes.c_double
         L.orc_bin.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64,
                               ctypes.c_uint64, ctypes.c_int64, ctypes.c_void_p]
         L.orc_bin.restype = None
@@ -127,6 +134,10 @@ def config(N, K, stages, delays, seed=0, mode=EXACT, B0=0, identity_round0=False
     if rc != 0:
         raise ValueError(f"oracle config rejected (rc={rc}) N={N} K={K} stages={stages} "
                          f"delays={delays} mode={mode} B0={B0}")
+    if "rffast" in overrides:
+        C, m = overrides.pop("rffast")
+        if L.orc_set_rffast(ctypes.byref(c), seed, int(C), int(m)) != 0:
+            raise ValueError("R-FFAST delay set rejected")
     for k, v in overrides.items():
         if k == "start_f":
             c.n_starts = len(v)
@@ -176,6 +187,12 @@ def solve(cfg: Cfg, x, libpath=None):
     cnt = lib(libpath).orc_solve(ctypes.byref(cfg), x.ctypes.data, idx.ctypes.data,
                                  val.ctypes.data, ctypes.byref(tr))
     return idx, val, int(cnt), tr
+
+
+def kay_phase(y, libpath=None) -> float:
+    """Kay's weighted phase-difference estimate of m samples (Eq. 21-22)."""
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.complex128))
+    return float(lib(libpath).orc_kay_phase(y.ctypes.data, len(y)))
 
 
 def splitmix64(seed: int, count: int, libpath=None):

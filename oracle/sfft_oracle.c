@@ -1,8 +1,8 @@
 /*
  * sfft_oracle.c -- plain, slow FP64 CPU oracle of the aliasing-filter sparse
  * FFT hot path: frequency bucketization, singleton test, phase-to-index
- * location, two-ton moment preserving solve, FFAST peeling and binary-tree
- * search, as described in
+ * location, two-ton moment preserving solve, R-FFAST singleton estimator,
+ * FFAST peeling (both schedules) and binary-tree search, as described in
  * Li, Jiang & Chen, "On Performance of Sparse Fast Fourier Transform
  * Algorithms Using the Aliasing Filter" (2020).
  *
@@ -22,7 +22,9 @@
  * identity against a brute-force DFT, exact recovery of planted spectra, the
  * N=20 peeling example of Sect. 3.2, the N=64 tree example and the
  * small-support case of Sect. 3.3, Table 1 by Monte Carlo; the two-ton
- * solve by the residue structure of the tree and the N=64 example), except the
+ * solve by the residue structure of the tree and the N=64 example; the
+ * packet-erasure schedule by the six-identification N=20 example; Kay's
+ * estimator by its noiseless limit and the Cramer-Rao bound), except the
  * noisy-mode thresholds (parity unpinned: the paper gives no values for T0,
  * T1; they are checked only through their noiseless limit and statistics).
  */
@@ -68,9 +70,20 @@ static void cfg_defaults(orc_cfg *c) {
   c->window = 0;
 }
 
+int orc_set_rffast(orc_cfg *c, uint64_t seed, int32_t C, int32_t m) {
+  if (c->kind != ORC_FFAST || C < 1 || C > ORC_MAX_ROUNDS || m < 2 || C * m > 64) return -1;
+  uint64_t st = seed;
+  c->rf_iters = C;
+  c->rf_m = m;
+  c->D = C * m;
+  for (int i = 0; i < C; i++) c->rf_off[i] = orc_splitmix64_next(&st) % (uint64_t)c->N;
+  return 0;
+}
+
 int orc_draw_starts(orc_cfg *c, uint64_t seed, int32_t count) {
   if (count < 0 || count > ORC_MAX_STARTS) return -1;
   uint64_t st = seed;
+  for (int i = 0; i < c->rf_iters; i++) (void)orc_splitmix64_next(&st);
   c->n_starts = count;
   for (int i = 0; i < count; i++) c->start_f[i] = (int64_t)(orc_splitmix64_next(&st) % (uint64_t)c->N);
   return 0;
@@ -207,6 +220,14 @@ void orc_bin(const float *x, int64_t N, int64_t B, uint64_t sigma, uint64_t tau,
   out[1] = cimag(v);
 }
 
+/* delay of FFAST measurement i: d = i, or with the R-FFAST set of Sect. 3.2
+   the i-th of r_0, r_0 + 1, ..., r_1, r_1 + 2, ..., r_c + 2^c t, ...  */
+static uint64_t ffast_tau(const orc_cfg *c, int i) {
+  if (c->rf_iters <= 0) return (uint64_t)i;
+  int it = i / c->rf_m, t = i % c->rf_m;
+  return (c->rf_off[it] + ((uint64_t)t << it)) % (uint64_t)c->N;
+}
+
 /* ------------------------------------------------------------------ */
 /* Singleton test of Sect. 3.2, Subproblems 1 and 2.                    */
 
@@ -248,6 +269,44 @@ static int64_t snap_index(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B)
     for (int d = 0; d + 1 < cf->D; d++)
       P += Y[r * cf->D + d + 1] * conj(Y[r * cf->D + d]);
   return lattice_of_phase(cf->N, B, c, atan2(cimag(P), creal(P)));
+}
+
+/* Kay's estimator (Eq. 21-22): the angle of e^{2 pi i f g / N} from m samples
+   y_t spaced g apart, as the weighted mean of the m-1 phase differences
+   Delta_t = angle(y_{t+1} conj y_t) with the parabolic weights
+   w_t = 3m / (2(m^2 - 1)) (1 - ((2t - m + 2) / m)^2). */
+static double kay_phase(const cplx *y, int m) {
+  double th = 0;
+  for (int t = 0; t + 1 < m; t++) {
+    cplx p = y[t + 1] * conj(y[t]);
+    double u = (2.0 * t - m + 2.0) / (double)m;
+    double w = 3.0 * m / (2.0 * ((double)m * m - 1.0)) * (1.0 - u * u);
+    th += w * atan2(cimag(p), creal(p));
+  }
+  return th;
+}
+
+double orc_kay_phase(const double *y, int32_t m) { return kay_phase((const cplx *)y, m); }
+
+/* R-FFAST singleton estimator (Sect. 3.2, Subproblem 2, general case):
+   iteration c estimates the angle of e^{2 pi i 2^c f / N} from its m delays
+   r_c + 2^c t and halves the interval that holds f -- angle in [0, pi): the
+   lower half -- starting from [0, N); the estimate is the lattice point
+   c + kB nearest to the final interval's midpoint. */
+static int64_t rffast_locate(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
+  const orc_cfg *cf = x->c;
+  int64_t N = cf->N, L = N / B;
+  double lo = 0.0, len = (double)N;
+  for (int it = 0; it < cf->rf_iters; it++) {
+    double th = kay_phase(Y + it * cf->rf_m, cf->rf_m);
+    if (th < 0) th += TWO_PI;
+    len *= 0.5;
+    if (th >= TWO_PI / 2) lo += len;
+  }
+  double mid = lo + 0.5 * len;
+  int64_t k = (int64_t)floor((mid - (double)c) / (double)B + 0.5) % L;
+  if (k < 0) k += L;
+  return k;
 }
 
 /* matched filter |sum_i Y_i e^{-2 pi i f tau_i / N}|^2 */
@@ -358,7 +417,9 @@ static verdict classify(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
   if (E2 <= T0sq) return v;
   /* locate */
   int64_t k;
-  if (cf->mode == ORC_EXACT) {
+  if (cf->kind == ORC_FFAST && cf->rf_iters > 0) {
+    k = rffast_locate(x, Y, c, B);
+  } else if (cf->mode == ORC_EXACT) {
     k = snap_index(x, Y, c, B);
   } else {
     int64_t lo, cnt;
@@ -533,7 +594,7 @@ int orc_level0(const orc_cfg *c, const float *x, double *out) {
       int64_t B = c->stageB[j];
       cplx *tw = twiddles(B);
       for (int64_t h = 0; h < B; h++)
-        for (int d = 0; d < c->D; d++) o[h * c->D + d] = bin_tw(x, c->N, B, 1, (uint64_t)d, h, tw);
+        for (int d = 0; d < c->D; d++) o[h * c->D + d] = bin_tw(x, c->N, B, 1, ffast_tau(c, d), h, tw);
       o += B * c->D;
       free(tw);
     }
@@ -681,7 +742,7 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
   cx.c = c;
   cx.rounds = 1;
   cx.n = D;
-  for (int d = 0; d < D; d++) cx.tau[d] = (uint64_t)d;
+  for (int d = 0; d < D; d++) cx.tau[d] = ffast_tau(c, d);
   cx.sref2 = s / (double)(nb * D);
   double phi = 0;
   for (int j = 0; j < S; j++)
@@ -771,7 +832,7 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
       for (int j = 0; j < S; j++) {
         int64_t b = off[j] + nf[i] % c->stageB[j];
         for (int d = 0; d < D; d++) {
-          int64_t t = (int64_t)mulmod((uint64_t)nf[i], (uint64_t)d, (uint64_t)N);
+          int64_t t = (int64_t)mulmod((uint64_t)nf[i], cx.tau[d], (uint64_t)N);
           Y[b * D + d] -= na[i] * unit(t, N, +1);
         }
         modified[b] = 1;

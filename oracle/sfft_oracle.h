@@ -40,6 +40,11 @@ typedef struct {
   double noise_var;    /* > 0: time-domain noise variance given, else estimated */
   int32_t mpp;         /* tree, exact mode: 2 = resolve two-tons by the moment
                           preserving solve (Sect. 3.1, a_m = 2); 0 = off */
+  int32_t rf_iters;    /* FFAST: C > 0 = R-FFAST delays and singleton estimator
+                          (Sect. 3.2, Subproblem 2, general case): D = C * rf_m
+                          delays r_c + 2^c t (c < C, t < rf_m) per stage */
+  int32_t rf_m;
+  uint64_t rf_off[ORC_MAX_ROUNDS];     /* r_c, SplitMix64 draws mod N */
   int32_t n_starts;    /* FFAST: 0 = every bucket in the first peeling (method 1);
                           > 0 = packet-erasure schedule (method 2) grown from the
                           buckets of these start frequencies */
@@ -70,6 +75,13 @@ uint64_t orc_splitmix64_next(uint64_t *state);
 /* start frequencies of the packet-erasure schedule: count SplitMix64 draws
    from seed, each reduced modulo N */
 int orc_draw_starts(orc_cfg *c, uint64_t seed, int32_t count);
+/* R-FFAST delay set of an FFAST plan: C iterations of m delays r_c + 2^c t;
+   r_c are the first C SplitMix64 draws from seed (start frequencies, if any,
+   are drawn after them), each mod N */
+int orc_set_rffast(orc_cfg *c, uint64_t seed, int32_t C, int32_t m);
+/* Kay's weighted phase-difference estimate (Eq. 21-22) from m complex
+   samples (interleaved re, im); returns the angle in (-pi, pi] */
+double orc_kay_phase(const double *y, int32_t m);
 
 /* One bin of the B-point filtered spectrum of Eq. 5-6 (advance shift tau). */
 void orc_bin(const float *x, int64_t N, int64_t B, uint64_t sigma, uint64_t tau,

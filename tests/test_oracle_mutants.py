@@ -41,6 +41,11 @@ MUTANTS = {
     "schedule_start_stage": ("active[off[j] + c->start_f[i] % c->stageB[j]] = 1;",
                              "active[off[j] + c->start_f[i] % c->stageB[0]] = 1;"),
     "schedule_no_stop_at_K": ("if (schedule && fl.n >= c->K) {", "if (schedule && fl.n > c->K) {"),
+    "kay_weight_center": ("double u = (2.0 * t - m + 2.0) / (double)m;",
+                          "double u = (2.0 * t - m) / (double)m;"),
+    "rffast_decision_flipped": ("if (th >= TWO_PI / 2) lo += len;", "if (th < TWO_PI / 2) lo += len;"),
+    "rffast_delay_spacing": ("return (c->rf_off[it] + ((uint64_t)t << it)) % (uint64_t)c->N;",
+                             "return (c->rf_off[it] + ((uint64_t)t << (it + 1))) % (uint64_t)c->N;"),
     "mpp_value_cross_term": ("cplx a0 = (nn * q0 - s01 * q1) / dv;",
                              "cplx a0 = (nn * q0 + s01 * q1) / dv;"),
 }
@@ -138,7 +143,23 @@ def battery(libpath):
         idx, val, cnt, tr = oracle.solve(cfg, x, libpath=libpath)
         return [tr.ident[r] for r in range(tr.levels)] == [3, 2, 1] and np.array_equal(idx, sup)
 
-    for name, fn in [("packet_erasure", packet_erasure), ("aliasing", aliasing), ("exact_tree", exact_tree), ("n20", n20),
+    def rffast():
+        rng = np.random.default_rng(5)
+        y = np.exp(1j * 0.7 * np.arange(8))[None, :] + (rng.standard_normal((4000, 8))
+                                                         + 1j * rng.standard_normal((4000, 8))) * 0.02236
+        est = np.array([oracle.kay_phase(r, libpath=libpath) for r in y])
+        crlb = 6.0 / (1000.0 * 8 * 63)
+        if not (0.8 * crlb < np.var(est - 0.7) < 1.2 * crlb):
+            return False
+        for f in range(20):
+            x = siggen.synth(siggen.make_spec(20, 1, 0, support=[f], values=[1.0]))
+            cfg = oracle.config(20, 1, 2, 2, stageB=[4, 5], rffast=(4, 2), seed=f, libpath=libpath)
+            idx, val, cnt, tr = oracle.solve(cfg, x, libpath=libpath)
+            if idx[0] != f:
+                return False
+        return True
+
+    for name, fn in [("rffast", rffast), ("packet_erasure", packet_erasure), ("aliasing", aliasing), ("exact_tree", exact_tree), ("n20", n20),
                      ("n64", n64), ("splitmix", splitmix), ("topk", topk), ("noisy", noisy),
                      ("two_tons", two_tons)]:
         check(name, fn)

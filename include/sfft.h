@@ -112,6 +112,17 @@ typedef struct {
                               it fits; needs rounds x (delays - 2) >= 2, else
                               SFFT_EINVAL; noisy mode or FFAST: SFFT_EUNSUPPORTED.
                               0 = off (default) */
+  int32_t rf_iters;        /* FFAST: C in 1..16 selects the R-FFAST delay set and singleton
+                              estimator (Sect. 3.2, Subproblem 2, general case): each stage
+                              is measured at the C * rf_m delays r_c + 2^c t (c < C,
+                              t < rf_m; r_c = the first C SplitMix64 draws from `seed`,
+                              each mod N), replacing `delays`; a bucket's frequency is
+                              found by C halvings of [0, N), halving c deciding from the
+                              angle of e^{2 pi i 2^c f / N} estimated by Kay's weighted
+                              phase differences (Eq. 21-22), then snapped to the bucket's
+                              lattice.  Needs rf_m >= 2 and C * rf_m <= 64, else
+                              SFFT_EINVAL; tree plans: SFFT_EUNSUPPORTED.  0 = off */
+  int32_t rf_m;            /* R-FFAST: delays per iteration (m) */
   int32_t peel_starts;     /* FFAST: 0 = genie-assisted peeling, every bucket identified
                               in the first peeling (Sect. 3.2, Subproblem 3, method 1;
                               default).  S in 1..SFFT_MAX_PEEL_STARTS = packet-erasure
@@ -122,8 +133,9 @@ typedef struct {
                               Tree plans: SFFT_EUNSUPPORTED. */
   int64_t peel_start_f[SFFT_MAX_PEEL_STARTS];
                            /* the S start frequencies (each in [0, N)); all -1 (the
-                              default) = S SplitMix64 draws from `seed`, each mod N;
-                              a mix of given and -1 entries: SFFT_EINVAL */
+                              default) = S SplitMix64 draws from `seed` (after the
+                              R-FFAST offsets, if any), each mod N; a mix of given
+                              and -1 entries: SFFT_EINVAL */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -147,6 +159,8 @@ typedef struct {
   int32_t mpp;             /* two-ton solve (2) or off (0) */
   int32_t peel_starts;     /* FFAST schedule: start frequencies (0 = method 1) */
   int64_t peel_start_f[SFFT_MAX_PEEL_STARTS];
+  int32_t rf_iters, rf_m;  /* R-FFAST delay set (rf_iters = 0: delays 0..D-1) */
+  uint64_t rf_off[SFFT_MAX_ROUNDS];   /* r_c */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */

@@ -54,6 +54,7 @@ class Params(ctypes.Structure):
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
         ("mpp", ctypes.c_int32),
+        ("rf_iters", ctypes.c_int32), ("rf_m", ctypes.c_int32),
         ("peel_starts", ctypes.c_int32),
         ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
     ]
@@ -77,6 +78,8 @@ class PlanInfo(ctypes.Structure):
         ("mpp", ctypes.c_int32),
         ("peel_starts", ctypes.c_int32),
         ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
+        ("rf_iters", ctypes.c_int32), ("rf_m", ctypes.c_int32),
+        ("rf_off", ctypes.c_uint64 * MAX_ROUNDS),
     ]
 
 
@@ -177,7 +180,8 @@ class Plan:
     stage_B (explicit co-prime FFAST stages), max_peel_rounds, jump_L, eps0, eps1,
     zero_k, single_k, noise_var, mpp (2 = two-ton moment preserving solve), peel_starts
     (FFAST packet-erasure schedule: number of drawn start frequencies) or peel_start_f
-    (explicit start frequencies)."""
+    (explicit start frequencies), rf_iters and rf_m (FFAST R-FFAST delay set and
+    singleton estimator)."""
 
     def __init__(self, N: int, K: int, stages: int, delays: int, seed: int = 0, **kw):
         p = Params()

@@ -186,6 +186,9 @@ struct BatchCtx {
       d.jump_L = in.kind == SFFT_KIND_TREE ? in.jump_L : 0;
       d.mpp = in.mpp;
       d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
+      d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
+      d.rf_m = in.rf_m;
+      for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.rf_off[r] = in.rf_off[r];
       for (int i = 0; i < SFFT_MAX_PEEL_STARTS; i++) d.start_f[i] = in.peel_start_f[i];
       for (int j = 0; j < SFFT_MAX_STAGES; j++) d.stageB[j] = in.stage_B[j];
       for (int j = 0; j <= SFFT_MAX_STAGES; j++) d.stageOff[j] = p->stage_off[j];
@@ -414,14 +417,23 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
   sfft_plan_info_t &in = pl->info;
   memset(&in, 0, sizeof(in));
   if (p.N < 2 || p.N > kMaxN || p.K < 1 || p.K > p.N || p.K > 4096) return SFFT_EINVAL;
-  if (p.delays < 1 || p.stages < 1) return SFFT_EINVAL;
+  // the R-FFAST delay set replaces the D consecutive delays
+  int32_t delays = p.delays;
+  if (p.rf_iters != 0) {
+    if (pow2(p.N) && p.nstage_B == 0) return SFFT_EUNSUPPORTED;
+    if (p.rf_iters < 1 || p.rf_iters > SFFT_MAX_ROUNDS || p.rf_m < 2 ||
+        (int64_t)p.rf_iters * p.rf_m > kMaxMeas)
+      return SFFT_EINVAL;
+    delays = p.rf_iters * p.rf_m;
+  }
+  if (delays < 1 || p.stages < 1) return SFFT_EINVAL;
   if (p.mode != SFFT_EXACT && p.mode != SFFT_NOISY) return SFFT_EINVAL;
-  if (p.mode == SFFT_EXACT && p.delays < 2) return SFFT_EINVAL;
+  if (p.mode == SFFT_EXACT && delays < 2) return SFFT_EINVAL;
   if (p.window < 0) return SFFT_EINVAL;
   in.N = p.N;
   in.K = p.K;
   in.mode = p.mode;
-  in.D = p.delays;
+  in.D = delays;
   in.window = p.window;
   in.eps0 = p.eps0;
   in.eps1 = p.eps1;
@@ -441,15 +453,15 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
   if (pow2(p.N) && p.nstage_B == 0) {
     // binary tree search over R rounds sharing B0
     if (p.stages > SFFT_MAX_ROUNDS) return SFFT_EINVAL;
-    if ((int64_t)p.stages * p.delays > kMaxMeas) return SFFT_EUNSUPPORTED;
-    if (p.delays > kMaxD) return SFFT_EUNSUPPORTED;
+    if ((int64_t)p.stages * delays > kMaxMeas) return SFFT_EUNSUPPORTED;
+    if (delays > kMaxD) return SFFT_EUNSUPPORTED;
     int64_t B0 = p.B0;
     if (B0 <= 0) B0 = std::min<int64_t>(npow2(2 * p.K), p.N);
     if (!pow2(B0) || B0 > p.N) return SFFT_EINVAL;
     if (B0 > kFftMax) return SFFT_EUNSUPPORTED;
     if (p.peel_starts != 0) return SFFT_EUNSUPPORTED;
     if (p.mpp == 2 && p.mode != SFFT_EXACT) return SFFT_EUNSUPPORTED;
-    if (p.mpp == 2 && (int64_t)p.stages * (p.delays - 2) < 2) return SFFT_EINVAL;
+    if (p.mpp == 2 && (int64_t)p.stages * (delays - 2) < 2) return SFFT_EINVAL;
     in.kind = SFFT_KIND_TREE;
     in.R = p.stages;
     in.B0 = B0;
@@ -467,7 +479,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
       }
     }
     phi = std::pow(1.0 - 1.0 / (double)B0, (double)p.K);
-    cnt = (int64_t)p.stages * p.delays * B0;
+    cnt = (int64_t)p.stages * delays * B0;
   } else {
     // FFAST: co-prime stages, from explicit sizes or the prime powers of N
     std::vector<int64_t> st;
@@ -499,6 +511,10 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     }
     if ((int)st.size() > SFFT_MAX_STAGES) return SFFT_EUNSUPPORTED;
     if (p.mpp != 0) return SFFT_EUNSUPPORTED;
+    SplitMix64 g{p.seed};
+    in.rf_iters = p.rf_iters;
+    in.rf_m = p.rf_iters ? p.rf_m : 0;
+    for (int c = 0; c < p.rf_iters; c++) in.rf_off[c] = g.next() % (uint64_t)p.N;
     if (p.peel_starts < 0 || p.peel_starts > SFFT_MAX_PEEL_STARTS) return SFFT_EINVAL;
     in.peel_starts = p.peel_starts;
     if (p.peel_starts > 0) {
@@ -508,11 +524,10 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
         given += p.peel_start_f[i] >= 0;
       }
       if (given != 0 && given != p.peel_starts) return SFFT_EINVAL;
-      SplitMix64 g{p.seed};
       for (int i = 0; i < p.peel_starts; i++)
         in.peel_start_f[i] = given ? p.peel_start_f[i] : (int64_t)(g.next() % (uint64_t)p.N);
     }
-    if (p.delays > kMaxMeas || p.N >= (int64_t(1) << 31)) return SFFT_EUNSUPPORTED;
+    if (delays > kMaxMeas || p.N >= (int64_t(1) << 31)) return SFFT_EUNSUPPORTED;
     in.kind = SFFT_KIND_FFAST;
     in.R = (int32_t)st.size();
     int64_t off = 0;
@@ -531,7 +546,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     if (off > kMaxFfastBuckets) return SFFT_EUNSUPPORTED;
     pl->nb = off;
     phi = wphi / (double)off;
-    cnt = off * p.delays;
+    cnt = off * delays;
   }
   // noise estimator constants: p-quantile of B |yhat|^2 with p = min(1/4, phi/2)
   const double q = std::min(0.25, phi / 2.0);
@@ -609,6 +624,8 @@ void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages, in
   p->single_k = 4.0;
   p->noise_var = 0.0;
   p->mpp = 0;
+  p->rf_iters = 0;
+  p->rf_m = 0;
   p->peel_starts = 0;
   for (int i = 0; i < SFFT_MAX_PEEL_STARTS; i++) p->peel_start_f[i] = -1;
 }

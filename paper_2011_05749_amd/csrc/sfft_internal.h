@@ -41,6 +41,8 @@ struct SigDesc {
   int32_t found_cap, multi_cap;
   int32_t jump_L;
   int32_t mpp;            // 2: two-ton moment preserving solve of multi-tons
+  int32_t rf_iters, rf_m; // FFAST R-FFAST delay set r_c + 2^c t (rf_iters = 0: delays 0..D-1)
+  uint64_t rf_off[SFFT_MAX_ROUNDS];
   int32_t n_starts;       // FFAST packet-erasure schedule: start frequencies (0: method 1)
   int64_t start_f[SFFT_MAX_PEEL_STARTS];
   int64_t stageB[SFFT_MAX_STAGES];

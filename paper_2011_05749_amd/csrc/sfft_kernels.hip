@@ -69,9 +69,15 @@ __device__ __forceinline__ uint64_t mod_n(uint64_t v, const SigDesc &d) {
   return d.log2N >= 0 ? (v & (uint64_t)(d.N - 1)) : v % (uint64_t)d.N;
 }
 
-// delay of measurement i of a class vector: shift of its round + its delay
+// delay of measurement i of a class vector: shift of its round + its delay;
+// FFAST: delay i, or the i-th of the R-FFAST set r_c + 2^c t (Sect. 3.2)
+template <bool TREE = true>
 __device__ __forceinline__ uint64_t tau_of(const SigDesc &d, int i) {
-  if (d.kind == SFFT_KIND_FFAST) return (uint64_t)i;
+  if (!TREE) {
+    if (d.rf_iters <= 0) return (uint64_t)i;
+    const int c = i / d.rf_m, t = i % d.rf_m;
+    return (d.rf_off[c] + ((uint64_t)t << c)) % (uint64_t)d.N;
+  }
   return mod_n(d.shift[i / d.D] + (uint64_t)(i % d.D), d);
 }
 
@@ -391,7 +397,9 @@ __device__ __forceinline__ void two_ton(const double2 (&Y)[NMAX], const SigDesc 
 
 // Singleton test (Sect. 3.2, Subproblems 1-2) of one class vector Y (n values,
 // rounds x D layout) of class c among B buckets.
-template <int NMAX, bool TWO = true>
+// TREE: the two-ton solve may follow (tree kernels); otherwise the R-FFAST
+// estimator may locate (FFAST kernel) -- each kernel compiles only its own
+template <int NMAX, bool TREE = true>
 __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
                             int64_t c, int64_t B, double sref2, double noise_var) {
   Verdict v;
@@ -420,7 +428,35 @@ __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, i
 
   // phase-to-index (exact-case locator, advance-shift sign)
   int64_t ksnap = 0;
-  if (D >= 2) {
+  const bool rffast = !TREE && d.rf_iters > 0;
+  if (rffast) {
+    // R-FFAST estimator: iteration c estimates the angle of e^{2 pi i 2^c f / N}
+    // by Kay's weighted phase differences of its m delays (Eq. 21-22) and
+    // keeps the lower half of the interval holding f when it lies in [0, pi)
+    const double two_pi = 6.283185307179586476925286766559;
+    const int m = d.rf_m;
+    double lo = 0.0, len = (double)N;
+    for (int it = 0; it < d.rf_iters; it++) {
+      double th = 0.0;
+#pragma unroll
+      for (int i = 0; i + 1 < NMAX; i++) {
+        if (i / m == it && (i % m) + 1 < m) {
+          const double2 a = Y[i + 1], b = Y[i];
+          const double px = a.x * b.x + a.y * b.y, py = a.y * b.x - a.x * b.y;
+          const double u = (2.0 * (double)(i % m) - (double)m + 2.0) / (double)m;
+          const double w = 3.0 * (double)m / (2.0 * ((double)m * (double)m - 1.0)) * (1.0 - u * u);
+          th += w * atan2(py, px);
+        }
+      }
+      if (th < 0) th += two_pi;
+      len *= 0.5;
+      if (th >= 0.5 * two_pi) lo += len;
+    }
+    const double mid = lo + 0.5 * len;
+    int64_t k = (int64_t)floor((mid - (double)c) / (double)B + 0.5) % L;
+    if (k < 0) k += L;
+    ksnap = k;
+  } else if (D >= 2) {
     double2 P = make_double2(0.0, 0.0);
 #pragma unroll
     for (int i = 0; i + 1 < NMAX; i++) {
@@ -433,7 +469,7 @@ __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, i
     ksnap = lattice_k(atan2(P.y, P.x), N, B, c);
   }
   int64_t k = ksnap;
-  if (d.mode == SFFT_NOISY) {
+  if (d.mode == SFFT_NOISY && !rffast) {
     // enumeration of the candidates c + kB (Sect. 3.1, Method 2) by the
     // matched filter |sum_i Y_i e^{-2 pi i (c + kB) tau_i / N}|, FP32 MACs,
     // twiddles re-anchored exactly every 32 candidates
@@ -456,7 +492,7 @@ __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, i
 #pragma unroll
       for (int i = 0; i < NMAX; i++) {
         if (i < n) {
-          const uint64_t ti = tau_of(d, i);
+          const uint64_t ti = tau_of<TREE>(d, i);
           const double2 a = unit_d(mod_n(f0 * ti, d), (uint64_t)N, -1);
           const double2 b = unit_d(mod_n(mod_n((uint64_t)B * ti, d), d), (uint64_t)N, -1);
           tw[i] = make_float2((float)a.x, (float)a.y);
@@ -492,7 +528,7 @@ __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, i
 #pragma unroll
   for (int i = 0; i < NMAX; i++) {
     if (i < n) {
-      e[i] = unit_d(mod_n((uint64_t)f * tau_of(d, i), d), (uint64_t)N, -1);
+      e[i] = unit_d(mod_n((uint64_t)f * tau_of<TREE>(d, i), d), (uint64_t)N, -1);
       const double2 t = cmul(Y[i], e[i]);
       a.x += t.x;
       a.y += t.y;
@@ -512,7 +548,7 @@ __device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, i
   v.f = f;
   v.a = a;
   v.cls = (rho2 <= T1sq) ? kSingle : kMulti;
-  if (TWO && v.cls == kMulti && d.mpp == 2) two_ton<NMAX>(Y, d, n, rounds, c, B, T0sq, T1sq, v);
+  if (TREE && v.cls == kMulti && d.mpp == 2) two_ton<NMAX>(Y, d, n, rounds, c, B, T0sq, T1sq, v);
   return v;
 }
 
@@ -720,8 +756,9 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
         }
       }
       for (int dl = 0; dl < D; dl++) {
+        const uint64_t tdl = tau_of<false>(d, dl);
         for (int64_t m = threadIdx.x; m < B; m += blockDim.x) {
-          const uint64_t pos = ((uint64_t)m * (uint64_t)L + (uint64_t)dl) % (uint64_t)N;
+          const uint64_t pos = ((uint64_t)m * (uint64_t)L + tdl) % (uint64_t)N;
           lds[lb >= 0 ? (int64_t)bitrev((uint32_t)m, lb) : m] = ldg(x + pos);
         }
         __syncthreads();
@@ -898,7 +935,7 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
           if (f % Bj != h) continue;
           const double2 a = c.A.found_a[d.found_off + nfound + q];
           for (int dl = 0; dl < D; dl++) {
-            const double2 r = cmul(a, unit_d(((uint64_t)f * (uint64_t)dl) % (uint64_t)N, (uint64_t)N, +1));
+            const double2 r = cmul(a, unit_d(((uint64_t)f * tau_of<false>(d, dl)) % (uint64_t)N, (uint64_t)N, +1));
             Yf[(int64_t)b * D + dl].x -= r.x;
             Yf[(int64_t)b * D + dl].y -= r.y;
           }

@@ -133,6 +133,22 @@ def test_peel_schedule_validation():
     assert sfft._lib.sfft_last_error() == -1
 
 
+def test_rffast_plan_matches_oracle_and_validates():
+    p = sfft.Plan(10800, 10, 3, 2, seed=99, rf_iters=5, rf_m=3, peel_starts=2)
+    c = oracle.config(10800, 10, 3, 2, seed=99, rffast=(5, 3), peel_starts=2)
+    assert p.info.D == c.D == 15 and p.info.rf_iters == 5 and p.info.rf_m == 3
+    assert [p.info.rf_off[i] for i in range(5)] == [c.rf_off[i] for i in range(5)]
+    assert [p.info.peel_start_f[i] for i in range(2)] == [c.start_f[i] for i in range(2)]
+    for kw, code in [({"rf_iters": 17, "rf_m": 2}, -1), ({"rf_iters": 4, "rf_m": 1}, -1),
+                     ({"rf_iters": 11, "rf_m": 6}, -1)]:
+        with pytest.raises(sfft.SfftError) as e:
+            sfft.Plan(10800, 10, 3, 2, **kw)
+        assert e.value.code == code
+    with pytest.raises(sfft.SfftError) as e:
+        sfft.Plan(1024, 10, 2, 2, rf_iters=4, rf_m=2)
+    assert e.value.code == -2
+
+
 def test_noisy_plan_allows_one_delay_and_window():
     p = sfft.Plan(2 ** 16, 32, 4, 1, seed=1, mode="noisy", window=16)
     assert p.info.mode == sfft.NOISY and p.info.D == 1 and p.info.window == 16

@@ -50,6 +50,8 @@ def solve_both(sfft, x, N, K, stages, delays, seed=0, **kw):
             ocfg_kw[k] = ok[k]
     if "peel_start_f" in ok:
         ocfg_kw["start_f"] = ok["peel_start_f"]
+    if ok.get("rf_iters"):
+        ocfg_kw["rffast"] = (ok["rf_iters"], ok["rf_m"])
     cfg = oracle_cfg(N, K, stages, delays, seed=seed, mode=mode, B0=kw.get("B0", 0),
                      identity_round0=bool(kw.get("identity_round0", 0)),
                      stage_B=kw.get("stage_B"), **ocfg_kw)

@@ -12,7 +12,8 @@ Every signal's result is checked against its planted support.  A second
 plan shape of the same signals -- 2 rounds x 4 delays with the two-ton moment
 preserving solve (Sect. 3.1) inside the tree -- is timed as "variants", as are
 2048 FFAST signals (N = 10800, K = 10) decoded by the genie-assisted peeling
-and by the packet-erasure schedule (Sect. 3.2, Subproblem 3).
+and by the packet-erasure schedule (Sect. 3.2, Subproblem 3), and 2048 at
+20 dB located by the R-FFAST estimator and by enumeration.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -137,27 +138,53 @@ def run_ffast_c1(sfft, torch, np, nsig, steps, warmup, dev):
     xs = [torch.from_numpy(siggen.synth(sp)).to(dev) for sp in specs]
     out = {}
     for name, kw in (("method1", {}), ("schedule", {"peel_starts": K})):
-        plans = [sfft.Plan(N, K, 3, 2, seed=s, **kw) for s in seeds]
-        b = sfft.Batch(plans, xs)
-        for _ in range(warmup):
-            b.run(graph=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            b.run(graph=True)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        counts = b.counts.cpu().numpy()
-        ok = sum(int(counts[i] == K and np.array_equal(b.idxs[i].cpu().numpy(), siggen.truth(sp)[0]))
-                 for i, sp in enumerate(specs))
-        st = [b.stats(i) for i in range(nsig)]
-        out[name] = {"value": round(nsig / dt, 1), "unit": "spectra/s", "ms_per_batch": round(dt * 1e3, 4),
-                     "identifications_per_solve": float(np.mean([s["ident"] for s in st])),
-                     "peeling_rounds_mean": float(np.mean([s["levels"] for s in st])),
-                     "verified": f"{ok}/{nsig} signals: exact support, count K", **kw}
-        del b
-        sfft.release_batches()
+        out[name] = _time_plans(sfft, torch, np, [sfft.Plan(N, K, 3, 2, seed=s, **kw) for s in seeds],
+                                xs, specs, K, steps, warmup, **kw)
     return out
+
+
+def run_ffast_noisy(sfft, torch, np, nsig, steps, warmup, dev):
+    """Config-1 FFAST signals at 20 dB: the R-FFAST estimator (C = 11
+    iterations x m = 4 delays) against the enumeration of all L candidates
+    with the same number (44) of consecutive delays."""
+    import siggen
+    N, K, C, m = 10800, 10, 11, 4
+    seeds = [30000 + i for i in range(nsig)]
+    specs = [siggen.make_spec(N, K, s, snr_db=20.0) for s in seeds]
+    xs = [torch.from_numpy(siggen.synth(sp)).to(dev) for sp in specs]
+    out = {}
+    for name, D, kw in (("rffast", 2, {"rf_iters": C, "rf_m": m}), ("enumeration", C * m, {})):
+        plans = [sfft.Plan(N, K, 3, D, seed=s, mode="noisy", **kw) for s in seeds]
+        out[name] = _time_plans(sfft, torch, np, plans, xs, specs, K, steps, warmup,
+                                delays=C * m, **kw)
+    return out
+
+
+def _time_plans(sfft, torch, np, plans, xs, specs, K, steps, warmup, **extra):
+    """spectra/s of one captured batch of `plans`, and how many results are
+    exactly the planted spectrum."""
+    import siggen
+    nsig = len(plans)
+    b = sfft.Batch(plans, xs)
+    for _ in range(warmup):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    counts = b.counts.cpu().numpy()
+    ok = sum(int(counts[i] == K and np.array_equal(b.idxs[i].cpu().numpy(), siggen.truth(sp)[0]))
+             for i, sp in enumerate(specs))
+    st = [b.stats(i) for i in range(nsig)]
+    res = {"value": round(nsig / dt, 1), "unit": "spectra/s", "ms_per_batch": round(dt * 1e3, 4),
+           "identifications_per_solve": float(np.mean([s["ident"] for s in st])),
+           "peeling_rounds_mean": float(np.mean([s["levels"] for s in st])),
+           "verified": f"{ok}/{nsig} signals: exact support, count K", **extra}
+    del b
+    sfft.release_batches()
+    return res
 
 
 def main():
@@ -287,6 +314,8 @@ def main():
         print("bench: FFAST peeling schedules", file=sys.stderr, flush=True)
         variants["ffast_n10800_k10_batch2048"] = run_ffast_c1(sfft, torch, np, 2048, args.steps,
                                                               args.warmup, dev)
+        variants["ffast_n10800_k10_20db_batch2048"] = run_ffast_noisy(sfft, torch, np, 2048,
+                                                                      args.steps, args.warmup, dev)
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None

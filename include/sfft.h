@@ -174,6 +174,7 @@ typedef struct {
   double sref2;            /* mean level-0 bucket power */
   uint64_t level_mask;     /* tree: bit l set when level l gathered samples */
   int64_t ident;           /* FFAST: bucket identifications over all peeling rounds */
+  int64_t h2d_bytes;       /* sfft_exec_host: sample bytes copied to the device */
 } sfft_stats_t;
 
 /* Defaults for (N, K, stages, delays, seed). */
@@ -192,6 +193,24 @@ void sfft_destroy(sfft_plan_t plan);
    out_idx: device int64[K]; out_val: device complex64[K].  Entries [count, K)
    are padded with index -1 and value 0.  Returns count >= 0 or SFFT_E*. */
 int64_t sfft_exec(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val);
+
+/* Solve of a HOST-resident signal, for callers whose signals are not on the
+   device: only the samples the solve reads cross to the device -- R*D*B0 at
+   level 0, R*D*B' at each tree level it opens, D*sum B_j for FFAST (Sect. 2.2:
+   a round costs B samples) -- instead of all N.  The samples are gathered on
+   the host (up to 16 threads), copied through a pinned staging buffer and
+   scattered into a device image of x on which the kernels of sfft_exec run,
+   level by level: the host waits for each tree level's scheduling to learn
+   whether the next level opens (one synchronisation per level).  The dense
+   subtree pass is not used (it reads all of x); results otherwise follow the
+   same rules as sfft_exec.  x: HOST complex64[N]; out_idx: HOST int64[K];
+   out_val: HOST complex64[K] (pageable or pinned; device pointers are
+   rejected with SFFT_EINVAL); stats: optional host record of the solve,
+   with h2d_bytes set.  Synchronous, on an internal stream.  Returns count or
+   SFFT_E*.  The plan keeps a device image of N samples and the staging
+   buffers until sfft_destroy. */
+int64_t sfft_exec_host(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val,
+                       sfft_stats_t *stats);
 
 /* Asynchronous solve on `stream` (a hipStream_t; NULL = null stream).
    d_count: device int64[1], d_status: device int32[1] receive the result. */

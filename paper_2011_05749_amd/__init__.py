@@ -89,6 +89,7 @@ class Stats(ctypes.Structure):
         ("samples", ctypes.c_int64), ("found", ctypes.c_int64),
         ("noise_var", ctypes.c_double), ("sref2", ctypes.c_double),
         ("level_mask", ctypes.c_uint64), ("ident", ctypes.c_int64),
+        ("h2d_bytes", ctypes.c_int64),
     ]
 
 
@@ -111,6 +112,8 @@ _lib.sfft_destroy.argtypes = [_vp]
 _lib.sfft_destroy.restype = None
 _lib.sfft_exec.argtypes = [_vp, _vp, _vp, _vp]
 _lib.sfft_exec.restype = ctypes.c_int64
+_lib.sfft_exec_host.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(Stats)]
+_lib.sfft_exec_host.restype = ctypes.c_int64
 _lib.sfft_exec_async.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.sfft_exec_async.restype = ctypes.c_int32
 _lib.sfft_exec_batch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp]
@@ -135,7 +138,7 @@ _lib.sfft_strerror.argtypes = [ctypes.c_int32]
 _lib.sfft_strerror.restype = ctypes.c_char_p
 
 EXPORTS = ["sfft_params_init", "sfft_plan", "sfft_plan_ex", "sfft_plan_info", "sfft_destroy",
-           "sfft_exec", "sfft_exec_async", "sfft_exec_batch", "sfft_exec_batch_ex",
+           "sfft_exec", "sfft_exec_host", "sfft_exec_async", "sfft_exec_batch", "sfft_exec_batch_ex",
            "sfft_exec_batch_profile",
            "sfft_bucketize", "sfft_exec_stats", "sfft_batch_stats", "sfft_release_batches",
            "sfft_last_error", "sfft_strerror"]
@@ -242,6 +245,21 @@ class Plan:
         vp = _dev_ptr(out_val, "complex64", self.K, "out_val")
         cnt = _check(_lib.sfft_exec(self._h, xp, ip, vp), "sfft_exec")
         return out_idx, out_val, int(cnt)
+
+    def exec_host(self, x):
+        """Solve of a host-resident signal (numpy complex64[N]); only the samples
+        the solve reads are copied to the device.  Returns (idx int64[K],
+        val complex64[K], count, stats) as numpy arrays and a dict."""
+        import numpy as np
+        x = np.ascontiguousarray(x, dtype=np.complex64)
+        if x.shape != (self.N,):
+            raise SfftError(-1, f"x must be complex64[{self.N}]")
+        idx = np.empty(self.K, dtype=np.int64)
+        val = np.empty(self.K, dtype=np.complex64)
+        st = Stats()
+        cnt = _check(_lib.sfft_exec_host(self._h, x.ctypes.data, idx.ctypes.data, val.ctypes.data,
+                                         ctypes.byref(st)), "sfft_exec_host")
+        return idx, val, int(cnt), {f: getattr(st, f) for f, _ in Stats._fields_}
 
     def exec_async(self, x, out_idx, out_val, d_count, d_status, stream=None):
         _check(_lib.sfft_exec_async(

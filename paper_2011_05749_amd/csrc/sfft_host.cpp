@@ -8,6 +8,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "sfft_internal.h"
@@ -61,6 +62,7 @@ uint64_t gcd64(uint64_t a, uint64_t b) {
 }
 
 struct BatchCtx;
+struct HostCtx;
 
 }  // namespace
 
@@ -71,6 +73,7 @@ struct sfft_plan_s {
   double noise_p_den;
   int64_t noise_at;
   std::unique_ptr<BatchCtx> single;
+  std::unique_ptr<HostCtx> host;   // host-gather solves (sfft_exec_host)
 };
 
 namespace {
@@ -155,7 +158,7 @@ struct BatchCtx {
     if (io_pinned) (void)hipHostFree(io_pinned);
   }
 
-  int32_t build(const std::vector<const sfft_plan_s *> &ps) {
+  int32_t build(const std::vector<const sfft_plan_s *> &ps, bool no_jump = false) {
     plans = ps;
     nsig = (int)ps.size();
     if (hipGetDevice(&device) != hipSuccess) return SFFT_EDEVICE;
@@ -183,7 +186,7 @@ struct BatchCtx {
       d.max_peel_rounds = in.max_peel_rounds;
       d.found_cap = in.found_cap;
       d.multi_cap = in.multi_cap;
-      d.jump_L = in.kind == SFFT_KIND_TREE ? in.jump_L : 0;
+      d.jump_L = (in.kind == SFFT_KIND_TREE && !no_jump) ? in.jump_L : 0;
       d.mpp = in.mpp;
       d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
       d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
@@ -597,6 +600,116 @@ int32_t run_single(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_
   return SFFT_OK;
 }
 
+// ------------------------------------------------------- host-gather solves
+// A host-resident signal is solved with only the samples each step reads
+// crossing to the device: the host packs them in (round or stage, m, delay)
+// order, k_scatter writes them to their positions in a device image of x,
+// and the usual kernels run on that image (the dense pass, which reads all
+// of x, is switched off).  Tree levels are decided one at a time: after a
+// level's scheduling the host reads whether the next level has open classes.
+struct HostCtx {
+  int device = -1;
+  BatchCtx b;
+  DevBuf img, packed, res;
+  float2 *staging = nullptr;   // pinned host buffer of `cap` samples
+  uint64_t *word = nullptr;    // pinned host word for the level mask
+  size_t cap = 0;
+  hipStream_t stream = nullptr;
+  ~HostCtx() {
+    if (staging) (void)hipHostFree(staging);
+    if (word) (void)hipHostFree(word);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+  int32_t reserve(size_t n) {
+    if (n <= cap) return SFFT_OK;
+    if (staging) (void)hipHostFree(staging);
+    staging = nullptr;
+    cap = 0;
+    if (hipHostMalloc((void **)&staging, n * sizeof(float2), 0) != hipSuccess) return SFFT_ENOMEM;
+    if (packed.alloc(n * sizeof(float2)) != hipSuccess) return SFFT_ENOMEM;
+    cap = n;
+    return SFFT_OK;
+  }
+};
+
+// samples read by tree level `level` (FFAST: its stages, level 0)
+int64_t level_samples(const sfft_plan_s *p, int level) {
+  const sfft_plan_info_t &in = p->info;
+  if (in.kind == SFFT_KIND_FFAST) return p->nb * in.D;
+  const int64_t Bp = level == 0 ? in.B0 : (in.B0 << (level - 1));
+  return (int64_t)in.R * in.D * Bp;
+}
+
+// position in x of packed sample i of `level` (the order k_scatter writes)
+inline uint64_t sample_pos(const sfft_plan_s *p, int level, int lgB0, int64_t i) {
+  const sfft_plan_info_t &in = p->info;
+  const uint64_t N = (uint64_t)in.N;
+  const int dl = (int)(i % in.D);
+  const int64_t rm = i / in.D;
+  if (in.kind == SFFT_KIND_FFAST) {
+    int j = 0;
+    while (j + 1 < in.R && p->stage_off[j + 1] <= rm) j++;
+    const uint64_t m = (uint64_t)(rm - p->stage_off[j]);
+    uint64_t tau = (uint64_t)dl;
+    if (in.rf_iters > 0) {
+      const int c = dl / in.rf_m, t = dl % in.rf_m;
+      tau = (in.rf_off[c] + ((uint64_t)t << c)) % N;
+    }
+    return (m * (N / (uint64_t)in.stage_B[j]) + tau) % N;
+  }
+  const int lb = lgB0 + (level > 0 ? level - 1 : 0);
+  const uint64_t Bp = (uint64_t)1 << lb, Lp = N >> lb;
+  const int r = (int)(rm >> lb);
+  const uint64_t m = (uint64_t)rm & (Bp - 1);
+  return (m * Lp + (level > 0 ? (Lp >> 1) : 0) + in.shift[r] + (uint64_t)dl) & (N - 1);
+}
+
+void gather_samples(const sfft_plan_s *p, int level, const float2 *x, float2 *out, int64_t n) {
+  const int lgB0 = p->info.kind == SFFT_KIND_TREE ? ilog2(p->info.B0) : 0;
+  auto work = [&](int64_t a, int64_t b) {
+    for (int64_t i = a; i < b; i++) out[i] = x[sample_pos(p, level, lgB0, i)];
+  };
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const int64_t nt = n < (int64_t(1) << 16) ? 1 : (int64_t)hw;
+  if (nt == 1) {
+    work(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nt; t++) th.emplace_back(work, n * t / nt, n * (t + 1) / nt);
+  for (auto &t : th) t.join();
+}
+
+HostCtx *host_ctx(sfft_plan_t plan, int32_t *rc) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *rc = SFFT_EDEVICE;
+    return nullptr;
+  }
+  if (!plan->host || plan->host->device != dev) {
+    std::unique_ptr<HostCtx> h(new HostCtx());
+    h->device = dev;
+    int32_t r = h->b.build({plan}, /*no_jump=*/true);
+    const int64_t K = plan->info.K;
+    if (r == SFFT_OK &&
+        (h->img.alloc(sizeof(float2) * (size_t)plan->info.N) != hipSuccess ||
+         h->res.alloc((sizeof(int64_t) + sizeof(float2)) * (size_t)K + 16) != hipSuccess ||
+         hipHostMalloc((void **)&h->word, sizeof(uint64_t), 0) != hipSuccess))
+      r = SFFT_ENOMEM;
+    if (r == SFFT_OK && (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess ||
+                         hipMemsetAsync(h->img.p, 0, sizeof(float2) * (size_t)plan->info.N, h->stream) !=
+                             hipSuccess))
+      r = SFFT_EDEVICE;
+    if (r != SFFT_OK) {
+      *rc = r;
+      return nullptr;
+    }
+    plan->host = std::move(h);
+  }
+  *rc = SFFT_OK;
+  return plan->host.get();
+}
+
 }  // namespace
 
 // ================================================================== C-ABI
@@ -839,6 +952,73 @@ static void fill_stats(const SigState &st, const SigDesc &d, int64_t count, int3
   out->sref2 = st.sref2;
   out->level_mask = st.level_mask;
   out->ident = d.kind == SFFT_KIND_FFAST ? st.ident : 0;
+  out->h2d_bytes = 0;
+}
+
+int64_t sfft_exec_host(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val,
+                       sfft_stats_t *stats) {
+  if (!plan || !x || !out_idx || !out_val) return fail(SFFT_EINVAL);
+  if (is_device_ptr(x) || is_device_ptr(out_idx) || is_device_ptr(out_val)) return fail(SFFT_EINVAL);
+  int32_t rc;
+  HostCtx *h = host_ctx(plan, &rc);
+  if (!h) return fail(rc);
+  BatchCtx &b = h->b;
+  const int64_t K = plan->info.K;
+  LaunchCtx c = b.lc;
+  c.io = nullptr;
+  c.io1.x = (const float2 *)h->img.p;
+  c.io1.idx = (int64_t *)h->res.p;
+  c.io1.val = (float2 *)((int64_t *)h->res.p + K);
+  c.io1.count = (int64_t *)b.b_out.p;
+  c.io1.status = (int32_t *)((int64_t *)b.b_out.p + 2);
+  const hipStream_t s = h->stream;
+  const float2 *xh = (const float2 *)x;
+  int64_t moved = 0;
+  auto stage = [&](int level) -> int32_t {
+    const int64_t n = level_samples(plan, level);
+    const int32_t r = h->reserve((size_t)n);
+    if (r != SFFT_OK) return r;
+    gather_samples(plan, level, xh, h->staging, n);
+    if (hipMemcpyAsync(h->packed.p, h->staging, sizeof(float2) * (size_t)n, hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        launch_scatter(c.desc, level, (const float2 *)h->packed.p, n, (float2 *)h->img.p, s) != hipSuccess)
+      return SFFT_EDEVICE;
+    moved += n * (int64_t)sizeof(float2);
+    return SFFT_OK;
+  };
+  if ((rc = stage(0)) != SFFT_OK) return fail(rc);
+  if (launch_reset(c, s) != hipSuccess || launch_level0(c, s) != hipSuccess) return fail(SFFT_EDEVICE);
+  for (size_t i = 0; i < b.levels.size(); i++) {
+    const int l = (int)i + 1;
+    const LevelLaunch &L = b.levels[i];
+    // the level's samples are fetched only if the scheduler opened it
+    if (launch_sched(c, l, s) != hipSuccess ||
+        hipMemcpyAsync(h->word, &c.st[0].level_mask, sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return fail(SFFT_EDEVICE);
+    if (!((*h->word >> l) & 1ull)) break;
+    if ((rc = stage(l)) != SFFT_OK) return fail(rc);
+    if ((L.fft && launch_expand_fft(c, l, L.grid_fft, s) != hipSuccess) ||
+        (L.direct && launch_expand_direct(c, l, L.grid_direct, s) != hipSuccess) ||
+        (L.children && launch_children(c, l, L.grid_children, s) != hipSuccess))
+      return fail(SFFT_EDEVICE);
+  }
+  int64_t cnt = 0;
+  int32_t status = 0;
+  SigState st;
+  if (launch_finalize(c, s) != hipSuccess ||
+      hipMemcpyAsync(out_idx, c.io1.idx, sizeof(int64_t) * (size_t)K, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(out_val, c.io1.val, sizeof(float2) * (size_t)K, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&cnt, c.io1.count, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&status, c.io1.status, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&st, b.b_st.p, sizeof(SigState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return fail(SFFT_EDEVICE);
+  if (stats) {
+    fill_stats(st, b.desc[0], cnt, status, stats);
+    stats->h2d_bytes = moved;
+  }
+  return cnt;
 }
 
 int32_t sfft_exec_stats(sfft_plan_t plan, sfft_stats_t *out) {

@@ -127,5 +127,9 @@ hipError_t launch_jump_resolve(const LaunchCtx &c, int level, int grid, hipStrea
 hipError_t launch_finalize(const LaunchCtx &c, hipStream_t s);
 // level-0 class vectors in class-major order (tree: out[c*n + i]; FFAST as stored)
 hipError_t launch_export_level0(const LaunchCtx &c, void *out, hipStream_t s);
+// host-gather form: write `count` packed samples of tree level `level` (or of
+// the FFAST stages, level 0) to their positions in the device image of x
+hipError_t launch_scatter(const SigDesc *d_desc, int level, const float2 *packed, int64_t count,
+                          float2 *image, hipStream_t s);
 
 }  // namespace sfft

@@ -1679,6 +1679,45 @@ hipError_t launch_export_level0(const LaunchCtx &c, void *out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Host-gather form of a solve: the samples that tree level `level` (or the
+// FFAST stages) read arrive packed in (round or stage, m, delay) order and
+// are written to the positions the level's kernels read in the device image
+// of x -- level 0: m L0 + s_r + d (m < B0); level l >= 1: the odd offsets
+// m L' + L'/2 + s_r + d (m < B' = B0 2^{l-1}); FFAST stage j: m L_j + tau_d.
+__global__ __launch_bounds__(kThreads) void k_scatter(const SigDesc *desc, int level,
+                                                      const float2 *__restrict__ packed,
+                                                      int64_t count, float2 *image) {
+  const SigDesc &d = *desc;
+  const uint64_t N = (uint64_t)d.N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int dl = (int)(i % d.D);
+    const int64_t rm = i / d.D;
+    uint64_t pos;
+    if (d.kind == SFFT_KIND_FFAST) {
+      int j = 0;
+      while (j + 1 < d.nstages && d.stageOff[j + 1] <= rm) j++;
+      const uint64_t m = (uint64_t)(rm - d.stageOff[j]);
+      pos = (m * (N / (uint64_t)d.stageB[j]) + tau_of<false>(d, dl)) % N;
+    } else {
+      const int lb = d.log2B0 + (level > 0 ? level - 1 : 0);
+      const uint64_t Bp = (uint64_t)1 << lb, Lp = N >> lb;
+      const int r = (int)(rm >> lb);
+      const uint64_t m = (uint64_t)rm & (Bp - 1);
+      pos = (m * Lp + (level > 0 ? (Lp >> 1) : 0) + d.shift[r] + (uint64_t)dl) & (N - 1);
+    }
+    image[pos] = packed[i];
+  }
+}
+
+hipError_t launch_scatter(const SigDesc *d_desc, int level, const float2 *packed, int64_t count,
+                          float2 *image, hipStream_t s) {
+  const int64_t blocks = (count + kThreads - 1) / kThreads;
+  const int grid = (int)(blocks < 8192 ? (blocks > 0 ? blocks : 1) : 8192);
+  hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(kThreads), 0, s, d_desc, level, packed, count, image);
+  return hipGetLastError();
+}
+
 static int nmax_bucket(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : 64); }
 
 // kernels whose dynamic LDS can exceed 64 KiB declare the gfx950 maximum once

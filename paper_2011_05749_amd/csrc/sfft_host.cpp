@@ -4,7 +4,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -607,9 +609,62 @@ int32_t run_single(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_
 // and the usual kernels run on that image (the dense pass, which reads all
 // of x, is switched off).  Tree levels are decided one at a time: after a
 // level's scheduling the host reads whether the next level has open classes.
+// A fixed set of worker threads that split an index range [0, n) between
+// them and the calling thread; kept for the life of a host-gather context.
+struct GatherPool {
+  std::vector<std::thread> th;
+  std::mutex mu;
+  std::condition_variable cv, done;
+  std::function<void(int64_t, int64_t)> job;
+  int64_t n = 0;
+  uint64_t gen = 0;
+  int pending = 0;
+  bool stop = false;
+  int parts = 1;
+  explicit GatherPool(int workers) : parts(workers + 1) {
+    for (int w = 0; w < workers; w++) th.emplace_back([this, w] { loop(w + 1); });
+  }
+  ~GatherPool() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    for (auto &t : th) t.join();
+  }
+  void loop(int part) {
+    uint64_t seen = 0;
+    for (;;) {
+      std::unique_lock<std::mutex> lk(mu);
+      cv.wait(lk, [&] { return stop || gen != seen; });
+      if (stop) return;
+      seen = gen;
+      const int64_t a = n * part / parts, b = n * (part + 1) / parts;
+      lk.unlock();
+      job(a, b);
+      lk.lock();
+      if (--pending == 0) done.notify_one();
+    }
+  }
+  void run(int64_t count, const std::function<void(int64_t, int64_t)> &f) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      job = f;
+      n = count;
+      pending = (int)th.size();
+      gen++;
+    }
+    cv.notify_all();
+    f(0, count / parts);
+    std::unique_lock<std::mutex> lk(mu);
+    done.wait(lk, [&] { return pending == 0; });
+  }
+};
+
 struct HostCtx {
   int device = -1;
   BatchCtx b;
+  std::unique_ptr<GatherPool> pool;
   DevBuf img, packed, res;
   float2 *staging = nullptr;   // pinned host buffer of `cap` samples
   uint64_t *word = nullptr;    // pinned host word for the level mask
@@ -664,20 +719,17 @@ inline uint64_t sample_pos(const sfft_plan_s *p, int level, int lgB0, int64_t i)
   return (m * Lp + (level > 0 ? (Lp >> 1) : 0) + in.shift[r] + (uint64_t)dl) & (N - 1);
 }
 
-void gather_samples(const sfft_plan_s *p, int level, const float2 *x, float2 *out, int64_t n) {
+void gather_samples(const sfft_plan_s *p, int level, const float2 *x, float2 *out, int64_t n,
+                    GatherPool *pool) {
   const int lgB0 = p->info.kind == SFFT_KIND_TREE ? ilog2(p->info.B0) : 0;
   auto work = [&](int64_t a, int64_t b) {
     for (int64_t i = a; i < b; i++) out[i] = x[sample_pos(p, level, lgB0, i)];
   };
-  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  const int64_t nt = n < (int64_t(1) << 16) ? 1 : (int64_t)hw;
-  if (nt == 1) {
+  if (!pool || n < (int64_t(1) << 13)) {
     work(0, n);
     return;
   }
-  std::vector<std::thread> th;
-  for (int64_t t = 0; t < nt; t++) th.emplace_back(work, n * t / nt, n * (t + 1) / nt);
-  for (auto &t : th) t.join();
+  pool->run(n, work);
 }
 
 HostCtx *host_ctx(sfft_plan_t plan, int32_t *rc) {
@@ -689,6 +741,9 @@ HostCtx *host_ctx(sfft_plan_t plan, int32_t *rc) {
   if (!plan->host || plan->host->device != dev) {
     std::unique_ptr<HostCtx> h(new HostCtx());
     h->device = dev;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int workers = (int)std::min(15u, hw > 1 ? hw - 1 : 0u);
+    if (workers > 0) h->pool.reset(new GatherPool(workers));
     int32_t r = h->b.build({plan}, /*no_jump=*/true);
     const int64_t K = plan->info.K;
     if (r == SFFT_OK &&
@@ -978,7 +1033,7 @@ int64_t sfft_exec_host(sfft_plan_t plan, const void *x, int64_t *out_idx, void *
     const int64_t n = level_samples(plan, level);
     const int32_t r = h->reserve((size_t)n);
     if (r != SFFT_OK) return r;
-    gather_samples(plan, level, xh, h->staging, n);
+    gather_samples(plan, level, xh, h->staging, n, h->pool.get());
     if (hipMemcpyAsync(h->packed.p, h->staging, sizeof(float2) * (size_t)n, hipMemcpyHostToDevice, s) !=
             hipSuccess ||
         launch_scatter(c.desc, level, (const float2 *)h->packed.p, n, (float2 *)h->img.p, s) != hipSuccess)

@@ -367,3 +367,42 @@ def test_config4_precision_shape(sfft):
     l0, l1, l2 = _l_errors(g[0], g[1], *siggen.truth(sp))
     print(f"config4: L0={l0} L1={l1:.3e} L2={l2:.3e} count={g[2]}")
     assert l2 < 0.05
+
+
+def test_config5_serving_mix(sfft):
+    """24 requests of the serving mix: N uniform on {2^16, ..., 2^24}, K
+    log-uniform on [16, 4096], SNR uniform on [10, 40] dB, B0 = next pow2 >=
+    2K, 4 rounds x 2 delays, noisy mode, all in one batch (graph replay).
+    Every request against its planted spectrum; those the oracle finishes in
+    seconds (N <= 2^18, or N = 2^20 with K < 1024) against the oracle, with
+    indices bit-exact."""
+    rng = np.random.default_rng(7000)
+    reqs = []
+    for i in range(24):
+        N = 2 ** int(rng.choice([16, 18, 20, 22, 24]))
+        K = int(round(np.exp(rng.uniform(np.log(16), np.log(4096)))))
+        reqs.append((N, K, float(rng.uniform(10, 40))))
+    plans, xs, specs = [], [], []
+    for i, (N, K, snr) in enumerate(reqs):
+        B0 = min(1 << max(0, (2 * K - 1).bit_length()), N)
+        sp = siggen.make_spec(N, K, 7000 + i, snr_db=snr)
+        specs.append(sp)
+        xs.append(siggen.synth_torch(sp, torch.device("cuda")))
+        plans.append(sfft.Plan(N, K, 4, 2, seed=7000 + i, B0=B0, mode="noisy"))
+    b = sfft.Batch(plans, xs)
+    for _ in range(2):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    exact = 0
+    for i, sp in enumerate(specs):
+        gi = b.idxs[i].cpu().numpy()
+        exact += int(np.array_equal(gi, siggen.truth(sp)[0]))
+        N, K, snr = reqs[i]
+        if N <= 2 ** 18 or (N == 2 ** 20 and K < 1024):
+            cfg = oracle_cfg(N, K, 4, 2, seed=7000 + i, mode=1, B0=int(plans[i].info.B0))
+            oi, ov, oc, tr = oracle.solve(cfg, xs[i].cpu().numpy())
+            np.testing.assert_array_equal(gi, oi)
+            m = oi >= 0
+            assert rel_l2(b.vals[i].cpu().numpy()[m].astype(np.complex128), ov[m]) <= 1e-4
+    print(f"config5: {exact}/24 requests recover the planted support exactly")
+    assert exact >= 20   # low-SNR requests (10-15 dB) may lose a tone

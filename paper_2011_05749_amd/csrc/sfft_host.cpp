@@ -296,7 +296,7 @@ struct BatchCtx {
     c.jstride = jstride;
     c.any_wide_jump = 0;
     for (int s = 0; s < nsig; s++)
-      if (desc[s].kind == SFFT_KIND_TREE && desc[s].jump_L >= 128) c.any_wide_jump = 1;
+      if (desc[s].kind == SFFT_KIND_TREE && desc[s].jump_L >= (1 << kJumpMfmaMinLg)) c.any_wide_jump = 1;
     c.nsig = nsig;
     c.ntree = (int)tree.size();
     c.nffast = (int)ffast.size();

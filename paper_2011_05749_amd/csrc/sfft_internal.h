@@ -21,8 +21,8 @@ constexpr int kMaxFfastBuckets = 4096;
 constexpr int kJumpMax = 128;        // largest stride L' resolved by the dense pass
 constexpr int kJumpItemRows = 4096;  // rows of L' elements per dense-pass work item
 constexpr int kJumpBlockRows = 256;  // rows whose twiddles share one LDS table (VALU form)
-constexpr int kJumpMfmaRows = 256;   // rows per LDS twiddle table on the MFMA path (L' >= 32)
 constexpr int kJumpMfmaClasses = 16; // classes per MFMA pass (32 output rows: re, im)
+constexpr int kJumpMfmaMinLg = 7;    // dense passes with L' = 128 run on the matrix cores
 constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses split FFTs
 
 // log2 of the sub-FFT size used when the D delays of a sample are held in
@@ -107,7 +107,7 @@ struct LaunchCtx {
   const int32_t *l0_pre;   // prefix over tree_list of the rounds (level-0 FFT items)
   const int32_t *l0c_pre;  // prefix over tree_list of ceil(B0 / 256) (classify items)
   int32_t l0_items, l0c_items;
-  int32_t any_wide_jump;   // some signal may run the dense pass at L' = 128
+  int32_t any_wide_jump;   // some signal may run the dense pass on the matrix cores (L' >= 32)
   int32_t jstride;         // dense-pass coefficients per multi-ton slot (kJumpMax)
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)

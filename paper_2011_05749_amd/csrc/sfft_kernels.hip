@@ -1318,64 +1318,69 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 template <int NT>
 __device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const float2 *__restrict__ x, int64_t row0,
-                               int nrows, int lgL, uint64_t Bp, const uint64_t *cls /* LDS */, int nq,
-                               float *TA, float *red, int64_t slot0) {
+                               int nrows, uint64_t Bp, const uint64_t *cls /* LDS */, int nq,
+                               float2 *tile /* LDS, 2 x 32 KiB */, float *red /* aliases tile */,
+                               int64_t slot0) {
+  constexpr int Lp = 32 * NT;
+  constexpr int TR = 4096 / Lp;             // rows of a 32 KiB tile
+  constexpr int PV = TR * Lp / 2 / kThreads;  // 16-byte loads per thread and tile (8)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 31, k = lane >> 5;
+  const int q = m >> 1, o = m & 1;
+  const uint64_t cq = q < nq ? cls[q] : 0;
+  // the rows of a wave are 4 apart: their twiddles differ by e^{-2 pi i 4 c_q / B'}
+  const float2 st = unit_f((cq * 4u) & (Bp - 1), Bp);
   floatx16 acc[NT];
 #pragma unroll
   for (int nt = 0; nt < NT; nt++)
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[nt][r] = 0.f;
-  // lane l supplies B[k][m] = (k ? Im : Re) x[row][32 nt + m]: one float per lane,
-  // 256 contiguous bytes per wave and row
-  typedef __attribute__((address_space(1))) const float gf32;
-  gf32 *xs = (gf32 *)x;
-  for (int b0 = 0; b0 < nrows; b0 += kJumpMfmaRows) {
-    const int nb = (nrows - b0) < kJumpMfmaRows ? (nrows - b0) : kJumpMfmaRows;
-    // A operands in lane order: TA[rr][2 mm + kk], mm = 2 q + o
-    for (int u = threadIdx.x; u < kJumpMfmaRows * kJumpMfmaClasses; u += kThreads) {
-      const int rr = u / kJumpMfmaClasses, q = u % kJumpMfmaClasses;
-      float2 v = make_float2(0.f, 0.f);
-      if (rr < nb && q < nq) v = unit_f((cls[q] * (uint64_t)(row0 + b0 + rr)) & (Bp - 1), Bp);
-      float *t = TA + rr * 64 + q * 4;
-      t[0] = v.x;   // o = 0, k = 0:  Re W
-      t[1] = -v.y;  // o = 0, k = 1: -Im W
-      t[2] = v.y;   // o = 1, k = 0:  Im W
-      t[3] = v.x;   // o = 1, k = 1:  Re W
-    }
-    __syncthreads();
-    // wave w takes rows w, w + 4, ...; the loads of the next four rows are in
-    // flight while the MFMAs of the current four run
-    auto load4 = [&](int rr0, float (&bv)[4][NT]) {
+  // tiles of TR rows stream through LDS: the 16-byte loads of tile t + 1 are
+  // in flight while the MFMAs of tile t run
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(1))) const f32x4 gf4;
+  gf4 *xv = (gf4 *)x;
+  const int ntiles = (nrows + TR - 1) / TR;
+  f32x4 pre[PV];
+  auto fetch = [&](int t) {
+    const int64_t base = (row0 + (int64_t)t * TR) * (Lp / 2);
+    const int64_t lim = ((int64_t)nrows - (int64_t)t * TR) * (Lp / 2);
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int rr = rr0 + 4 * u;
-        const uint64_t rg = (uint64_t)(row0 + b0 + (rr < nb ? rr : nb - 1));
+    for (int u = 0; u < PV; u++) {
+      int64_t i = threadIdx.x + (int64_t)u * kThreads;
+      if (i >= lim) i = lim - 1;  // rows past the item: an in-bounds re-read, never used
+      pre[u] = xv[base + i];
+    }
+  };
+  auto stash = [&](int buf) {
+    f32x4 *dst = (f32x4 *)(tile + (size_t)buf * TR * Lp);
+#pragma unroll
+    for (int u = 0; u < PV; u++) dst[threadIdx.x + u * kThreads] = pre[u];
+  };
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int t = 0; t < ntiles; t++) {
+    if (t + 1 < ntiles) fetch(t + 1);
+    const float *xt = (const float *)(tile + (size_t)(t & 1) * TR * Lp);
+    // lane l supplies A[l % 32][l / 32]: output row 2q + o of class q, re/im
+    // o, times x's re/im k -- [Re W, -Im W; Im W, Re W] -- and B[l / 32][l % 32]
+    // = (k ? Im : Re) x[row][32 nt + m], read from the tile
+    float2 wv = unit_f((cq * (uint64_t)(row0 + (int64_t)t * TR + w)) & (Bp - 1), Bp);
+#pragma unroll 2
+    for (int j = 0; j < TR / 4; j++) {
+      const int rr = w + 4 * j;
+      if ((int64_t)t * TR + rr < nrows) {
+        const float a = o == 0 ? (k == 0 ? wv.x : -wv.y) : (k == 0 ? wv.y : wv.x);
 #pragma unroll
         for (int nt = 0; nt < NT; nt++)
-          bv[u][nt] = xs[(((rg << lgL) + (uint64_t)(nt * 32 + m)) << 1) + (uint64_t)k];
+          acc[nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, xt[(rr * Lp + nt * 32 + m) * 2 + k], acc[nt],
+                                                          0, 0, 0);
       }
-    };
-    float bcur[4][NT], bnxt[4][NT];
-    load4(w, bcur);
-    for (int rr0 = w; rr0 < nb; rr0 += 16) {
-      if (rr0 + 16 < nb) load4(rr0 + 16, bnxt);
-#pragma unroll
-      for (int u = 0; u < 4; u++) {
-        const int rr = rr0 + 4 * u;
-        if (rr < nb) {
-          const float a = TA[rr * 64 + 2 * m + k];
-#pragma unroll
-          for (int nt = 0; nt < NT; nt++)
-            acc[nt] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bcur[u][nt], acc[nt], 0, 0, 0);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < 4; u++)
-#pragma unroll
-        for (int nt = 0; nt < NT; nt++) bcur[u][nt] = bnxt[u][nt];
+      wv = cmulf(wv, st);
     }
+    __syncthreads();
+    if (t + 1 < ntiles) stash((t + 1) & 1);
     __syncthreads();
   }
   // sum the four waves' tiles in LDS, then one FP64 atomic per (class, re|im, t)
@@ -1391,9 +1396,9 @@ __device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const float2 
       const int row = e >> 5, col = e & 31;
       const float v = red[row * 32 + col] + red[(32 + row) * 32 + col] +
                       red[(64 + row) * 32 + col] + red[(96 + row) * 32 + col];
-      const int q = row >> 1;
-      if (q < nq) {
-        double *a = (double *)&c.A.jacc[(slot0 + q) * c.jstride + nt * 32 + col];
+      const int qq = row >> 1;
+      if (qq < nq) {
+        double *a = (double *)&c.A.jacc[(slot0 + qq) * c.jstride + nt * 32 + col];
         atomicAdd(a + (row & 1), (double)v);
       }
     }
@@ -1401,13 +1406,15 @@ __device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const float2 
   }
 }
 
-// Dense pass, L' <= 64 (VALU form) or L' = 128 (MFMA form): two kernels so
-// that each keeps its own register budget; each takes the items of its width.
-template <bool MFMA>
+// Dense pass, L' < 32 (VALU form, NT = 0) or L' = 32 NT for NT = 1, 2, 4
+// (MFMA form): one kernel per width so that each keeps its own register
+// budget; each takes the items of its width.
+template <int NT>
 __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) {
-  // twiddle table (32 KiB as 16 classes x 256 rows of complex64 for the VALU
-  // form, 64 KiB as 256 rows x 64 A-operand floats for the MFMA form, whose
-  // 16 KiB reduction scratch reuses it after the row loop)
+  constexpr bool MFMA = NT > 0;
+  // VALU form: twiddle table of 16 classes x 256 rows of complex64 (32 KiB);
+  // MFMA form: two 32 KiB tiles of x, whose first 16 KiB serve the
+  // reduction after the row loop
   __shared__ float2 T[MFMA ? 8192 : 4096 + 512];
   __shared__ uint64_t cls[kJumpMfmaClasses];
   const int par = (level - 1) & 1;
@@ -1420,7 +1427,10 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
     const SigDesc &d = c.desc[s];
     const int lb = d.log2B0 + level - 1;
     const int lgL = d.log2N - lb;
-    if ((lgL >= 7) != MFMA) continue;
+    // the MFMA kernel of width NT takes L' = 32 NT (when that width runs on the
+    // matrix cores); the VALU kernel every narrower width
+    constexpr int kLg = NT == 1 ? 5 : (NT == 2 ? 6 : 7);
+    if (MFMA ? (lgL != kLg || lgL < kJumpMfmaMinLg) : (lgL >= kJumpMfmaMinLg)) continue;
     const float2 *__restrict__ x = io_of(c, s).x;
     const uint64_t Bp = (uint64_t)1 << lb;
     int m_s = c.st[s].multi[par];
@@ -1436,8 +1446,7 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
       __syncthreads();
       const int64_t slot0 = d.multi_off + j0;
       if constexpr (MFMA) {
-        float *TA = (float *)T;
-        jump_rows_mfma<4>(c, x, row0, nrows, lgL, Bp, cls, nq, TA, TA, slot0);
+        jump_rows_mfma<(NT > 0 ? NT : 1)>(c, x, row0, nrows, Bp, cls, nq, T, (float *)T, slot0);
       } else {
         float2 (*redv)[64] = (float2 (*)[64])(T + 4096);
         switch (nq) {
@@ -1784,10 +1793,12 @@ hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStre
 }
 
 hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_jump_pass<false>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  hipLaunchKernelGGL(k_jump_pass<0>, dim3(grid), dim3(kThreads), 0, s, c, level);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !c.any_wide_jump) return e;
-  hipLaunchKernelGGL(k_jump_pass<true>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  hipLaunchKernelGGL(k_jump_pass<1>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  hipLaunchKernelGGL(k_jump_pass<2>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  hipLaunchKernelGGL(k_jump_pass<4>, dim3(grid), dim3(kThreads), 0, s, c, level);
   return hipGetLastError();
 }
 

@@ -294,6 +294,10 @@ struct BatchCtx {
     c.l0_items = acc0;
     c.l0c_items = acc1;
     c.jstride = jstride;
+    // dense-pass items: 4096 rows for batches of 64 signals or more, fewer
+    // rows (more work-groups per signal) for smaller batches
+    c.jrows = kJumpItemRows;
+    while (c.jrows > kJumpItemRowsMin && (int64_t)c.jrows * 64 > (int64_t)kJumpItemRows * nsig) c.jrows >>= 1;
     c.any_wide_jump = 0;
     for (int s = 0; s < nsig; s++)
       if (desc[s].kind == SFFT_KIND_TREE && desc[s].jump_L >= (1 << kJumpMfmaMinLg)) c.any_wide_jump = 1;
@@ -323,7 +327,7 @@ struct BatchCtx {
         if (l > jl + 1) continue;
         const int64_t Bp = d.B0 << (l - 1);
         if (l >= jl) {  // the dense pass may run at jl (few classes) and runs at jl + 1
-          nj += (Bp + kJumpItemRows - 1) / kJumpItemRows;
+          nj += (Bp + c.jrows - 1) / c.jrows;
           nr += d.multi_cap;
         }
         if (l > jl) continue;

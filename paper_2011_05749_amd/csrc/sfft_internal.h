@@ -19,7 +19,8 @@ constexpr int kMaxD = 4;             // delays handled by the direct partial-sum
 constexpr int kMaxMeas = 64;         // rounds x delays per class vector
 constexpr int kMaxFfastBuckets = 4096;
 constexpr int kJumpMax = 128;        // largest stride L' resolved by the dense pass
-constexpr int kJumpItemRows = 4096;  // rows of L' elements per dense-pass work item
+constexpr int kJumpItemRows = 4096;  // rows of L' elements per dense-pass work item (large batches)
+constexpr int kJumpItemRowsMin = 256; // ... and for a single signal (more work-groups per signal)
 constexpr int kJumpBlockRows = 256;  // rows whose twiddles share one LDS table (VALU form)
 constexpr int kJumpMfmaClasses = 16; // classes per MFMA pass (32 output rows: re, im)
 constexpr int kJumpMfmaMinLg = 7;    // dense passes with L' = 128 run on the matrix cores
@@ -109,6 +110,7 @@ struct LaunchCtx {
   int32_t l0_items, l0c_items;
   int32_t any_wide_jump;   // some signal may run the dense pass on the matrix cores (L' >= 32)
   int32_t jstride;         // dense-pass coefficients per multi-ton slot (kJumpMax)
+  int32_t jrows;           // rows per dense-pass work item (power of two)
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;

@@ -1006,7 +1006,7 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
           const bool jump = d.jump_L > 0 && Lp <= d.jump_L &&
                             (m <= kJumpMfmaClasses || 2 * Lp <= d.jump_L);
           if (jump) {
-            cnt[3] = (int)((Bp + kJumpItemRows - 1) / kJumpItemRows);
+            cnt[3] = (int)((Bp + c.jrows - 1) / c.jrows);
             cnt[4] = m;
             c.st[s].samples += d.N;
           } else {
@@ -1240,7 +1240,7 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
 // coalesced read of x.  All L' elements of a row m share the twiddle of the
 // row, so the twiddles of a block of rows live in LDS (one entry per class
 // and row) and each element costs one complex multiply-add per class.
-// Item = (signal, kJumpItemRows rows); thread tid owns t = tid mod L'.
+// Item = (signal, c.jrows rows); thread tid owns t = tid mod L'.
 template <int NQ>
 __device__ __forceinline__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__restrict__ x,
                           int64_t row0, int nrows, int lgL, uint64_t Bp, const uint64_t *cls,
@@ -1435,8 +1435,8 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
     const uint64_t Bp = (uint64_t)1 << lb;
     int m_s = c.st[s].multi[par];
     if (m_s > d.multi_cap) m_s = d.multi_cap;
-    const int64_t row0 = (int64_t)ch * kJumpItemRows;
-    const int nrows = (int)((int64_t)Bp - row0 < kJumpItemRows ? (int64_t)Bp - row0 : kJumpItemRows);
+    const int64_t row0 = (int64_t)ch * c.jrows;
+    const int nrows = (int)((int64_t)Bp - row0 < c.jrows ? (int64_t)Bp - row0 : c.jrows);
     const int G = kJumpMfmaClasses;
     for (int j0 = 0; j0 < m_s; j0 += G) {
       const int nq = (m_s - j0) < G ? (m_s - j0) : G;
@@ -1484,6 +1484,7 @@ template <int NMAX>
 __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int level) {
   __shared__ double2 V[kJumpMax][NMAX];
   __shared__ double2 Ms[kJumpMax];
+  __shared__ double2 root[kJumpMax];
   __shared__ int open_cur[kJumpMax], open_nxt[kJumpMax];
   __shared__ int any_open;
   const int par = (level - 1) & 1;
@@ -1503,17 +1504,20 @@ __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int leve
     const int64_t slot = d.multi_off + j;
     const int64_t cpar = c.A.multi_c[par][slot];
     const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
+    // e^{-2 pi i f_k t / N} = e^{-2 pi i c t / N} e^{-2 pi i k t / L'} (f_k = c + k B'):
+    // thread t folds the first factor into M(t), the second is a root of unity
     if (k < Lp) {
       const double2 a = c.A.jacc[slot * c.jstride + k];
-      Ms[k] = make_double2(a.x / (double)Bp, a.y / (double)Bp);
+      const double2 b = unit_d(mod_n((uint64_t)cpar * (uint64_t)k, d), (uint64_t)N, -1);
+      Ms[k] = cmul(make_double2(a.x / (double)Bp, a.y / (double)Bp), b);
+      root[k] = unit_d((uint64_t)k, (uint64_t)Lp, -1);
     }
     __syncthreads();
     if (k < Lp) {
       const uint64_t f = (uint64_t)(cpar + (int64_t)k * Bp);
       double2 xh = make_double2(0.0, 0.0);
       for (int t = 0; t < Lp; t++) {
-        const double2 e = unit_d(mod_n(f * (uint64_t)t, d), (uint64_t)N, -1);
-        const double2 u = cmul(Ms[t], e);
+        const double2 u = cmul(Ms[t], root[(k * t) & (Lp - 1)]);
         xh.x += u.x;
         xh.y += u.y;
       }

@@ -244,7 +244,8 @@ def main():
                     help="only copy MIB MiB device-to-device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "single-GPU benchmark: --gpus must be 1 (solves are independent; "
+                                   "scale out with one process per GPU, each with its own signals)"}))
         sys.exit(2)
 
     import numpy as np

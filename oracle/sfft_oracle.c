@@ -237,7 +237,7 @@ typedef struct {
   cplx a;
   int64_t f2;   /* two-ton: the second position and value */
   cplx a2;
-} verdict;
+} decision;
 
 typedef struct {
   const orc_cfg *c;
@@ -334,7 +334,7 @@ static double match2(const cls_ctx *x, const cplx *Y, int64_t f) {
    values clear the zero-ton level and the residual passes the single-ton
    bound. */
 static void two_ton(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B, double T0sq,
-                    double T1sq, verdict *v) {
+                    double T1sq, decision *v) {
   const orc_cfg *cf = x->c;
   int64_t N = cf->N;
   int n = x->n, D = cf->D;
@@ -393,11 +393,11 @@ static void two_ton(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B, doubl
   v->a2 = a1;
 }
 
-static verdict classify(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
+static decision classify(const cls_ctx *x, const cplx *Y, int64_t c, int64_t B) {
   const orc_cfg *cf = x->c;
   int64_t N = cf->N, L = N / B;
   int n = x->n;
-  verdict v;
+  decision v;
   v.cls = ORC_ZERO;
   v.f = -1;
   v.a = 0;
@@ -647,7 +647,7 @@ static int64_t solve_tree(const orc_cfg *c, const float *x, int64_t *out_idx,
     int64_t nnext = 0;
     int nz = 0, ns = 0, nm = 0, nd = 0;
     for (int64_t q = 0; q < ncls; q++) {
-      verdict v = classify(&cx, Y + q * n, cls[q], B);
+      decision v = classify(&cx, Y + q * n, cls[q], B);
       if (v.cls == ORC_ZERO) {
         nz++;
       } else if (v.cls == ORC_SINGLE) {
@@ -797,7 +797,7 @@ static int64_t solve_ffast(const orc_cfg *c, const float *x, int64_t *out_idx,
         if (!active[b]) continue;
         ident++;
         seen[b] = 1;
-        verdict v = classify(&cx, Y + b * D, h, c->stageB[j]);
+        decision v = classify(&cx, Y + b * D, h, c->stageB[j]);
         last[b] = v.cls;
         if (v.cls == ORC_ZERO) nz++;
         if (v.cls == ORC_MULTI) nm++;

@@ -280,7 +280,7 @@ __device__ float select_kth_power(const float2 *v, int64_t cnt, float scale, int
   return __uint_as_float(prefix);
 }
 
-struct Verdict {
+struct Decision {
   int cls;
   int64_t f;
   double2 a;
@@ -324,7 +324,7 @@ __device__ __forceinline__ double2 conj_mul(double2 a, double2 b) {  // conj(a) 
 // Vandermonde system of all measurements in least squares (Eq. 9).  FP64.
 template <int NMAX>
 __device__ __forceinline__ void two_ton(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
-                                     int64_t c, int64_t B, double T0sq, double T1sq, Verdict &v) {
+                                     int64_t c, int64_t B, double T0sq, double T1sq, Decision &v) {
   const int D = d.D;
   const int64_t N = d.N;
   double g00 = 0.0, g11 = 0.0;
@@ -400,9 +400,9 @@ __device__ __forceinline__ void two_ton(const double2 (&Y)[NMAX], const SigDesc 
 // TREE: the two-ton solve may follow (tree kernels); otherwise the R-FFAST
 // estimator may locate (FFAST kernel) -- each kernel compiles only its own
 template <int NMAX, bool TREE = true>
-__device__ Verdict classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
+__device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
                             int64_t c, int64_t B, double sref2, double noise_var) {
-  Verdict v;
+  Decision v;
   v.cls = kZero;
   v.f = -1;
   v.a = make_double2(0.0, 0.0);
@@ -677,7 +677,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
     const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
     const int64_t cc = (int64_t)(item - c.l0c_pre[li]) * kThreads + threadIdx.x;
     const bool valid = cc < B;
-    Verdict v;
+    Decision v;
     v.cls = kZero;
     double2 Y[NMAX];
 #pragma unroll
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(kThreads) void k_ffast(LaunchCtx c) {
         double2 Y[NMAX];
 #pragma unroll
         for (int i = 0; i < NMAX; i++) Y[i] = i < D ? Yf[(int64_t)b * D + i] : make_double2(0.0, 0.0);
-        const Verdict v = classify<NMAX, false>(Y, d, D, 1, h, d.stageB[j], sref2, nv);
+        const Decision v = classify<NMAX, false>(Y, d, D, 1, h, d.stageB[j], sref2, nv);
         cls[b] = (uint8_t)v.cls;
         if (v.cls == kSingle) {
           det[b] = 1;
@@ -1201,7 +1201,7 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
     }
     const int64_t cc = cpar + (side ? Bp : 0);
     const SigState &ss = c.st[s];
-    const Verdict v = classify<NMAX>(Y, d, n, d.R, cc, B, ss.sref2, ss.noise_var);
+    const Decision v = classify<NMAX>(Y, d, n, d.R, cc, B, ss.sref2, ss.noise_var);
     if (v.cls == kSingle) {
       const int fs = atomicAdd(&c.st[s].found, 1);
       push_found(c, s, d, fs, v.f, v.a);
@@ -1547,7 +1547,7 @@ __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int leve
             }
         }
         const int64_t cc = cpar + (int64_t)k * Bp;
-        const Verdict v = classify<NMAX>(Y, d, n, d.R, cc, Bd, sref2, nv);
+        const Decision v = classify<NMAX>(Y, d, n, d.R, cc, Bd, sref2, nv);
         atomicMax(&c.st[s].levels, lvl);
         if (v.cls == kSingle) {
           const int fs = atomicAdd(&c.st[s].found, 1);

@@ -99,7 +99,7 @@ typedef struct {
                               its L' coefficients, measured by one dense pass over x;
                               every later level's class vectors are the same linear
                               functionals of x as the level-by-level gathers.
-                              0 = level by level to the end (default 64) */
+                              0 = level by level to the end (default 128) */
   double eps0;             /* exact: zero-ton if |Y|^2 <= eps0^2 sref^2 n (1e-4) */
   double eps1;             /* exact: single-ton if residual^2 <= eps1^2 |Y|^2 (1e-4) */
   double zero_k;           /* noisy: T0^2 = s_b^2 (n + zero_k sqrt(n))        (4) */

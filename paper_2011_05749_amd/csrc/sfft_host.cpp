@@ -789,7 +789,7 @@ void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages, in
   p->identity_round0 = 0;
   p->nstage_B = 0;
   p->max_peel_rounds = 64;
-  p->jump_L = 64;
+  p->jump_L = 128;
   p->eps0 = 1e-4;
   p->eps1 = 1e-4;
   p->zero_k = 4.0;

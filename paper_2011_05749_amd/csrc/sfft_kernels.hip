@@ -1292,10 +1292,18 @@ __device__ __forceinline__ void jump_rows(const LaunchCtx &c, const SigDesc &d, 
     if (lane < Lp) red[w][lane] = make_float2(vx, vy);
     __syncthreads();
     if (threadIdx.x < Lp) {
+      // L' < 64: every wave holds t = lane once; L' >= 64: threads t, t + L', ...
       double sx = 0.0, sy = 0.0;
-      for (int ww = 0; ww < kThreads / 64; ww++) {
-        sx += (double)red[ww][threadIdx.x].x;
-        sy += (double)red[ww][threadIdx.x].y;
+      if (Lp < 64) {
+        for (int ww = 0; ww < kThreads / 64; ww++) {
+          sx += (double)red[ww][threadIdx.x].x;
+          sy += (double)red[ww][threadIdx.x].y;
+        }
+      } else {
+        for (int u = threadIdx.x; u < kThreads; u += Lp) {
+          sx += (double)red[u >> 6][u & 63].x;
+          sy += (double)red[u >> 6][u & 63].y;
+        }
       }
       double *a = (double *)&c.A.jacc[(slot0 + q) * c.jstride + threadIdx.x];
       atomicAdd(a, sx);

@@ -15,7 +15,8 @@ preserving solve (Sect. 3.1) inside the tree -- is timed as "variants", as are
 and by the packet-erasure schedule (Sect. 3.2, Subproblem 3), 2048 at 20 dB
 located by the R-FFAST estimator and by enumeration, and 16 of the headline
 signals held in host memory, solved by the host-gather entry point against
-a full copy to the device.
+a full copy to the device, and the noisy N = 2^20 batch of 64 and the 2048
+uneven signals (batched and one solve per signal).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -200,6 +201,48 @@ def run_host_resident(sfft, torch, np, xs, specs, seeds, N, K, B0, nsig, dev):
     return out
 
 
+def run_configs(sfft, torch, np, steps, warmup, dev):
+    """The other workloads as batches: noisy N = 2^20, K = 256 at 20 dB (batch
+    of 64, B0 = 512, 4 rounds x 2 delays) and 2048 uneven exactly sparse
+    signals (N = 2^14..2^20, K = 4..512, one identity round, B0 = next pow2 >=
+    K), the latter also one sfft_exec_async per signal."""
+    import siggen
+    out = {}
+    N, K = 2 ** 20, 256
+    seeds = list(range(1000, 1064))
+    specs = [siggen.make_spec(N, K, s, snr_db=20.0) for s in seeds]
+    xs = [siggen.synth_torch(sp, dev) for sp in specs]
+    plans = [sfft.Plan(N, K, 4, 2, seed=s, B0=512, mode="noisy") for s in seeds]
+    out["noisy_n2p20_k256_20db_batch64"] = _time_plans(sfft, torch, np, plans, xs, specs, K, steps,
+                                                        warmup)
+    rng = np.random.default_rng(2000)
+    plans, xs, specs = [], [], []
+    for i in range(2048):
+        n = 2 ** int(rng.integers(14, 21))
+        k = int(round(np.exp(rng.uniform(np.log(4), np.log(512)))))
+        sp = siggen.make_spec(n, k, 2000 + i)
+        specs.append(sp)
+        xs.append(siggen.synth_torch(sp, dev))
+        plans.append(sfft.Plan(n, k, 1, 2, seed=2000 + i, B0=1 << max(0, (k - 1).bit_length()),
+                               identity_round0=1))
+    res = _time_plans(sfft, torch, np, plans, xs, specs, None, steps, warmup)
+    # one solve per signal on the current stream, same plans and buffers
+    outs = [(torch.empty(p.K, dtype=torch.int64, device=dev),
+             torch.empty(p.K, dtype=torch.complex64, device=dev)) for p in plans]
+    dc = torch.zeros(1, dtype=torch.int64, device=dev)
+    ds = torch.zeros(1, dtype=torch.int32, device=dev)
+    for i in range(8):
+        plans[i].exec_async(xs[i], outs[i][0], outs[i][1], dc, ds)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(len(plans)):
+        plans[i].exec_async(xs[i], outs[i][0], outs[i][1], dc, ds)
+    torch.cuda.synchronize()
+    res["plain_value"] = round(len(plans) / (time.perf_counter() - t0), 1)
+    out["uneven_2048_signals"] = res
+    return out
+
+
 def _time_plans(sfft, torch, np, plans, xs, specs, K, steps, warmup, **extra):
     """spectra/s of one captured batch of `plans`, and how many results are
     exactly the planted spectrum."""
@@ -215,12 +258,12 @@ def _time_plans(sfft, torch, np, plans, xs, specs, K, steps, warmup, **extra):
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
     counts = b.counts.cpu().numpy()
-    ok = sum(int(counts[i] == K and np.array_equal(b.idxs[i].cpu().numpy(), siggen.truth(sp)[0]))
+    ok = sum(int(counts[i] == sp.K and np.array_equal(b.idxs[i].cpu().numpy(), siggen.truth(sp)[0]))
              for i, sp in enumerate(specs))
     st = [b.stats(i) for i in range(nsig)]
     res = {"value": round(nsig / dt, 1), "unit": "spectra/s", "ms_per_batch": round(dt * 1e3, 4),
            "identifications_per_solve": float(np.mean([s["ident"] for s in st])),
-           "peeling_rounds_mean": float(np.mean([s["levels"] for s in st])),
+           "levels_mean": float(np.mean([s["levels"] for s in st])),  # FFAST: peeling rounds
            "verified": f"{ok}/{nsig} signals: exact support, count K", **extra}
     del b
     sfft.release_batches()
@@ -360,6 +403,8 @@ def main():
         print("bench: host-resident signals", file=sys.stderr, flush=True)
         variants["host_resident_two_ton_r2_d4"] = run_host_resident(sfft, torch, np, xs, specs, seeds,
                                                                     N, K, B0, 16, dev)
+        print("bench: other workloads", file=sys.stderr, flush=True)
+        variants.update(run_configs(sfft, torch, np, args.steps, args.warmup, dev))
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None

@@ -15,8 +15,9 @@ preserving solve (Sect. 3.1) inside the tree -- is timed as "variants", as are
 and by the packet-erasure schedule (Sect. 3.2, Subproblem 3), 2048 at 20 dB
 located by the R-FFAST estimator and by enumeration, and 16 of the headline
 signals held in host memory, solved by the host-gather entry point against
-a full copy to the device, and the noisy N = 2^20 batch of 64 and the 2048
-uneven signals (batched and one solve per signal).
+a full copy to the device, the noisy N = 2^20 batch of 64, the 2048 uneven
+signals (batched and one solve per signal), and the FP64 / FP32 precision
+study at N = 2^24, K = 4096.
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -243,6 +244,48 @@ def run_configs(sfft, torch, np, steps, warmup, dev):
     return out
 
 
+def run_precision_study(sfft, torch, np, steps, warmup, dev, nsig=8):
+    """N = 2^24, K = 4096, magnitudes 10^U[0,2], 30 dB, B0 = 8192, 4 rounds x 2
+    delays, noisy mode: FP64 against FP32 locate / value / residual, speed and
+    errors against the planted spectrum (L0 = support misses + false alarms,
+    L2 = relative error)."""
+    import siggen
+    N, K = 2 ** 24, 4096
+    seeds = [5000 + i for i in range(nsig)]
+    specs = [siggen.make_spec(N, K, s, mag="loguniform", mag_lo=0.0, mag_hi=2.0, snr_db=30.0)
+             for s in seeds]
+    xs = [siggen.synth_torch(sp, dev) for sp in specs]
+    out = {}
+    for prec in (0, 1):
+        plans = [sfft.Plan(N, K, 4, 2, seed=s, B0=8192, mode="noisy", precision=prec) for s in seeds]
+        b = sfft.Batch(plans, xs)
+        for _ in range(warmup):
+            b.run(graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            b.run(graph=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        l0s, l2s = [], []
+        for i, sp in enumerate(specs):
+            idx = b.idxs[i].cpu().numpy()
+            val = b.vals[i].cpu().numpy().astype(np.complex128)
+            sup, vals = siggen.truth(sp)
+            got = dict(zip(idx[idx >= 0].tolist(), val[idx >= 0].tolist()))
+            want = dict(zip(sup.tolist(), vals.tolist()))
+            keys = set(got) | set(want)
+            l0s.append(len(set(got) ^ set(want)))
+            d = np.array([got.get(k, 0) - want.get(k, 0) for k in keys])
+            l2s.append(float(np.linalg.norm(d) / np.linalg.norm(vals)))
+        out["fp64" if prec == 0 else "fp32"] = {
+            "value": round(nsig / dt, 2), "unit": "spectra/s", "L0_mean": float(np.mean(l0s)),
+            "L2_mean": float(np.mean(l2s))}
+        del b
+        sfft.release_batches()
+    return out
+
+
 def _time_plans(sfft, torch, np, plans, xs, specs, K, steps, warmup, **extra):
     """spectra/s of one captured batch of `plans`, and how many results are
     exactly the planted spectrum."""
@@ -405,6 +448,8 @@ def main():
                                                                     N, K, B0, 16, dev)
         print("bench: other workloads", file=sys.stderr, flush=True)
         variants.update(run_configs(sfft, torch, np, args.steps, args.warmup, dev))
+        variants["precision_n2p24_k4096_30db_batch8"] = run_precision_study(sfft, torch, np, args.steps,
+                                                                            args.warmup, dev)
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None

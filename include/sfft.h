@@ -112,6 +112,11 @@ typedef struct {
                               it fits; needs rounds x (delays - 2) >= 2, else
                               SFFT_EINVAL; noisy mode or FFAST: SFFT_EUNSUPPORTED.
                               0 = off (default) */
+  int32_t precision;       /* 0 (default): phase-to-index, values and residuals in FP64 on
+                              FP32 buckets; 1: all in FP32 (the precision study of the
+                              N = 2^24, K = 4096 workload); the two-ton solve stays
+                              FP64.  Tree plans only (FFAST: SFFT_EUNSUPPORTED); other
+                              values: SFFT_EINVAL */
   int32_t rf_iters;        /* FFAST: C in 1..16 selects the R-FFAST delay set and singleton
                               estimator (Sect. 3.2, Subproblem 2, general case): each stage
                               is measured at the C * rf_m delays r_c + 2^c t (c < C,
@@ -161,6 +166,7 @@ typedef struct {
   int64_t peel_start_f[SFFT_MAX_PEEL_STARTS];
   int32_t rf_iters, rf_m;  /* R-FFAST delay set (rf_iters = 0: delays 0..D-1) */
   uint64_t rf_off[SFFT_MAX_ROUNDS];   /* r_c */
+  int32_t precision;       /* 0: FP64 decisions, 1: FP32 */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */

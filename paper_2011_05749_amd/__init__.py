@@ -54,6 +54,7 @@ class Params(ctypes.Structure):
         ("zero_k", ctypes.c_double), ("single_k", ctypes.c_double),
         ("noise_var", ctypes.c_double),
         ("mpp", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
         ("rf_iters", ctypes.c_int32), ("rf_m", ctypes.c_int32),
         ("peel_starts", ctypes.c_int32),
         ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
@@ -80,6 +81,7 @@ class PlanInfo(ctypes.Structure):
         ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
         ("rf_iters", ctypes.c_int32), ("rf_m", ctypes.c_int32),
         ("rf_off", ctypes.c_uint64 * MAX_ROUNDS),
+        ("precision", ctypes.c_int32),
     ]
 
 
@@ -184,7 +186,7 @@ class Plan:
     zero_k, single_k, noise_var, mpp (2 = two-ton moment preserving solve), peel_starts
     (FFAST packet-erasure schedule: number of drawn start frequencies) or peel_start_f
     (explicit start frequencies), rf_iters and rf_m (FFAST R-FFAST delay set and
-    singleton estimator)."""
+    singleton estimator), precision (0: FP64 decisions, 1: FP32)."""
 
     def __init__(self, N: int, K: int, stages: int, delays: int, seed: int = 0, **kw):
         p = Params()

@@ -190,6 +190,7 @@ struct BatchCtx {
       d.multi_cap = in.multi_cap;
       d.jump_L = (in.kind == SFFT_KIND_TREE && !no_jump) ? in.jump_L : 0;
       d.mpp = in.mpp;
+      d.precision = in.precision;
       d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
       d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
       d.rf_m = in.rf_m;
@@ -298,6 +299,9 @@ struct BatchCtx {
     // rows (more work-groups per signal) for smaller batches
     c.jrows = kJumpItemRows;
     while (c.jrows > kJumpItemRowsMin && (int64_t)c.jrows * 64 > (int64_t)kJumpItemRows * nsig) c.jrows >>= 1;
+    c.any_fp32 = 0;
+    for (int s = 0; s < nsig; s++)
+      if (desc[s].kind == SFFT_KIND_TREE && desc[s].precision == 1) c.any_fp32 = 1;
     c.any_wide_jump = 0;
     for (int s = 0; s < nsig; s++)
       if (desc[s].kind == SFFT_KIND_TREE && desc[s].jump_L >= (1 << kJumpMfmaMinLg)) c.any_wide_jump = 1;
@@ -454,6 +458,8 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
   in.jump_L = p.jump_L;
   if (p.mpp != 0 && p.mpp != 2) return SFFT_EINVAL;
   in.mpp = p.mpp;
+  if (p.precision != 0 && p.precision != 1) return SFFT_EINVAL;
+  in.precision = p.precision;
   in.found_cap = (int32_t)std::max<int64_t>(64, npow2(2 * p.K));
   in.multi_cap = (int32_t)std::max<int64_t>(64, p.K);
   memset(pl->stage_off, 0, sizeof(pl->stage_off));
@@ -519,7 +525,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
       if ((int)st.size() != p.stages) return SFFT_EUNSUPPORTED;
     }
     if ((int)st.size() > SFFT_MAX_STAGES) return SFFT_EUNSUPPORTED;
-    if (p.mpp != 0) return SFFT_EUNSUPPORTED;
+    if (p.mpp != 0 || p.precision != 0) return SFFT_EUNSUPPORTED;
     SplitMix64 g{p.seed};
     in.rf_iters = p.rf_iters;
     in.rf_m = p.rf_iters ? p.rf_m : 0;
@@ -796,6 +802,7 @@ void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages, in
   p->single_k = 4.0;
   p->noise_var = 0.0;
   p->mpp = 0;
+  p->precision = 0;
   p->rf_iters = 0;
   p->rf_m = 0;
   p->peel_starts = 0;

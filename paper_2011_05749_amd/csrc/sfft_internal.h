@@ -42,6 +42,7 @@ struct SigDesc {
   int32_t found_cap, multi_cap;
   int32_t jump_L;
   int32_t mpp;            // 2: two-ton moment preserving solve of multi-tons
+  int32_t precision;      // 0: locate / value / residual in FP64; 1: in FP32
   int32_t rf_iters, rf_m; // FFAST R-FFAST delay set r_c + 2^c t (rf_iters = 0: delays 0..D-1)
   uint64_t rf_off[SFFT_MAX_ROUNDS];
   int32_t n_starts;       // FFAST packet-erasure schedule: start frequencies (0: method 1)
@@ -111,6 +112,7 @@ struct LaunchCtx {
   int32_t any_wide_jump;   // some signal may run the dense pass on the matrix cores (L' >= 32)
   int32_t jstride;         // dense-pass coefficients per multi-ton slot (kJumpMax)
   int32_t jrows;           // rows per dense-pass work item (power of two)
+  int32_t any_fp32;        // some tree signal classifies in single precision
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;

@@ -398,8 +398,10 @@ __device__ __forceinline__ void two_ton(const double2 (&Y)[NMAX], const SigDesc 
 // Singleton test (Sect. 3.2, Subproblems 1-2) of one class vector Y (n values,
 // rounds x D layout) of class c among B buckets.
 // TREE: the two-ton solve may follow (tree kernels); otherwise the R-FFAST
-// estimator may locate (FFAST kernel) -- each kernel compiles only its own
-template <int NMAX, bool TREE = true>
+// estimator may locate (FFAST kernel) -- each kernel compiles only its own.
+// F32: the single-precision variant of locate / value / residual is compiled
+// in (batches holding a plan that asks for it).
+template <int NMAX, bool TREE = true, bool F32 = false>
 __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
                             int64_t c, int64_t B, double sref2, double noise_var) {
   Decision v;
@@ -456,6 +458,24 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
     int64_t k = (int64_t)floor((mid - (double)c) / (double)B + 0.5) % L;
     if (k < 0) k += L;
     ksnap = k;
+  } else if (F32 && D >= 2 && d.precision == 1) {
+    // FP32 variant: pooled phase, angle and lattice snap in single precision
+    float px = 0.f, py = 0.f;
+#pragma unroll
+    for (int i = 0; i + 1 < NMAX; i++) {
+      if (i + 1 < n && (i % D) != D - 1 && (i / D) < rounds) {
+        const float ax = (float)Y[i + 1].x, ay = (float)Y[i + 1].y;
+        const float bx = (float)Y[i].x, by = (float)Y[i].y;
+        px += ax * bx + ay * by;
+        py += ay * bx - ax * by;
+      }
+    }
+    float phi = atan2f(py, px);
+    if (phi < 0.f) phi += 6.2831853071795865f;
+    const float u = phi * ((float)N / 6.2831853071795865f);
+    int64_t kk = (int64_t)floorf((u - (float)c) / (float)B + 0.5f) % L;
+    if (kk < 0) kk += L;
+    ksnap = kk;
   } else if (D >= 2) {
     double2 P = make_double2(0.0, 0.0);
 #pragma unroll
@@ -522,6 +542,38 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
     k = bestk;
   }
   const int64_t f = c + k * B;
+  if (F32 && d.precision == 1) {
+    // FP32 variant: value and residual in single precision, FP32 twiddles
+    // from exact integer ratios
+    float ax = 0.f, ay = 0.f;
+#pragma unroll
+    for (int i = 0; i < NMAX; i++) {
+      if (i < n) {
+        const float2 ef = unit_f(mod_n((uint64_t)f * tau_of<TREE>(d, i), d), (uint64_t)N);  // e^{-i..}
+        const float yx = (float)Y[i].x, yy = (float)Y[i].y;
+        ax += yx * ef.x - yy * ef.y;
+        ay += yx * ef.y + yy * ef.x;
+      }
+    }
+    ax /= (float)n;
+    ay /= (float)n;
+    float r2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < NMAX; i++) {
+      if (i < n) {
+        const float2 ef = unit_f(mod_n((uint64_t)f * tau_of<TREE>(d, i), d), (uint64_t)N);
+        // a e^{+i..} = a conj(ef)
+        const float rx = ax * ef.x + ay * ef.y, ry = ay * ef.x - ax * ef.y;
+        const float ex = (float)Y[i].x - rx, ey = (float)Y[i].y - ry;
+        r2 += ex * ex + ey * ey;
+      }
+    }
+    v.f = f;
+    v.a = make_double2(ax, ay);
+    v.cls = ((double)r2 <= T1sq) ? kSingle : kMulti;
+    if (TREE && v.cls == kMulti && d.mpp == 2) two_ton<NMAX>(Y, d, n, rounds, c, B, T0sq, T1sq, v);
+    return v;
+  }
   // value: least-squares mean of the de-rotated measurements (FP64)
   double2 e[NMAX];
   double2 a = make_double2(0.0, 0.0);
@@ -664,7 +716,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_stats(LaunchCtx c) {
 // Classification of the B0 level-0 classes (Sect. 3.2, Subproblems 1-2):
 // item = (signal, 256 classes); single-tons and multi-tons are compacted by
 // wave ballot + prefix, one atomic per wave and list.
-template <int NMAX>
+template <int NMAX, bool F32>
 __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
   for (int item = blockIdx.x; item < c.l0c_items; item += gridDim.x) {
     const int li = find_owner(c.l0c_pre, c.ntree, item);
@@ -686,7 +738,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
 #pragma unroll
       for (int i = 0; i < NMAX; i++)
         if (i < n) Y[i] = to_d(Y0[(int64_t)i * B + cc]);
-      v = classify<NMAX>(Y, d, n, d.R, cc, B, sref2, nv);
+      v = classify<NMAX, true, F32>(Y, d, n, d.R, cc, B, sref2, nv);
     }
     const int nf = !valid ? 0 : (v.cls == kSingle ? 1 : (v.cls == kDouble ? 2 : 0));
     const int fs = wave_append_n(&c.st[s].found, nf);
@@ -1165,7 +1217,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_direct(LaunchCtx c, int lev
 
 // Children of every multi-ton of level-1: Y_child = 1/2 (Y_parent +- w Z/B'),
 // w = e^{-pi i c / B'} (radix-2 split of the level's transform); classify.
-template <int NMAX>
+template <int NMAX, bool F32>
 __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
   const int par = (level - 1) & 1, cur = level & 1;
   const int32_t *pc = c.A.pre + 2 * (c.nsig + 1);
@@ -1201,7 +1253,7 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
     }
     const int64_t cc = cpar + (side ? Bp : 0);
     const SigState &ss = c.st[s];
-    const Decision v = classify<NMAX>(Y, d, n, d.R, cc, B, ss.sref2, ss.noise_var);
+    const Decision v = classify<NMAX, true, F32>(Y, d, n, d.R, cc, B, ss.sref2, ss.noise_var);
     if (v.cls == kSingle) {
       const int fs = atomicAdd(&c.st[s].found, 1);
       push_found(c, s, d, fs, v.f, v.a);
@@ -1488,7 +1540,7 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
 // xhat_f e^{2 pi i f tau_i / N} -- the same linear functional of x as the
 // level's gathered buckets -- so the level-by-level classification of the
 // tree search (Sect. 3.3) runs on these vectors.
-template <int NMAX>
+template <int NMAX, bool F32>
 __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int level) {
   __shared__ double2 V[kJumpMax][NMAX];
   __shared__ double2 Ms[kJumpMax];
@@ -1555,7 +1607,7 @@ __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int leve
             }
         }
         const int64_t cc = cpar + (int64_t)k * Bp;
-        const Decision v = classify<NMAX>(Y, d, n, d.R, cc, Bd, sref2, nv);
+        const Decision v = classify<NMAX, true, F32>(Y, d, n, d.R, cc, Bd, sref2, nv);
         atomicMax(&c.st[s].levels, lvl);
         if (v.cls == kSingle) {
           const int fs = atomicAdd(&c.st[s].found, 1);
@@ -1771,9 +1823,15 @@ hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
     hipLaunchKernelGGL(k_level0_stats, dim3(c.ntree < 4096 ? c.ntree : 4096), dim3(kThreads), 0, s, c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int g = c.l0c_items < 8192 ? c.l0c_items : 8192;
-    if (nm == 8) hipLaunchKernelGGL(k_level0_classify<8>, dim3(g), dim3(kThreads), 0, s, c);
-    else if (nm == 16) hipLaunchKernelGGL(k_level0_classify<16>, dim3(g), dim3(kThreads), 0, s, c);
-    else hipLaunchKernelGGL(k_level0_classify<64>, dim3(g), dim3(kThreads), 0, s, c);
+    if (c.any_fp32) {
+      if (nm == 8) hipLaunchKernelGGL((k_level0_classify<8, true>), dim3(g), dim3(kThreads), 0, s, c);
+      else if (nm == 16) hipLaunchKernelGGL((k_level0_classify<16, true>), dim3(g), dim3(kThreads), 0, s, c);
+      else hipLaunchKernelGGL((k_level0_classify<64, true>), dim3(g), dim3(kThreads), 0, s, c);
+    } else {
+      if (nm == 8) hipLaunchKernelGGL((k_level0_classify<8, false>), dim3(g), dim3(kThreads), 0, s, c);
+      else if (nm == 16) hipLaunchKernelGGL((k_level0_classify<16, false>), dim3(g), dim3(kThreads), 0, s, c);
+      else hipLaunchKernelGGL((k_level0_classify<64, false>), dim3(g), dim3(kThreads), 0, s, c);
+    }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (c.nffast > 0) {
@@ -1808,25 +1866,37 @@ hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t
   hipLaunchKernelGGL(k_jump_pass<0>, dim3(grid), dim3(kThreads), 0, s, c, level);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !c.any_wide_jump) return e;
-  hipLaunchKernelGGL(k_jump_pass<1>, dim3(grid), dim3(kThreads), 0, s, c, level);
-  hipLaunchKernelGGL(k_jump_pass<2>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  if (5 >= kJumpMfmaMinLg) hipLaunchKernelGGL(k_jump_pass<1>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  if (6 >= kJumpMfmaMinLg) hipLaunchKernelGGL(k_jump_pass<2>, dim3(grid), dim3(kThreads), 0, s, c, level);
   hipLaunchKernelGGL(k_jump_pass<4>, dim3(grid), dim3(kThreads), 0, s, c, level);
   return hipGetLastError();
 }
 
 hipError_t launch_jump_resolve(const LaunchCtx &c, int level, int grid, hipStream_t s) {
   const int nm = nmax_bucket(c.nmax);
-  if (nm == 8) hipLaunchKernelGGL(k_jump_resolve<8>, dim3(grid), dim3(kJumpMax), 0, s, c, level);
-  else if (nm == 16) hipLaunchKernelGGL(k_jump_resolve<16>, dim3(grid), dim3(kJumpMax), 0, s, c, level);
-  else hipLaunchKernelGGL(k_jump_resolve<64>, dim3(grid), dim3(kJumpMax), 0, s, c, level);
+  if (c.any_fp32) {
+    if (nm == 8) hipLaunchKernelGGL((k_jump_resolve<8, true>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
+    else if (nm == 16) hipLaunchKernelGGL((k_jump_resolve<16, true>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
+    else hipLaunchKernelGGL((k_jump_resolve<64, true>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
+  } else {
+    if (nm == 8) hipLaunchKernelGGL((k_jump_resolve<8, false>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
+    else if (nm == 16) hipLaunchKernelGGL((k_jump_resolve<16, false>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
+    else hipLaunchKernelGGL((k_jump_resolve<64, false>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_children(const LaunchCtx &c, int level, int grid, hipStream_t s) {
   const int nm = nmax_bucket(c.nmax);
-  if (nm == 8) hipLaunchKernelGGL(k_children<8>, dim3(grid), dim3(kThreads), 0, s, c, level);
-  else if (nm == 16) hipLaunchKernelGGL(k_children<16>, dim3(grid), dim3(kThreads), 0, s, c, level);
-  else hipLaunchKernelGGL(k_children<64>, dim3(grid), dim3(kThreads), 0, s, c, level);
+  if (c.any_fp32) {
+    if (nm == 8) hipLaunchKernelGGL((k_children<8, true>), dim3(grid), dim3(kThreads), 0, s, c, level);
+    else if (nm == 16) hipLaunchKernelGGL((k_children<16, true>), dim3(grid), dim3(kThreads), 0, s, c, level);
+    else hipLaunchKernelGGL((k_children<64, true>), dim3(grid), dim3(kThreads), 0, s, c, level);
+  } else {
+    if (nm == 8) hipLaunchKernelGGL((k_children<8, false>), dim3(grid), dim3(kThreads), 0, s, c, level);
+    else if (nm == 16) hipLaunchKernelGGL((k_children<16, false>), dim3(grid), dim3(kThreads), 0, s, c, level);
+    else hipLaunchKernelGGL((k_children<64, false>), dim3(grid), dim3(kThreads), 0, s, c, level);
+  }
   return hipGetLastError();
 }
 

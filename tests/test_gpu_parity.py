@@ -40,7 +40,7 @@ def oracle_cfg(N, K, stages, delays, seed=0, mode=0, B0=0, identity_round0=False
 
 
 def solve_both(sfft, x, N, K, stages, delays, seed=0, **kw):
-    ok = {k: v for k, v in kw.items() if k not in ("stage_B", "jump_L")}
+    ok = {k: v for k, v in kw.items() if k not in ("stage_B", "jump_L", "precision")}
     mode = kw.get("mode", 0)
     plan = sfft.Plan(N, K, stages, delays, seed=seed, **kw)
     ocfg_kw = {}

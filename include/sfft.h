@@ -141,6 +141,15 @@ typedef struct {
                               default) = S SplitMix64 draws from `seed` (after the
                               R-FFAST offsets, if any), each mod N; a mix of given
                               and -1 entries: SFFT_EINVAL */
+  int32_t l1_resolve;      /* tree: 1 (default) = resolve every level-0 multi-ton at
+                              level 1 from one pass over x: viewing x as B0 rows of
+                              L = N/B0 samples, a B0-point DFT down each column gives
+                              every class's L coefficients M_c(t) (the class's bucket
+                              measured with shift t, times B0), and each class vector
+                              of any later level (Sect. 3.3) is a sum of 2^d of them,
+                              d levels below; taken when B0 is 1024, 2048 or 4096 and
+                              L >= 32768 / B0, in place of jump_L and the level-by-level
+                              gathers.  0 = off; other values: SFFT_EINVAL */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -167,6 +176,7 @@ typedef struct {
   int32_t rf_iters, rf_m;  /* R-FFAST delay set (rf_iters = 0: delays 0..D-1) */
   uint64_t rf_off[SFFT_MAX_ROUNDS];   /* r_c */
   int32_t precision;       /* 0: FP64 decisions, 1: FP32 */
+  int32_t l1_resolve;      /* 1 when the level-1 column pass is taken */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */
@@ -250,6 +260,8 @@ int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs,
 #define SFFT_KERNEL_FINALIZE 6
 #define SFFT_KERNEL_JUMP_PASS 7     /* dense pass: L' coefficients of each open class */
 #define SFFT_KERNEL_JUMP_RESOLVE 8  /* subtree classification from the coefficients */
+#define SFFT_KERNEL_COL_PASS 9      /* level-1 column DFTs: M_c(t) of every open class */
+#define SFFT_KERNEL_COL_RESOLVE 10  /* classification of every later level from M_c(t) */
 int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
                                 int64_t *const *idx, void *const *vals, int64_t *d_counts,
                                 int32_t *d_status, int32_t n, float *ms, int32_t *kernel,

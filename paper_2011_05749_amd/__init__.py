@@ -58,6 +58,7 @@ class Params(ctypes.Structure):
         ("rf_iters", ctypes.c_int32), ("rf_m", ctypes.c_int32),
         ("peel_starts", ctypes.c_int32),
         ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
+        ("l1_resolve", ctypes.c_int32),
     ]
 
 
@@ -82,6 +83,7 @@ class PlanInfo(ctypes.Structure):
         ("rf_iters", ctypes.c_int32), ("rf_m", ctypes.c_int32),
         ("rf_off", ctypes.c_uint64 * MAX_ROUNDS),
         ("precision", ctypes.c_int32),
+        ("l1_resolve", ctypes.c_int32),
     ]
 
 
@@ -97,7 +99,7 @@ class Stats(ctypes.Structure):
 
 KERNEL_NAMES = {0: "k_reset", 1: "k_level0", 2: "k_sched", 3: "k_expand_fft",
                 4: "k_expand_direct", 5: "k_children", 6: "k_finalize", 7: "k_jump_pass",
-                8: "k_jump_resolve"}
+                8: "k_jump_resolve", 9: "k_col_pass", 10: "k_col_resolve"}
 
 _vp = ctypes.c_void_p
 _lib.sfft_params_init.argtypes = [ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int64,
@@ -186,7 +188,8 @@ class Plan:
     zero_k, single_k, noise_var, mpp (2 = two-ton moment preserving solve), peel_starts
     (FFAST packet-erasure schedule: number of drawn start frequencies) or peel_start_f
     (explicit start frequencies), rf_iters and rf_m (FFAST R-FFAST delay set and
-    singleton estimator), precision (0: FP64 decisions, 1: FP32)."""
+    singleton estimator), precision (0: FP64 decisions, 1: FP32), l1_resolve (1:
+    level-1 column pass when the shape allows, 0: off)."""
 
     def __init__(self, N: int, K: int, stages: int, delays: int, seed: int = 0, **kw):
         p = Params()

@@ -123,8 +123,8 @@ hipError_t device_twiddles(int dev, const float2 **out) {
 }
 
 struct LevelLaunch {
-  bool fft, direct, children, jump;
-  int grid_fft, grid_direct, grid_children, grid_jump, grid_resolve;
+  bool fft, direct, children, jump, col;
+  int grid_fft, grid_direct, grid_children, grid_jump, grid_resolve, grid_col, grid_col_resolve;
 };
 
 // first tree level whose parents' stride N / (B0 2^{l-1}) is <= jump_L, or a
@@ -141,7 +141,7 @@ struct BatchCtx {
   std::vector<const sfft_plan_s *> plans;
   int nsig = 0;
   std::vector<SigDesc> desc;
-  DevBuf b_desc, b_io, b_st, b_lists, b_y0, b_fst, b_ff, b_fa, b_mc, b_my, b_mz, b_pre, b_out, b_jacc;
+  DevBuf b_desc, b_io, b_st, b_lists, b_y0, b_fst, b_ff, b_fa, b_mc, b_my, b_mz, b_pre, b_out, b_jacc, b_jcol;
   LaunchCtx lc{};
   std::vector<LevelLaunch> levels;
   std::vector<SigIO> io_last;
@@ -165,7 +165,7 @@ struct BatchCtx {
     nsig = (int)ps.size();
     if (hipGetDevice(&device) != hipSuccess) return SFFT_EDEVICE;
     desc.resize(nsig);
-    int64_t y0 = 0, fst = 0, fc = 0, mc = 0, mz = 0;
+    int64_t y0 = 0, fst = 0, fc = 0, mc = 0, mz = 0, jc = 0;
     int nmax = 1, maxB0 = 1, maxStage = 1, maxFcap = 64, maxLevels = 0;
     std::vector<std::pair<int64_t, int>> tree, ffast;
     for (int s = 0; s < nsig; s++) {
@@ -188,7 +188,8 @@ struct BatchCtx {
       d.max_peel_rounds = in.max_peel_rounds;
       d.found_cap = in.found_cap;
       d.multi_cap = in.multi_cap;
-      d.jump_L = (in.kind == SFFT_KIND_TREE && !no_jump) ? in.jump_L : 0;
+      d.l1 = (in.kind == SFFT_KIND_TREE && !no_jump && in.l1_resolve) ? 1 : 0;
+      d.jump_L = (in.kind == SFFT_KIND_TREE && !no_jump && !d.l1) ? in.jump_L : 0;
       d.mpp = in.mpp;
       d.precision = in.precision;
       d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
@@ -210,9 +211,11 @@ struct BatchCtx {
       d.found_off = fc;
       d.multi_off = mc;
       d.fst_off = fst;
+      d.jc_off = jc;
       if (in.kind == SFFT_KIND_TREE) {
         y0 += (int64_t)d.n * in.B0;
         mc += d.multi_cap;
+        if (d.l1) jc += (int64_t)d.multi_cap * (in.N / in.B0);
 
         tree.push_back({(int64_t)d.n * in.B0 * (in.max_levels + 1), s});
         maxB0 = std::max<int64_t>(maxB0, in.B0);
@@ -262,8 +265,9 @@ struct BatchCtx {
         !ck(b_y0.alloc(sizeof(float2) * (size_t)y0)) || !ck(b_fst.alloc(sizeof(double2) * (size_t)fst)) ||
         !ck(b_ff.alloc(sizeof(int64_t) * (size_t)fc)) || !ck(b_fa.alloc(sizeof(double2) * (size_t)fc)) ||
         !ck(b_mc.alloc(2 * sizeof(int64_t) * (size_t)mc)) || !ck(b_my.alloc(2 * sizeof(float2) * (size_t)mz)) ||
-        !ck(b_mz.alloc(2 * sizeof(double2) * (size_t)mz)) || !ck(b_pre.alloc(5 * sizeof(int32_t) * (ns + 1))) ||
+        !ck(b_mz.alloc(2 * sizeof(double2) * (size_t)mz)) || !ck(b_pre.alloc(kPre * sizeof(int32_t) * (ns + 1))) ||
         !ck(b_jacc.alloc(sizeof(double2) * (size_t)(any_jump ? mc * jstride : 1))) ||
+        !ck(b_jcol.alloc(sizeof(float2) * (size_t)(jc > 0 ? jc : 1))) ||
         !ck(b_out.alloc((sizeof(int64_t) + sizeof(int32_t)) * 2)))
       return SFFT_ENOMEM;
     if (hipMemcpy(b_desc.p, desc.data(), sizeof(SigDesc) * ns, hipMemcpyHostToDevice) != hipSuccess ||
@@ -287,6 +291,7 @@ struct BatchCtx {
     c.A.multi_z[1] = (double2 *)b_mz.p + mz;
     c.A.pre = (int32_t *)b_pre.p;
     c.A.jacc = (double2 *)b_jacc.p;
+    c.A.jcol = (float2 *)b_jcol.p;
     c.A.tw = tw;
     c.tree_list = (const int32_t *)b_lists.p;
     c.ffast_list = (const int32_t *)b_lists.p + tree.size();
@@ -302,6 +307,9 @@ struct BatchCtx {
     c.any_fp32 = 0;
     for (int s = 0; s < nsig; s++)
       if (desc[s].kind == SFFT_KIND_TREE && desc[s].precision == 1) c.any_fp32 = 1;
+    c.col_lp_mask = 0;
+    for (int s = 0; s < nsig; s++)
+      if (desc[s].l1) c.col_lp_mask |= 1 << (desc[s].log2B0 - 10);  // bit LP - 5, B0 = 2^(LP + 5)
     c.any_wide_jump = 0;
     for (int s = 0; s < nsig; s++)
       if (desc[s].kind == SFFT_KIND_TREE && desc[s].jump_L >= (1 << kJumpMfmaMinLg)) c.any_wide_jump = 1;
@@ -316,17 +324,27 @@ struct BatchCtx {
     // before its jump level, runs the dense pass and the subtree resolution at
     // it, and has no work after it
     levels.clear();
+    int ncu = 256;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 16)
+      ncu = 256;
     int last = 0;
     for (int s = 0; s < nsig; s++)
       if (desc[s].kind == SFFT_KIND_TREE)
-        last = std::max(last, std::min(desc[s].max_levels, jump_level(desc[s]) + 1));
+        last = std::max(last, desc[s].l1 ? 1 : std::min(desc[s].max_levels, jump_level(desc[s]) + 1));
     (void)maxLevels;
     for (int l = 1; l <= last; l++) {
       LevelLaunch L{};
-      int64_t nf = 0, nd = 0, nch = 0, nj = 0, nr = 0;
+      int64_t nf = 0, nd = 0, nch = 0, nj = 0, nr = 0, ncol = 0, ncr = 0;
       for (int s = 0; s < nsig; s++) {
         const SigDesc &d = desc[s];
         if (d.kind != SFFT_KIND_TREE || l > d.max_levels) continue;
+        if (d.l1) {
+          if (l == 1) {
+            ncol += (d.N >> d.log2B0) / (kColThreads / (d.B0 / kColQ));
+            ncr += d.multi_cap;
+          }
+          continue;
+        }
         const int jl = jump_level(d);
         if (l > jl + 1) continue;
         const int64_t Bp = d.B0 << (l - 1);
@@ -348,6 +366,11 @@ struct BatchCtx {
       L.direct = nd > 0;
       L.children = nch > 0;
       L.jump = nj > 0;
+      L.col = ncol > 0;
+      // column pass: one resident work-group per CU (a multiple of 16, for the
+      // XCD pairing of its items)
+      L.grid_col = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)ncu & ~15, ((ncol + 15) / 16) * 16));
+      L.grid_col_resolve = (int)std::min<int64_t>(std::max<int64_t>(ncr, 1), 8192);
       L.grid_fft = (int)std::min<int64_t>(std::max<int64_t>(nf, 1), 4096);
       L.grid_direct = (int)std::min<int64_t>(std::max<int64_t>(nd, 1), 8192);
       L.grid_children = (int)std::min<int64_t>(std::max<int64_t>((nch + kThreads - 1) / kThreads, 1), 2048);
@@ -396,6 +419,11 @@ struct BatchCtx {
                      (e = mark(SFFT_KERNEL_JUMP_PASS | (l << 8))) != hipSuccess ||
                      (e = launch_jump_resolve(c, l, L.grid_resolve, s)) != hipSuccess ||
                      (e = mark(SFFT_KERNEL_JUMP_RESOLVE | (l << 8))) != hipSuccess))
+        return e;
+      if (L.col && ((e = launch_col_pass(c, L.grid_col, s)) != hipSuccess ||
+                    (e = mark(SFFT_KERNEL_COL_PASS | (l << 8))) != hipSuccess ||
+                    (e = launch_col_resolve(c, L.grid_col_resolve, s)) != hipSuccess ||
+                    (e = mark(SFFT_KERNEL_COL_RESOLVE | (l << 8))) != hipSuccess))
         return e;
     }
     if ((e = launch_finalize(c, s)) != hipSuccess) return e;
@@ -460,6 +488,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
   in.mpp = p.mpp;
   if (p.precision != 0 && p.precision != 1) return SFFT_EINVAL;
   in.precision = p.precision;
+  if (p.l1_resolve != 0 && p.l1_resolve != 1) return SFFT_EINVAL;
   in.found_cap = (int32_t)std::max<int64_t>(64, npow2(2 * p.K));
   in.multi_cap = (int32_t)std::max<int64_t>(64, p.K);
   memset(pl->stage_off, 0, sizeof(pl->stage_off));
@@ -482,6 +511,10 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     in.B0 = B0;
     const int full = ilog2(p.N / B0);
     in.max_levels = (p.max_levels < 0 || p.max_levels > full) ? full : p.max_levels;
+    // level-1 column pass: B0 = P x 32 with P in {32, 64, 128}, and an even
+    // number of column blocks of 512 / P columns
+    in.l1_resolve = p.l1_resolve && (B0 == 1024 || B0 == 2048 || B0 == 4096) &&
+                    p.N / B0 >= 32768 / B0 && in.max_levels >= 1;
     SplitMix64 g{p.seed};
     for (int r = 0; r < p.stages; r++) {
       if (r == 0 && p.identity_round0) {
@@ -807,6 +840,7 @@ void sfft_params_init(sfft_params_t *p, int64_t N, int64_t K, int32_t stages, in
   p->rf_m = 0;
   p->peel_starts = 0;
   for (int i = 0; i < SFFT_MAX_PEEL_STARTS; i++) p->peel_start_f[i] = -1;
+  p->l1_resolve = 1;
 }
 
 sfft_plan_t sfft_plan_ex(const sfft_params_t *p) {

@@ -9,7 +9,8 @@
 
 namespace sfft {
 
-constexpr int kThreads = 256;        // work-group size of every kernel
+constexpr int kThreads = 256;        // work-group size of most kernels
+constexpr int kPre = 7;              // prefix arrays of the per-level work
 constexpr int kFftMax = 8192;        // largest LDS-resident pow2 FFT (64 KiB complex64)
 constexpr int kLog2FftMax = 13;
 constexpr int kDirectMax = 2048;     // largest non-pow2 stage (direct DFT in LDS)
@@ -25,6 +26,9 @@ constexpr int kJumpBlockRows = 256;  // rows whose twiddles share one LDS table 
 constexpr int kJumpMfmaClasses = 16; // classes per MFMA pass (32 output rows: re, im)
 constexpr int kJumpMfmaMinLg = 7;    // dense passes with L' = 128 run on the matrix cores
 constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses split FFTs
+constexpr int kColThreads = 512;     // work-group of the level-1 column pass
+constexpr int kColQ = 32;            // column pass: B0 = P x 32, 32 rows per thread
+constexpr int kColResolveCap = 256;  // open subclasses per depth of one class
 
 // log2 of the sub-FFT size used when the D delays of a sample are held in
 // LDS together (D planes of complex64 within 64 KiB)
@@ -41,6 +45,7 @@ struct SigDesc {
   int32_t max_levels, window, nstages, max_peel_rounds;
   int32_t found_cap, multi_cap;
   int32_t jump_L;
+  int32_t l1;             // level-0 multi-tons resolved at level 1 from the column pass
   int32_t mpp;            // 2: two-ton moment preserving solve of multi-tons
   int32_t precision;      // 0: locate / value / residual in FP64; 1: in FP32
   int32_t rf_iters, rf_m; // FFAST R-FFAST delay set r_c + 2^c t (rf_iters = 0: delays 0..D-1)
@@ -58,6 +63,7 @@ struct SigDesc {
   int64_t fst_off;        // double2 FFAST state (D*sum B) + per-bucket scratch
   int64_t found_off;      // found list slots
   int64_t multi_off;      // multi-ton slots (per parity)
+  int64_t jc_off;         // column-pass rows: complex64 offset of multi_cap rows of L = N/B0
 };
 
 // Per-call pointers of one signal.
@@ -91,9 +97,11 @@ struct Arena {
   int64_t *multi_c[2];
   float2 *multi_y[2];
   double2 *multi_z[2];
-  int32_t *pre;           // 5 prefix arrays of nsig+1: fft items, direct items,
-                          // children, dense-pass items, subtree-resolve items
+  int32_t *pre;           // kPre prefix arrays of nsig+1: fft items, direct items,
+                          // children, dense-pass items, subtree-resolve items,
+                          // column-pass items, column-resolve items
   double2 *jacc;          // per multi-ton slot: jstride dense-pass coefficients
+  float2 *jcol;           // per level-0 multi-ton slot: M_c(t), t < N/B0
   const float2 *tw;       // e^{-2 pi i k / kFftMax}, k < kFftMax
 };
 
@@ -113,6 +121,7 @@ struct LaunchCtx {
   int32_t jstride;         // dense-pass coefficients per multi-ton slot (kJumpMax)
   int32_t jrows;           // rows per dense-pass work item (power of two)
   int32_t any_fp32;        // some tree signal classifies in single precision
+  int32_t col_lp_mask;     // bit LP - 5 set when a signal with B0 = 2^(LP+5) takes the column pass
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;
@@ -128,6 +137,8 @@ hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStre
 hipError_t launch_children(const LaunchCtx &c, int level, int grid, hipStream_t s);
 hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t s);
 hipError_t launch_jump_resolve(const LaunchCtx &c, int level, int grid, hipStream_t s);
+hipError_t launch_col_pass(const LaunchCtx &c, int grid, hipStream_t s);
+hipError_t launch_col_resolve(const LaunchCtx &c, int grid, hipStream_t s);
 hipError_t launch_finalize(const LaunchCtx &c, hipStream_t s);
 // level-0 class vectors in class-major order (tree: out[c*n + i]; FFAST as stored)
 hipError_t launch_export_level0(const LaunchCtx &c, void *out, hipStream_t s);

@@ -92,6 +92,7 @@ def test_plan_draws_match_oracle(N, K, R, seed, B0, ident):
     ((1024, 10, 17, 2), {}, -1),           # too many rounds
     ((1024, 10, 2, 2), {"jump_L": 48}, -1),   # subtree stride not a power of two
     ((1024, 10, 2, 2), {"jump_L": 256}, -1),  # beyond the dense-pass width
+    ((1024, 10, 2, 2), {"l1_resolve": 2}, -1),  # the column pass is on or off
 ])
 def test_plan_validation(args, kw, code):
     with pytest.raises(sfft.SfftError) as e:
@@ -152,3 +153,19 @@ def test_rffast_plan_matches_oracle_and_validates():
 def test_noisy_plan_allows_one_delay_and_window():
     p = sfft.Plan(2 ** 16, 32, 4, 1, seed=1, mode="noisy", window=16)
     assert p.info.mode == sfft.NOISY and p.info.D == 1 and p.info.window == 16
+
+
+def test_column_pass_shapes():
+    """The level-1 column pass is taken for B0 = 1024, 2048, 4096 with at
+    least 32768 / B0 columns and one tree level, never for FFAST plans."""
+    assert sfft.Plan(2 ** 22, 1024, 4, 2, B0=2048).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 15, 300, 2, 2, B0=2048).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 14, 300, 2, 2, B0=2048).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 15, 300, 2, 2, B0=1024).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 14, 300, 2, 2, B0=1024).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 15, 300, 2, 2, B0=4096).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=8192).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, l1_resolve=0).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, max_levels=0).info.l1_resolve == 0
+    assert sfft.Plan(10800, 10, 3, 2).info.l1_resolve == 0

@@ -1,0 +1,152 @@
+"""Parity of the level-1 column pass (plan field l1_resolve) with the FP64
+oracle's level-by-level tree search (Sect. 3.3), and with the gathering path
+of the same plan.
+
+The column pass measures every level-0 multi-ton's coefficients M_c(t) from
+one read of x and classifies each later level's class vectors from them; the
+oracle gathers those vectors level by level.  Bar: indices bit-exact (padding
+included), counts and status equal, values within relative L2 1e-5.
+Shapes cover the three widths B0 = 1024, 2048, 4096, the smallest stride each
+takes (L = 32768 / B0), both modes, the two-ton solve, the FP32 decisions, a
+depth cap, and a batch that mixes the widths with signals that gather.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import siggen
+from tests.test_gpu_parity import assert_parity, oracle_cfg, rel_l2, solve_both, to_dev, VAL_TOL
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sfft():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    import paper_2011_05749_amd as m
+    return m
+
+
+EXACT_CASES = [
+    # N, K, rounds, delays, B0, seed
+    (2 ** 15, 300, 2, 2, 2048, 1),    # L = 16: one item pair per signal
+    (2 ** 15, 700, 4, 2, 1024, 2),    # L = 32, 16 columns per item
+    (2 ** 15, 1500, 3, 2, 4096, 3),   # L = 8, 4 columns per item
+    (2 ** 18, 900, 4, 2, 2048, 4),
+    (2 ** 17, 500, 2, 3, 1024, 5),
+    (2 ** 20, 2000, 3, 2, 4096, 6),
+]
+
+
+@pytest.mark.parametrize("N,K,R,D,B0,seed", EXACT_CASES)
+def test_exact_matches_oracle(sfft, N, K, R, D, B0, seed):
+    x = siggen.synth(siggen.make_spec(N, K, seed))
+    g, o = solve_both(sfft, x, N, K, R, D, seed=seed, B0=B0)
+    assert_parity(g, o)
+    p = sfft.Plan(N, K, R, D, seed=seed, B0=B0)
+    assert p.info.l1_resolve == 1
+    st = g[3]
+    # level 0 reads n B0 samples, the column pass all N of them
+    if g[2] > 0 and (st["level_mask"] >> 1) & 1:
+        assert st["samples"] == R * D * B0 + N
+
+
+@pytest.mark.parametrize("N,K,R,D,B0,seed", EXACT_CASES[:4])
+def test_same_as_gathering_path(sfft, N, K, R, D, B0, seed):
+    x = to_dev(siggen.synth(siggen.make_spec(N, K, seed + 100)))
+    a = sfft.Plan(N, K, R, D, seed=seed, B0=B0)
+    b = sfft.Plan(N, K, R, D, seed=seed, B0=B0, l1_resolve=0)
+    assert a.info.l1_resolve == 1 and b.info.l1_resolve == 0
+    ia, va, ca = a.exec(x)
+    ib, vb, cb = b.exec(x)
+    assert ca == cb
+    np.testing.assert_array_equal(ia.cpu().numpy(), ib.cpu().numpy())
+    m = ia.cpu().numpy() >= 0
+    if m.any():
+        assert rel_l2(va.cpu().numpy()[m].astype(np.complex128),
+                      vb.cpu().numpy()[m].astype(np.complex128)) <= VAL_TOL
+    assert a.stats()["status"] == b.stats()["status"]
+
+
+@pytest.mark.parametrize("seed", [11, 12])
+def test_noisy_matches_oracle(sfft, seed):
+    N, K, B0 = 2 ** 18, 400, 1024
+    x = siggen.synth(siggen.make_spec(N, K, seed, snr_db=25.0))
+    g, o = solve_both(sfft, x, N, K, 4, 2, seed=seed, B0=B0, mode=1)
+    assert_parity(g, o)
+
+
+def test_two_ton_solve_matches_oracle(sfft):
+    N, K, B0 = 2 ** 16, 900, 1024
+    x = siggen.synth(siggen.make_spec(N, K, 21))
+    g, o = solve_both(sfft, x, N, K, 2, 3, seed=21, B0=B0, mpp=2)
+    assert_parity(g, o)
+
+
+def test_fp32_decisions_match_oracle(sfft):
+    N, K, B0 = 2 ** 17, 800, 2048
+    x = siggen.synth(siggen.make_spec(N, K, 22))
+    g, o = solve_both(sfft, x, N, K, 4, 2, seed=22, B0=B0, precision=1)
+    assert_parity(g, o)
+
+
+@pytest.mark.parametrize("cap", [1, 2, 3])
+def test_depth_cap_matches_oracle(sfft, cap):
+    """A multi-ton still open at the deepest allowed level leaves the solve
+    partial, as in the oracle."""
+    N, K, B0 = 2 ** 16, 1200, 1024
+    x = siggen.synth(siggen.make_spec(N, K, 30 + cap))
+    g, o = solve_both(sfft, x, N, K, 2, 2, seed=30 + cap, B0=B0, max_levels=cap)
+    assert_parity(g, o)
+
+
+def test_no_multiton_reads_nothing_more(sfft):
+    """A signal whose level-0 buckets all close takes no column items."""
+    N, K, B0 = 2 ** 16, 3, 1024
+    sp = siggen.make_spec(N, K, 40, support=[5, 77, 1030])
+    x = siggen.synth(sp)
+    g, o = solve_both(sfft, x, N, K, 2, 2, seed=40, B0=B0)
+    assert_parity(g, o)
+    assert g[3]["samples"] == 2 * 2 * B0
+
+
+def test_unsupported_widths_fall_back(sfft):
+    assert sfft.Plan(2 ** 16, 100, 2, 2, B0=512).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 16, 100, 2, 2, B0=8192).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 14, 100, 2, 2, B0=2048).info.l1_resolve == 0   # L = 8 < 16
+    assert sfft.Plan(2 ** 16, 100, 2, 2, B0=2048, max_levels=0).info.l1_resolve == 0
+
+
+def test_mixed_batch_matches_oracle(sfft):
+    """Widths 1024 / 2048 / 4096 beside signals that gather level by level, in
+    one batch, eager and graph-replayed."""
+    shapes = [(2 ** 16, 500, 1024), (2 ** 17, 900, 2048), (2 ** 15, 1500, 4096),
+              (2 ** 16, 120, 256), (2 ** 18, 700, 2048), (2 ** 14, 200, 512),
+              (2 ** 17, 1000, 1024), (2 ** 16, 800, 4096)]
+    plans, xs, host, cfgs = [], [], [], []
+    for i, (N, K, B0) in enumerate(shapes):
+        seed = 700 + i
+        x = siggen.synth(siggen.make_spec(N, K, seed))
+        plans.append(sfft.Plan(N, K, 3, 2, seed=seed, B0=B0))
+        cfgs.append(oracle_cfg(N, K, 3, 2, seed=seed, B0=B0))
+        host.append(x)
+        xs.append(to_dev(x))
+    for graph in (False, True, True):
+        b = sfft.Batch(plans, xs)
+        b.run(graph=graph)
+        torch.cuda.synchronize()
+        counts = b.counts.cpu().numpy()
+        status = b.status.cpu().numpy()
+        for i, (x, cfg) in enumerate(zip(host, cfgs)):
+            oi, ov, oc, tr = oracle.solve(cfg, x)
+            gi = b.idxs[i].cpu().numpy()
+            gv = b.vals[i].cpu().numpy()
+            assert counts[i] == oc and status[i] == tr.status, i
+            np.testing.assert_array_equal(gi, oi)
+            m = oi >= 0
+            if m.any():
+                assert rel_l2(gv[m].astype(np.complex128), ov[m]) <= VAL_TOL
+        torch.cuda.synchronize()
+        _ = (xs[0].abs() * 2).sum().item()

@@ -61,6 +61,10 @@ def kernel_bytes(name, level, plans, stats):
         n = inf.R * inf.D
         if name == "k_level0":
             tot += n * inf.B0 * 8
+        elif name == "k_col_pass" and level == 1:
+            # the level-1 column pass reads the whole signal once
+            if inf.l1_resolve and (int(st["level_mask"]) >> 1) & 1:
+                tot += inf.N * 8
         elif name == "k_jump_pass" and level >= 1:
             # a signal's dense pass runs once, at the deepest level it opened
             deepest = int(st["level_mask"]).bit_length() - 1
@@ -324,6 +328,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jump-L", type=int, default=None,
                     help="override the plans' subtree-resolution stride (0 = level by level)")
+    ap.add_argument("--l1-resolve", type=int, default=None,
+                    help="override the plans' level-1 column pass (0 = gather level by level)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the two-ton (moment preserving) plan variant")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -359,6 +365,8 @@ def main():
     xs = [siggen.synth_torch(sp, dev) for sp in specs]
     torch.cuda.synchronize()
     extra = {} if args.jump_L is None else {"jump_L": args.jump_L}
+    if args.l1_resolve is not None:
+        extra["l1_resolve"] = args.l1_resolve
     plans = [sfft.Plan(N, K, R, D, seed=s, B0=B0, **extra) for s in seeds]
     batch = sfft.Batch(plans, xs)
 
@@ -437,7 +445,10 @@ def main():
     if not args.no_variants:
         print("bench: two-ton variant", file=sys.stderr, flush=True)
         variants = {"two_ton_r2_d4": run_variant(sfft, torch, np, xs, specs, seeds, N, K, B0, 2, 4,
-                                                 args.steps, args.warmup, mpp=2, jump_L=0)}
+                                                 args.steps, args.warmup, mpp=2, jump_L=0, l1_resolve=0)}
+        print("bench: level-by-level gathers (column pass off)", file=sys.stderr, flush=True)
+        variants["gather_levels_l1_off"] = run_variant(sfft, torch, np, xs, specs, seeds, N, K, B0, R, D,
+                                                       args.steps, args.warmup, l1_resolve=0)
         print("bench: FFAST peeling schedules", file=sys.stderr, flush=True)
         variants["ffast_n10800_k10_batch2048"] = run_ffast_c1(sfft, torch, np, 2048, args.steps,
                                                               args.warmup, dev)
@@ -483,7 +494,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "N=2^22, K=1024 exactly sparse unit tones; tree search, B0=2048, "
-                               "4 rounds x 2 delays, exact mode; batch of 256 per graph",
+                               "4 rounds x 2 delays, exact mode, level-1 column pass; batch of 256 "
+                               "per graph",
                    "N": N, "K": K, "B0": B0, "rounds": R, "delays": D, "batch": nb},
         "batched": {"value": round(value, 2), "unit": "spectra/s",
                     "batch_p50_ms": round(pct(step_ms, 0.5), 4),

@@ -370,7 +370,7 @@ struct BatchCtx {
       // column pass: one resident work-group per CU (a multiple of 16, for the
       // XCD pairing of its items)
       L.grid_col = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)ncu & ~15, ((ncol + 15) / 16) * 16));
-      L.grid_col_resolve = (int)std::min<int64_t>(std::max<int64_t>(ncr, 1), 8192);
+      L.grid_col_resolve = (int)std::min<int64_t>(std::max<int64_t>((ncr + 64 / kColGroup - 1) / (64 / kColGroup), 1), 4096);
       L.grid_fft = (int)std::min<int64_t>(std::max<int64_t>(nf, 1), 4096);
       L.grid_direct = (int)std::min<int64_t>(std::max<int64_t>(nd, 1), 8192);
       L.grid_children = (int)std::min<int64_t>(std::max<int64_t>((nch + kThreads - 1) / kThreads, 1), 2048);

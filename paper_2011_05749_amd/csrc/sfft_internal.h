@@ -28,7 +28,10 @@ constexpr int kJumpMfmaMinLg = 7;    // dense passes with L' = 128 run on the ma
 constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses split FFTs
 constexpr int kColThreads = 512;     // work-group of the level-1 column pass
 constexpr int kColQ = 32;            // column pass: B0 = P x 32, 32 rows per thread
-constexpr int kColResolveCap = 256;  // open subclasses per depth of one class
+constexpr int kColResolveCap = 128;  // open subclasses per depth of one class
+constexpr int kColGroupLg = 2;      // column resolve: 2^2 lanes per class
+constexpr int kColGroup = 1 << kColGroupLg;
+constexpr int kColLaneDepth = 5;    // ... one lane per class-vector sum down to this depth
 
 // log2 of the sub-FFT size used when the D delays of a sample are held in
 // LDS together (D planes of complex64 within 64 KiB)

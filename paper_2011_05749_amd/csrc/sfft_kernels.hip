@@ -1784,7 +1784,13 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
   float2 xn[kColQ];
   int ln[RL];
   int m_n = 0;
-  // the open-class list (ahead, in registers), then the rows of an item
+  // the open-class list of an item (ahead, in registers), then its rows in
+  // four parts of eight, issued at three points of the previous item's work
+  // so that the vector-memory queue never holds all of them at once
+  gq *fx = nullptr;
+  uint32_t foff = 0;
+  int64_t frs = 0;
+  bool fon = false;
   auto fetch = [&](int item, int sg) {
     const __attribute__((address_space(4))) SigDesc &ds = cst(c.desc)[sg];
     const int m = cst(c.st)[sg].multi[0];
@@ -1795,12 +1801,16 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
       ln[r] = j < m_n ? (int)c.A.multi_c[0][ds.multi_off + j] : 0;
     }
     const int64_t L = ds.N >> ds.log2B0;
-    gq *xg = (gq *)(c.io ? cst(c.io)[sg].x : c.io1.x) + ((int64_t)(item - pc[sg]) << LTC);
-    const uint32_t off = (uint32_t)(p * L + t);  // < B0 L / 32: fits
-    const int64_t rs = (int64_t)P * L;
+    fx = (gq *)(c.io ? cst(c.io)[sg].x : c.io1.x) + ((int64_t)(item - pc[sg]) << LTC);
+    foff = (uint32_t)(p * L + t);  // < B0 L / 32: fits
+    frs = (int64_t)P * L;
+    fon = true;
+  };
+  auto fetch_part = [&](int part) {
+    if (!fon) return;
 #pragma unroll
-    for (int q = 0; q < kColQ; q++) {
-      const unsigned long long u = (xg + q * rs)[off];
+    for (int q = 8 * part; q < 8 * part + 8; q++) {
+      const unsigned long long u = (fx + q * frs)[foff];
       xn[q] = make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
     }
   };
@@ -1819,7 +1829,10 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
   };
   int s = 0;
   while (2 * ip0 + hf >= pc[s + 1]) s++;
-  if (cst(c.desc)[s].log2B0 == LP + 5) fetch(2 * ip0 + hf, s);
+  if (cst(c.desc)[s].log2B0 == LP + 5) {
+    fetch(2 * ip0 + hf, s);
+    for (int part = 0; part < 4; part++) fetch_part(part);
+  }
   for (int ip = ip0; ip < ip1; ip++) {
     const int item = 2 * ip + hf;
     while (item >= pc[s + 1]) s++;
@@ -1832,16 +1845,23 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
 #pragma unroll
     for (int r = 0; r < RL; r++) lc[r] = ln[r];
     const int m_s = m_n;
+    fon = false;
     if (ip + 1 < ip1) {
       int ns = s;
       while (item + 2 >= pc[ns + 1]) ns++;
       if (cst(c.desc)[ns].log2B0 == LP + 5) fetch(item + 2, ns);
     }
+    fetch_part(0);
+    fetch_part(1);
     // the previous item's stores go out behind the loads just issued
     if (pend) store_outputs();
     pend = false;
-    if (!mine) continue;
+    if (!mine) {
+      for (int part = 2; part < 4; part++) fetch_part(part);
+      continue;
+    }
     dft_reg<5>(v);
+    fetch_part(2);
     __syncthreads();  // the previous item's outputs are out of E and open_c
 #pragma unroll
     for (int r = 0; r < RL; r++)
@@ -1857,6 +1877,7 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
       E[t * ST + brev_c(i, 5) * SK + p] = i == 0 ? v[0] : cmulf(v[i], w);
     }
     __syncthreads();
+    fetch_part(3);
     {
       float2 *row = E + tr * ST + k1r * SK + h;
       float2 a[32];
@@ -1895,18 +1916,19 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
 }
 
 // acc += sum over u = u0, u0 + du, ... < nq of M[u Ld] w_u, w_u advancing by
-// st per term; the loads go out eight at a time
+// st per term; the loads go out CH at a time
+template <int CH>
 __device__ __forceinline__ void col_sum(const float2 *M, uint64_t Ld, int u0, int du, int nq, double2 w,
                                         double2 st, double2 &acc) {
-  for (int ub = u0; ub < nq; ub += 8 * du) {
-    float2 mv[8];
+  for (int ub = u0; ub < nq; ub += CH * du) {
+    float2 mv[CH];
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
+    for (int j = 0; j < CH; j++) {
       const int u = ub + j * du;
       mv[j] = u < nq ? M[(uint64_t)u * Ld] : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int j = 0; j < 8; j++) {
+    for (int j = 0; j < CH; j++) {
       acc.x += (double)mv[j].x * w.x - (double)mv[j].y * w.y;
       acc.y += (double)mv[j].x * w.y + (double)mv[j].y * w.x;
       w = cmul(w, st);
@@ -1973,7 +1995,7 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
             double2 w = unit_d((cs * ((tr - tau) & (N - 1))) & (N - 1), N, -1);
             const double2 st = unit_d((cs * Ld) & (N - 1), N, -1);
             double2 acc = make_double2(0.0, 0.0);
-            col_sum(M + tr, Ld, 0, 1, nq, w, st, acc);
+            col_sum<8>(M + tr, Ld, 0, 1, nq, w, st, acc);
             const double sc = 1.0 / (double)Bd;
             Ys[g][oi][i] = make_double2(acc.x * sc, acc.y * sc);
           }
@@ -2005,7 +2027,7 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
                 const uint64_t tr = tau & (Lde - 1);
                 const uint64_t t0 = tr + (uint64_t)uu * Lde;
                 double2 w = unit_d((cs * ((t0 - tau) & (Ne - 1))) & (Ne - 1), Ne, -1);
-                col_sum(Me + tr, Lde, uu, 8, nq, w, st, acc);
+                col_sum<8>(Me + tr, Lde, uu, 8, nq, w, st, acc);
               }
               for (int o = 4; o >= 1; o >>= 1) {
                 acc.x += __shfl_xor(acc.x, o);

@@ -153,14 +153,14 @@ def test_mixed_batch_matches_oracle(sfft):
 
 
 @pytest.mark.parametrize("N,B0,gap", [
-    (2 ** 16, 1024, 32 * 1024),        # L = 64: the pair splits at depth 6, row in LDS
+    (2 ** 16, 1024, 32 * 1024),        # L = 64: the pair splits at depth 6
     (2 ** 17, 2048, 32 * 2048),        # L = 64, width 2048
-    (2 ** 22, 1024, 2048 * 1024),      # L = 4096: splits at depth 12, row read from HBM
+    (2 ** 22, 1024, 2048 * 1024),      # L = 4096: the pair splits at depth 12
 ])
 def test_deep_pairs_match_oracle(sfft, N, B0, gap):
     """Pairs of tones in one level-0 class that agree on every level down to
-    depth d - 1 (f2 = f1 + gap, gap = B0 2^(d-1)) keep their class open into
-    the deep part of the resolve."""
+    depth d - 1 (f2 = f1 + gap, gap = B0 2^(d-1)) keep their class open past
+    depth 5, where the whole wave shares each class-vector sum."""
     rng = np.random.default_rng(N + B0)
     base = [int(f) for f in rng.choice(N - gap, 6, replace=False)]
     sup = sorted(set(base + [f + gap for f in base]))

@@ -29,7 +29,7 @@ constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses spl
 constexpr int kColThreads = 512;     // work-group of the level-1 column pass
 constexpr int kColQ = 32;            // column pass: B0 = P x 32, 32 rows per thread
 constexpr int kColResolveCap = 128;  // open subclasses per depth of one class
-constexpr int kColGroupLg = 2;      // column resolve: 2^2 lanes per class
+constexpr int kColGroupLg = 3;      // column resolve: 2^3 lanes per class
 constexpr int kColGroup = 1 << kColGroupLg;
 constexpr int kColLaneDepth = 5;    // ... one lane per class-vector sum down to this depth
 

@@ -108,7 +108,8 @@ struct Arena {
   const float2 *tw;       // e^{-2 pi i k / kFftMax}, k < kFftMax
 };
 
-// host-side kernel launchers (sfft_kernels.hip)
+// host-side kernel launchers (sfft_level0.hip, sfft_ffast.hip, sfft_tree.hip,
+// sfft_jump.hip, sfft_col.hip, sfft_finalize.hip)
 struct LaunchCtx {
   const SigDesc *desc;
   const SigIO *io;        // per-signal pointers in device memory (batches), or
@@ -134,6 +135,7 @@ struct LaunchCtx {
 
 hipError_t launch_reset(const LaunchCtx &c, hipStream_t s);
 hipError_t launch_level0(const LaunchCtx &c, hipStream_t s);
+hipError_t launch_ffast(const LaunchCtx &c, hipStream_t s);
 hipError_t launch_sched(const LaunchCtx &c, int level, hipStream_t s);
 hipError_t launch_expand_fft(const LaunchCtx &c, int level, int grid, hipStream_t s);
 hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStream_t s);

@@ -113,6 +113,12 @@ def lib(path: str | None = None):
         L.orc_bin.restype = None
         L.orc_level0.argtypes = [ctypes.POINTER(Cfg), ctypes.c_void_p, ctypes.c_void_p]
         L.orc_level0.restype = ctypes.c_int
+        L.orc_classify_tree.argtypes = [ctypes.POINTER(Cfg), ctypes.c_void_p, ctypes.c_int64,
+                                        ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+        L.orc_classify_tree.restype = ctypes.c_int32
+        L.orc_estimate_noise.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_double]
+        L.orc_estimate_noise.restype = ctypes.c_double
         L.orc_solve.argtypes = [ctypes.POINTER(Cfg), ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p, ctypes.POINTER(Trace)]
         L.orc_solve.restype = ctypes.c_int64
@@ -187,6 +193,28 @@ def solve(cfg: Cfg, x, libpath=None):
     cnt = lib(libpath).orc_solve(ctypes.byref(cfg), x.ctypes.data, idx.ctypes.data,
                                  val.ctypes.data, ctypes.byref(tr))
     return idx, val, int(cnt), tr
+
+
+def classify_tree(cfg: Cfg, Y, cls: int, B: int, sref2: float = 0.0, noise_var: float = 0.0,
+                  libpath=None):
+    """Decision rule alone on one tree class vector Y (R*D complex values):
+    returns (class code, position, value)."""
+    Y = np.ascontiguousarray(np.asarray(Y, dtype=np.complex128))
+    if Y.shape != (cfg.R * cfg.D,):
+        raise ValueError("class vector must hold R*D values")
+    f = ctypes.c_int64(0)
+    a = np.zeros(2, dtype=np.float64)
+    code = lib(libpath).orc_classify_tree(ctypes.byref(cfg), Y.ctypes.data, int(cls), int(B),
+                                          float(sref2), float(noise_var), ctypes.byref(f),
+                                          a.ctypes.data)
+    return int(code), int(f.value), complex(a[0], a[1])
+
+
+def estimate_noise(pw, phi: float, libpath=None) -> float:
+    """Noise variance estimate from values B |yhat|^2 and the expected
+    noise-only fraction phi of the entries."""
+    pw = np.array(pw, dtype=np.float64)  # a copy: the oracle sorts in place
+    return float(lib(libpath).orc_estimate_noise(pw.ctypes.data, len(pw), float(phi)))
 
 
 def kay_phase(y, libpath=None) -> float:

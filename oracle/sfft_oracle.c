@@ -24,9 +24,12 @@
  * small-support case of Sect. 3.3, Table 1 by Monte Carlo; the two-ton
  * solve by the residue structure of the tree and the N=64 example; the
  * packet-erasure schedule by the six-identification N=20 example; Kay's
- * estimator by its noiseless limit and the Cramer-Rao bound), except the
- * noisy-mode thresholds (parity unpinned: the paper gives no values for T0,
- * T1; they are checked only through their noiseless limit and statistics).
+ * estimator by its noiseless limit and the Cramer-Rao bound).  The paper
+ * names the noisy-mode thresholds T0, T1 without values; the widths taken
+ * here are pinned to the laws they imply: the zero-ton rate of noise-only
+ * class vectors equals P[Gamma(n,1) <= n + zero_k sqrt(n)], the single-ton
+ * rate of located tones P[Gamma(n-1,1) <= n-1 + single_k sqrt(n-1)], and
+ * the noise estimate lies in the interval its order statistic implies.
  */
 #include "sfft_oracle.h"
 
@@ -482,6 +485,35 @@ static double estimate_noise(double *pw, int64_t cnt, double phi) {
   int64_t at = (int64_t)(p * (double)(cnt - 1));
   return pw[at] / -log(1.0 - p / phi);
 }
+
+static void tree_taus(const orc_cfg *c, cls_ctx *x);
+
+/* The decision rule alone, for tests: one tree class vector Y (R*D values,
+   interleaved re, im, measured with the plan's round shifts and delays) of
+   class c among B buckets through the classification above (Sect. 3.2,
+   Subproblems 1-2), with the given reference power (exact mode) or
+   time-domain noise variance (noisy mode).  Returns the class code; *f and
+   a[0..1] receive the located position and value (two-ton: the first). */
+int32_t orc_classify_tree(const orc_cfg *c, const double *Y, int64_t cls, int64_t B,
+                          double sref2, double noise_var, int64_t *f, double *a) {
+  cls_ctx cx;
+  memset(&cx, 0, sizeof(cx));
+  cx.c = c;
+  tree_taus(c, &cx);
+  cx.sref2 = sref2;
+  cx.noise_var = noise_var;
+  decision v = classify(&cx, (const cplx *)Y, cls, B);
+  if (f) *f = v.f;
+  if (a) {
+    a[0] = creal(v.a);
+    a[1] = cimag(v.a);
+  }
+  return v.cls;
+}
+
+/* The noise estimate of the general sparse case from cnt values B |yhat|^2
+   (sorted in place) with expected noise-only fraction phi. */
+double orc_estimate_noise(double *pw, int64_t cnt, double phi) { return estimate_noise(pw, cnt, phi); }
 
 /* ------------------------------------------------------------------ */
 /* Found list and finalisation (goal of Sect. 2.1: K positions, K values). */

@@ -89,6 +89,14 @@ void orc_bin(const float *x, int64_t N, int64_t B, uint64_t sigma, uint64_t tau,
 /* Level-0 class table: out[c][i] (interleaved re,im), n = R*D (tree) or
    the per-stage tables concatenated stage by stage (FFAST). */
 int orc_level0(const orc_cfg *c, const float *x, double *out);
+/* The decision rule of Sect. 3.2 (Subproblems 1-2) on one tree class vector
+   (n = R*D values, interleaved) of class cls among B buckets; returns the
+   class code (ORC_ZERO .. ORC_DOUBLE), *f and a[2] the position and value. */
+int32_t orc_classify_tree(const orc_cfg *c, const double *Y, int64_t cls, int64_t B,
+                          double sref2, double noise_var, int64_t *f, double *a);
+/* Noise variance estimate from cnt values B |yhat|^2 (sorted in place) and the
+   expected noise-only fraction phi of the entries. */
+double orc_estimate_noise(double *pw, int64_t cnt, double phi);
 int64_t orc_solve(const orc_cfg *c, const float *x, int64_t *out_idx,
                   double *out_val, orc_trace *tr);
 #endif

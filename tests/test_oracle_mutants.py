@@ -46,6 +46,18 @@ MUTANTS = {
     "rffast_decision_flipped": ("if (th >= TWO_PI / 2) lo += len;", "if (th < TWO_PI / 2) lo += len;"),
     "rffast_delay_spacing": ("return (c->rf_off[it] + ((uint64_t)t << it)) % (uint64_t)c->N;",
                              "return (c->rf_off[it] + ((uint64_t)t << (it + 1))) % (uint64_t)c->N;"),
+    "zero_width_x3": ("T0sq = sb2 * ((double)n + cf->zero_k * sqrt((double)n));",
+                      "T0sq = sb2 * ((double)n + 3.0 * cf->zero_k * sqrt((double)n));"),
+    "single_width_x3": ("T1sq = sb2 * ((double)(n - 1) + cf->single_k * sqrt((double)(n - 1)));",
+                        "T1sq = sb2 * ((double)(n - 1) + 3.0 * cf->single_k * sqrt((double)(n - 1)));"),
+    "single_n_for_n_minus_1": ("T1sq = sb2 * ((double)(n - 1) + cf->single_k * sqrt((double)(n - 1)));",
+                               "T1sq = sb2 * ((double)n + cf->single_k * sqrt((double)n));"),
+    "single_n_and_width_x3": ("T1sq = sb2 * ((double)(n - 1) + cf->single_k * sqrt((double)(n - 1)));",
+                              "T1sq = sb2 * ((double)n + 3.0 * cf->single_k * sqrt((double)n));"),
+    "bucket_noise_without_1_over_B": ("double sb2 = x->noise_var / (double)B;",
+                                      "double sb2 = x->noise_var;"),
+    "noise_estimate_ignores_phi": ("return pw[at] / -log(1.0 - p / phi);",
+                                   "return pw[at] / -log(1.0 - p);"),
     "mpp_value_cross_term": ("cplx a0 = (nn * q0 - s01 * q1) / dv;",
                              "cplx a0 = (nn * q0 + s01 * q1) / dv;"),
 }
@@ -159,7 +171,28 @@ def battery(libpath):
                 return False
         return True
 
-    for name, fn in [("rffast", rffast), ("packet_erasure", packet_erasure), ("aliasing", aliasing), ("exact_tree", exact_tree), ("n20", n20),
+    def noisy_rules():
+        from tests import test_oracle_noisy_pins as nz
+        import math
+        from scipy import stats
+        n, trials = nz.R * nz.D, 4000
+        cfg = nz.cfg_with(zero_k=1.0, single_k=1.0, libpath=libpath)
+        p0 = stats.gamma.cdf(n + math.sqrt(n), n)
+        if not nz.within_band(nz.zero_rate(cfg, trials, 3, libpath=libpath), trials, p0):
+            return False
+        p1 = stats.gamma.cdf(n - 1 + math.sqrt(n - 1), n - 1)
+        hits, located = nz.single_rate(cfg, trials, 4, libpath=libpath)
+        if located != trials or not nz.within_band(hits, trials, p1):
+            return False
+        rng = np.random.default_rng(9)
+        cnt, phi = 4096, 0.6
+        m_noise = int(round(phi * cnt))
+        p = min(0.25, phi / 2)
+        lo, hi = nz._estimate_interval(int(p * (cnt - 1)) + 1, m_noise, -math.log(1 - p / phi))
+        pw = np.concatenate([rng.exponential(1.0, m_noise), 1e6 * (1 + rng.uniform(size=cnt - m_noise))])
+        return lo <= oracle.estimate_noise(pw, phi, libpath=libpath) <= hi
+
+    for name, fn in [("noisy_rules", noisy_rules), ("rffast", rffast), ("packet_erasure", packet_erasure), ("aliasing", aliasing), ("exact_tree", exact_tree), ("n20", n20),
                      ("n64", n64), ("splitmix", splitmix), ("topk", topk), ("noisy", noisy),
                      ("two_tons", two_tons)]:
         check(name, fn)

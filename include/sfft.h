@@ -279,6 +279,41 @@ int32_t sfft_bucketize(sfft_plan_t plan, const void *x, void *out);
 int32_t sfft_exec_stats(sfft_plan_t plan, sfft_stats_t *out);
 int32_t sfft_batch_stats(const sfft_plan_t *plans, int32_t n, int32_t i, sfft_stats_t *out);
 
+/* Device workspace of a batch, computed on the host from the plans alone (no
+   device call, no allocation): the size of the one device slab that an exec
+   of this plan list works in, and the element count of each arena in it --
+   for admission by HBM footprint and for checking the kernels' indexing
+   against what is allocated.  The workspace holds the level-0 buckets of
+   Eq. 5-6, the class lists of the tree search (Sect. 3.3) and the peeling
+   state (Sect. 3.2, Eq. 20).  sig (optional) receives n per-signal records.
+   Returns SFFT_OK or SFFT_EINVAL. */
+typedef struct {
+  int64_t bytes;       /* device slab of the batch */
+  int64_t y0;          /* level-0 planes, complex64 */
+  int64_t fst;         /* FFAST peeling state, complex128 */
+  int64_t found;       /* found-list slots (int64 position + complex128 value) */
+  int64_t multi;       /* multi-ton slots per level parity */
+  int64_t multi_vec;   /* class-vector entries per level parity (multi x nmax) */
+  int64_t jacc;        /* dense-pass coefficients, complex128 (multi x jstride, or 0) */
+  int64_t jcol;        /* column-pass rows, complex64 */
+  int32_t nmax;        /* class-vector stride of the multi-ton arenas */
+  int32_t jstride;     /* dense-pass coefficients per multi-ton slot */
+  int32_t levels;      /* tree levels launched after level 0 */
+  int32_t nsig;
+} sfft_workspace_t;
+
+typedef struct {
+  int64_t y0_off, fst_off, found_off, multi_off, jcol_off;  /* element offsets */
+  int32_t found_cap, multi_cap;
+  int32_t n;           /* measurements per class vector */
+  int32_t l1;          /* 1: takes the level-1 column pass */
+  int32_t jump_L;      /* dense-pass stride in effect (0: off) */
+  int32_t pad;
+} sfft_workspace_signal_t;
+
+int32_t sfft_workspace(const sfft_plan_t *plans, int32_t n, sfft_workspace_t *out,
+                       sfft_workspace_signal_t *sig);
+
 /* Release every cached batch context (graphs, workspaces). */
 void sfft_release_batches(void);
 

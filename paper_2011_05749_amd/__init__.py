@@ -97,6 +97,25 @@ class Stats(ctypes.Structure):
     ]
 
 
+class Workspace(ctypes.Structure):
+    _fields_ = [
+        ("bytes", ctypes.c_int64), ("y0", ctypes.c_int64), ("fst", ctypes.c_int64),
+        ("found", ctypes.c_int64), ("multi", ctypes.c_int64), ("multi_vec", ctypes.c_int64),
+        ("jacc", ctypes.c_int64), ("jcol", ctypes.c_int64),
+        ("nmax", ctypes.c_int32), ("jstride", ctypes.c_int32), ("levels", ctypes.c_int32),
+        ("nsig", ctypes.c_int32),
+    ]
+
+
+class WorkspaceSignal(ctypes.Structure):
+    _fields_ = [
+        ("y0_off", ctypes.c_int64), ("fst_off", ctypes.c_int64), ("found_off", ctypes.c_int64),
+        ("multi_off", ctypes.c_int64), ("jcol_off", ctypes.c_int64),
+        ("found_cap", ctypes.c_int32), ("multi_cap", ctypes.c_int32), ("n", ctypes.c_int32),
+        ("l1", ctypes.c_int32), ("jump_L", ctypes.c_int32), ("pad", ctypes.c_int32),
+    ]
+
+
 KERNEL_NAMES = {0: "k_reset", 1: "k_level0", 2: "k_sched", 3: "k_expand_fft",
                 4: "k_expand_direct", 5: "k_children", 6: "k_finalize", 7: "k_jump_pass",
                 8: "k_jump_resolve", 9: "k_col_pass", 10: "k_col_resolve"}
@@ -134,6 +153,8 @@ _lib.sfft_exec_stats.argtypes = [_vp, ctypes.POINTER(Stats)]
 _lib.sfft_exec_stats.restype = ctypes.c_int32
 _lib.sfft_batch_stats.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Stats)]
 _lib.sfft_batch_stats.restype = ctypes.c_int32
+_lib.sfft_workspace.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(Workspace), _vp]
+_lib.sfft_workspace.restype = ctypes.c_int32
 _lib.sfft_release_batches.argtypes = []
 _lib.sfft_release_batches.restype = None
 _lib.sfft_last_error.argtypes = []
@@ -145,6 +166,7 @@ EXPORTS = ["sfft_params_init", "sfft_plan", "sfft_plan_ex", "sfft_plan_info", "s
            "sfft_exec", "sfft_exec_host", "sfft_exec_async", "sfft_exec_batch", "sfft_exec_batch_ex",
            "sfft_exec_batch_profile",
            "sfft_bucketize", "sfft_exec_stats", "sfft_batch_stats", "sfft_release_batches",
+           "sfft_workspace",
            "sfft_last_error", "sfft_strerror"]
 
 
@@ -353,6 +375,18 @@ def exec_batch(plans, xs, graph: bool = True, stream=None):
     b = Batch(plans, xs)
     b.run(graph=graph, stream=stream)
     return b
+
+
+def workspace(plans):
+    """Device workspace of a batch of these plans (host-only; no device call):
+    (arena sizes as a dict, one dict of offsets per signal)."""
+    n = len(plans)
+    w = Workspace()
+    sig = (WorkspaceSignal * n)()
+    _check(_lib.sfft_workspace(_ptr_array([p.handle for p in plans]), n, ctypes.byref(w),
+                               ctypes.cast(sig, ctypes.c_void_p)), "sfft_workspace")
+    return ({f: getattr(w, f) for f, _ in Workspace._fields_},
+            [{f: getattr(x, f) for f, _ in WorkspaceSignal._fields_} for x in sig])
 
 
 def release_batches():

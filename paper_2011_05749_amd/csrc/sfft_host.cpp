@@ -136,14 +136,286 @@ int jump_level(const SigDesc &d) {
   return d.max_levels + 1;
 }
 
+constexpr size_t kSlabAlign = 256;
+size_t align_up(size_t v) { return (v + kSlabAlign - 1) & ~(kSlabAlign - 1); }
+
+// Workspace of one batch, decided on the host from its plans alone: every
+// signal's descriptor with its offsets into the arenas, the work lists, the
+// size of every arena and its byte offset in one device slab, and the static
+// launch shape of every tree level.  No device call.
+struct Layout {
+  std::vector<SigDesc> desc;
+  std::vector<int32_t> lists;
+  int ntree = 0, nffast = 0;
+  size_t l0_at = 0, l0c_at = 0;
+  int32_t l0_items = 0, l0c_items = 0;
+  int nmax = 1, max_B0 = 1, max_stage = 1, max_found_cap = 64;
+  int32_t jrows = kJumpItemRows, any_fp32 = 0, col_lp_mask = 0, any_wide_jump = 0;
+  bool any_jump = false;
+  std::vector<LevelLaunch> levels;
+  // arena sizes in elements
+  int64_t n_y0 = 0, n_fst = 0, n_found = 0, n_multi = 0, n_mvec = 0, n_jacc = 0, n_jcol = 0;
+  // byte offsets of the parts of the slab, and its size
+  size_t o_desc = 0, o_io = 0, o_st = 0, o_lists = 0, o_pre = 0, o_out = 0, o_y0 = 0, o_fst = 0,
+         o_ff = 0, o_fa = 0, o_mc = 0, o_my = 0, o_mz = 0, o_jacc = 0, o_jcol = 0, bytes = 0;
+};
+
+int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, int ncu, Layout &Y) {
+  const int nsig = (int)ps.size();
+  Y = Layout{};
+  Y.desc.resize(nsig);
+  int64_t y0 = 0, fst = 0, fc = 0, mc = 0, jc = 0;
+  int nmax = 1, maxB0 = 1, maxStage = 1, maxFcap = 64;
+  std::vector<std::pair<int64_t, int>> tree, ffast;
+  for (int s = 0; s < nsig; s++) {
+    const sfft_plan_s *p = ps[s];
+    const sfft_plan_info_t &in = p->info;
+    SigDesc d{};
+    d.N = in.N;
+    d.K = in.K;
+    d.B0 = in.B0;
+    d.log2N = pow2(in.N) ? ilog2(in.N) : -1;
+    d.log2B0 = in.kind == SFFT_KIND_TREE ? ilog2(in.B0) : 0;
+    d.kind = in.kind;
+    d.mode = in.mode;
+    d.R = in.R;
+    d.D = in.D;
+    d.n = in.kind == SFFT_KIND_TREE ? in.R * in.D : in.D;
+    d.max_levels = in.max_levels;
+    d.window = in.window;
+    d.nstages = in.kind == SFFT_KIND_FFAST ? in.R : 0;
+    d.max_peel_rounds = in.max_peel_rounds;
+    d.found_cap = in.found_cap;
+    d.multi_cap = in.multi_cap;
+    d.l1 = (in.kind == SFFT_KIND_TREE && !no_jump && in.l1_resolve) ? 1 : 0;
+    d.jump_L = (in.kind == SFFT_KIND_TREE && !no_jump && !d.l1) ? in.jump_L : 0;
+    d.mpp = in.mpp;
+    d.precision = in.precision;
+    d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
+    d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
+    d.rf_m = in.rf_m;
+    for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.rf_off[r] = in.rf_off[r];
+    for (int i = 0; i < SFFT_MAX_PEEL_STARTS; i++) d.start_f[i] = in.peel_start_f[i];
+    for (int j = 0; j < SFFT_MAX_STAGES; j++) d.stageB[j] = in.stage_B[j];
+    for (int j = 0; j <= SFFT_MAX_STAGES; j++) d.stageOff[j] = p->stage_off[j];
+    for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.shift[r] = in.shift[r];
+    d.eps0 = in.eps0;
+    d.eps1 = in.eps1;
+    d.zero_k = in.zero_k;
+    d.single_k = in.single_k;
+    d.noise_var = in.noise_var;
+    d.noise_p_den = p->noise_p_den;
+    d.noise_at = p->noise_at;
+    d.y0_off = y0;
+    d.found_off = fc;
+    d.multi_off = mc;
+    d.fst_off = fst;
+    d.jc_off = jc;
+    if (in.kind == SFFT_KIND_TREE) {
+      y0 += (int64_t)d.n * in.B0;
+      mc += d.multi_cap;
+      if (d.l1) jc += (int64_t)d.multi_cap * (in.N / in.B0);
+      tree.push_back({(int64_t)d.n * in.B0 * (in.max_levels + 1), s});
+      maxB0 = std::max<int64_t>(maxB0, in.B0);
+    } else {
+      y0 += (int64_t)in.D * p->nb;
+      fst += p->nb * (2 * (int64_t)in.D + 2);
+      ffast.push_back({(int64_t)in.D * p->nb, s});
+      for (int j = 0; j < in.R; j++) maxStage = std::max<int64_t>(maxStage, in.stage_B[j]);
+    }
+    fc += d.found_cap;
+    nmax = std::max(nmax, d.n);
+    maxFcap = std::max(maxFcap, d.found_cap);
+    Y.desc[s] = d;
+  }
+  for (int s = 0; s < nsig; s++)
+    if (Y.desc[s].kind == SFFT_KIND_TREE && jump_level(Y.desc[s]) <= Y.desc[s].max_levels) Y.any_jump = true;
+  // longest solves first (LPT order) for the persistent level-0 launches
+  std::stable_sort(tree.begin(), tree.end(), [](auto &a, auto &b) { return a.first > b.first; });
+  std::stable_sort(ffast.begin(), ffast.end(), [](auto &a, auto &b) { return a.first > b.first; });
+  for (auto &t : tree) Y.lists.push_back(t.second);
+  for (auto &t : ffast) Y.lists.push_back(t.second);
+  // level-0 item prefixes over the tree list: rounds, and 256-class chunks
+  Y.l0_at = Y.lists.size();
+  int32_t acc0 = 0;
+  for (auto &t : tree) {
+    Y.lists.push_back(acc0);
+    acc0 += Y.desc[t.second].R;
+  }
+  Y.lists.push_back(acc0);
+  Y.l0c_at = Y.lists.size();
+  int32_t acc1 = 0;
+  for (auto &t : tree) {
+    Y.lists.push_back(acc1);
+    acc1 += (int32_t)((Y.desc[t.second].B0 + kThreads - 1) / kThreads);
+  }
+  Y.lists.push_back(acc1);
+  Y.lists.push_back(0);
+  Y.ntree = (int)tree.size();
+  Y.nffast = (int)ffast.size();
+  Y.l0_items = acc0;
+  Y.l0c_items = acc1;
+  Y.nmax = nmax;
+  Y.max_B0 = maxB0;
+  Y.max_stage = maxStage;
+  Y.max_found_cap = (int)npow2(maxFcap);
+  // dense-pass items: 4096 rows for batches of 64 signals or more, fewer
+  // rows (more work-groups per signal) for smaller batches
+  Y.jrows = kJumpItemRows;
+  while (Y.jrows > kJumpItemRowsMin && (int64_t)Y.jrows * 64 > (int64_t)kJumpItemRows * nsig) Y.jrows >>= 1;
+  for (int s = 0; s < nsig; s++) {
+    const SigDesc &d = Y.desc[s];
+    if (d.kind == SFFT_KIND_TREE && d.precision == 1) Y.any_fp32 = 1;
+    if (d.l1) Y.col_lp_mask |= 1 << (d.log2B0 - 10);  // bit LP - 5, B0 = 2^(LP + 5)
+    if (d.kind == SFFT_KIND_TREE && d.jump_L >= (1 << kJumpMfmaMinLg)) Y.any_wide_jump = 1;
+  }
+  // arenas
+  Y.n_y0 = y0;
+  Y.n_fst = fst;
+  Y.n_found = fc;
+  Y.n_multi = mc;
+  Y.n_mvec = mc * (int64_t)nmax;  // multi-ton vectors use the batch-wide stride nmax
+  Y.n_jacc = Y.any_jump ? mc * (int64_t)kJumpMax : 0;
+  Y.n_jcol = jc;
+  const size_t ns = (size_t)nsig;
+  size_t o = 0;
+  auto part = [&](size_t &off, size_t bytes) {
+    off = o;
+    o = align_up(o + bytes);
+  };
+  part(Y.o_desc, sizeof(SigDesc) * ns);
+  part(Y.o_io, sizeof(SigIO) * ns);
+  part(Y.o_st, sizeof(SigState) * ns);
+  part(Y.o_lists, sizeof(int32_t) * Y.lists.size());
+  part(Y.o_pre, kPre * sizeof(int32_t) * (ns + 1));
+  part(Y.o_out, (sizeof(int64_t) + sizeof(int32_t)) * 2);
+  part(Y.o_y0, sizeof(float2) * (size_t)Y.n_y0);
+  part(Y.o_fst, sizeof(double2) * (size_t)Y.n_fst);
+  part(Y.o_ff, sizeof(int64_t) * (size_t)Y.n_found);
+  part(Y.o_fa, sizeof(double2) * (size_t)Y.n_found);
+  part(Y.o_mc, 2 * sizeof(int64_t) * (size_t)Y.n_multi);
+  part(Y.o_my, 2 * sizeof(float2) * (size_t)Y.n_mvec);
+  part(Y.o_mz, 2 * sizeof(double2) * (size_t)Y.n_mvec);
+  part(Y.o_jacc, sizeof(double2) * (size_t)Y.n_jacc);
+  part(Y.o_jcol, sizeof(float2) * (size_t)Y.n_jcol);
+  Y.bytes = o;
+  // static launch shape of every tree level: a signal gathers level by level
+  // before its jump level, runs the dense pass and the subtree resolution at
+  // it, and has no work after it
+  int last = 0;
+  for (int s = 0; s < nsig; s++) {
+    const SigDesc &d = Y.desc[s];
+    if (d.kind == SFFT_KIND_TREE)
+      last = std::max(last, d.l1 ? 1 : std::min(d.max_levels, jump_level(d) + 1));
+  }
+  for (int l = 1; l <= last; l++) {
+    LevelLaunch L{};
+    int64_t nf = 0, nd = 0, nch = 0, nj = 0, nr = 0, ncol = 0, ncr = 0;
+    for (int s = 0; s < nsig; s++) {
+      const SigDesc &d = Y.desc[s];
+      if (d.kind != SFFT_KIND_TREE || l > d.max_levels) continue;
+      if (d.l1) {
+        if (l == 1) {
+          ncol += (d.N >> d.log2B0) / (kColThreads / (d.B0 / kColQ));
+          ncr += d.multi_cap;
+        }
+        continue;
+      }
+      const int jl = jump_level(d);
+      if (l > jl + 1) continue;
+      const int64_t Bp = d.B0 << (l - 1);
+      if (l >= jl) {  // the dense pass may run at jl (few classes) and runs at jl + 1
+        nj += (Bp + Y.jrows - 1) / Y.jrows;
+        nr += d.multi_cap;
+      }
+      if (l > jl) continue;
+      const int64_t Bsmax = int64_t(1) << split_lg(d.D);
+      if (Bp <= Bsmax) {
+        nf += d.R;
+      } else {
+        nf += (int64_t)d.R * (Bp / Bsmax);
+        nd += (int64_t)d.R * ((Bp + kChunk - 1) / kChunk);
+      }
+      nch += 2 * (int64_t)d.multi_cap;
+    }
+    L.fft = nf > 0;
+    L.direct = nd > 0;
+    L.children = nch > 0;
+    L.jump = nj > 0;
+    L.col = ncol > 0;
+    // column pass: one resident work-group per CU (a multiple of 16, for the
+    // XCD pairing of its items)
+    L.grid_col = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)ncu & ~15, ((ncol + 15) / 16) * 16));
+    L.grid_col_resolve = (int)std::min<int64_t>(std::max<int64_t>((ncr + 64 / kColGroup - 1) / (64 / kColGroup), 1), 4096);
+    L.grid_fft = (int)std::min<int64_t>(std::max<int64_t>(nf, 1), 4096);
+    L.grid_direct = (int)std::min<int64_t>(std::max<int64_t>(nd, 1), 8192);
+    L.grid_children = (int)std::min<int64_t>(std::max<int64_t>((nch + kThreads - 1) / kThreads, 1), 2048);
+    L.grid_jump = (int)std::min<int64_t>(std::max<int64_t>(nj, 1), 8192);
+    L.grid_resolve = (int)std::min<int64_t>(std::max<int64_t>(nr, 1), 4096);
+    Y.levels.push_back(L);
+  }
+  return SFFT_OK;
+}
+
+// Launch context of a layout placed at `base` (a device slab of Y.bytes whose
+// descriptor and list parts hold Y.desc and Y.lists).
+void bind_layout(const Layout &Y, char *base, const float2 *tw, LaunchCtx &c) {
+  c = LaunchCtx{};
+  c.desc = (const SigDesc *)(base + Y.o_desc);
+  c.io = nullptr;
+  c.st = (SigState *)(base + Y.o_st);
+  c.A.y0 = (float2 *)(base + Y.o_y0);
+  c.A.fst = (double2 *)(base + Y.o_fst);
+  c.A.found_f = (int64_t *)(base + Y.o_ff);
+  c.A.found_a = (double2 *)(base + Y.o_fa);
+  c.A.multi_c[0] = (int64_t *)(base + Y.o_mc);
+  c.A.multi_c[1] = (int64_t *)(base + Y.o_mc) + Y.n_multi;
+  c.A.multi_y[0] = (float2 *)(base + Y.o_my);
+  c.A.multi_y[1] = (float2 *)(base + Y.o_my) + Y.n_mvec;
+  c.A.multi_z[0] = (double2 *)(base + Y.o_mz);
+  c.A.multi_z[1] = (double2 *)(base + Y.o_mz) + Y.n_mvec;
+  c.A.pre = (int32_t *)(base + Y.o_pre);
+  c.A.jacc = (double2 *)(base + Y.o_jacc);
+  c.A.jcol = (float2 *)(base + Y.o_jcol);
+  c.A.tw = tw;
+  const int32_t *lists = (const int32_t *)(base + Y.o_lists);
+  c.tree_list = lists;
+  c.ffast_list = lists + Y.ntree;
+  c.l0_pre = lists + Y.l0_at;
+  c.l0c_pre = lists + Y.l0c_at;
+  c.l0_items = Y.l0_items;
+  c.l0c_items = Y.l0c_items;
+  c.jstride = kJumpMax;
+  c.jrows = Y.jrows;
+  c.any_fp32 = Y.any_fp32;
+  c.col_lp_mask = Y.col_lp_mask;
+  c.any_wide_jump = Y.any_wide_jump;
+  c.nsig = (int32_t)Y.desc.size();
+  c.ntree = Y.ntree;
+  c.nffast = Y.nffast;
+  c.nmax = Y.nmax;
+  c.max_B0 = Y.max_B0;
+  c.max_stage_B = Y.max_stage;
+  c.max_found_cap = Y.max_found_cap;
+}
+
+int device_cus(int device) {
+  int ncu = 256;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 16) {
+    (void)hipGetLastError();
+    ncu = 256;
+  }
+  return ncu;
+}
+
 struct BatchCtx {
   int device = -1;
   std::vector<const sfft_plan_s *> plans;
   int nsig = 0;
-  std::vector<SigDesc> desc;
-  DevBuf b_desc, b_io, b_st, b_lists, b_y0, b_fst, b_ff, b_fa, b_mc, b_my, b_mz, b_pre, b_out, b_jacc, b_jcol;
+  Layout lay;
+  DevBuf slab;
+  char *base = nullptr;
   LaunchCtx lc{};
-  std::vector<LevelLaunch> levels;
   std::vector<SigIO> io_last;
   SigIO *io_pinned = nullptr;
   hipStream_t stream = nullptr;
@@ -159,229 +431,30 @@ struct BatchCtx {
     if (ev_io) (void)hipEventDestroy(ev_io);
     if (io_pinned) (void)hipHostFree(io_pinned);
   }
+  SigIO *io_dev() const { return (SigIO *)(base + lay.o_io); }
+  SigState *st_dev() const { return (SigState *)(base + lay.o_st); }
+  int64_t *count_dev() const { return (int64_t *)(base + lay.o_out); }
+  int32_t *status_dev() const { return (int32_t *)((int64_t *)(base + lay.o_out) + 2); }
 
   int32_t build(const std::vector<const sfft_plan_s *> &ps, bool no_jump = false) {
     plans = ps;
     nsig = (int)ps.size();
     if (hipGetDevice(&device) != hipSuccess) return SFFT_EDEVICE;
-    desc.resize(nsig);
-    int64_t y0 = 0, fst = 0, fc = 0, mc = 0, mz = 0, jc = 0;
-    int nmax = 1, maxB0 = 1, maxStage = 1, maxFcap = 64, maxLevels = 0;
-    std::vector<std::pair<int64_t, int>> tree, ffast;
-    for (int s = 0; s < nsig; s++) {
-      const sfft_plan_s *p = ps[s];
-      const sfft_plan_info_t &in = p->info;
-      SigDesc d{};
-      d.N = in.N;
-      d.K = in.K;
-      d.B0 = in.B0;
-      d.log2N = pow2(in.N) ? ilog2(in.N) : -1;
-      d.log2B0 = in.kind == SFFT_KIND_TREE ? ilog2(in.B0) : 0;
-      d.kind = in.kind;
-      d.mode = in.mode;
-      d.R = in.R;
-      d.D = in.D;
-      d.n = in.kind == SFFT_KIND_TREE ? in.R * in.D : in.D;
-      d.max_levels = in.max_levels;
-      d.window = in.window;
-      d.nstages = in.kind == SFFT_KIND_FFAST ? in.R : 0;
-      d.max_peel_rounds = in.max_peel_rounds;
-      d.found_cap = in.found_cap;
-      d.multi_cap = in.multi_cap;
-      d.l1 = (in.kind == SFFT_KIND_TREE && !no_jump && in.l1_resolve) ? 1 : 0;
-      d.jump_L = (in.kind == SFFT_KIND_TREE && !no_jump && !d.l1) ? in.jump_L : 0;
-      d.mpp = in.mpp;
-      d.precision = in.precision;
-      d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
-      d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
-      d.rf_m = in.rf_m;
-      for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.rf_off[r] = in.rf_off[r];
-      for (int i = 0; i < SFFT_MAX_PEEL_STARTS; i++) d.start_f[i] = in.peel_start_f[i];
-      for (int j = 0; j < SFFT_MAX_STAGES; j++) d.stageB[j] = in.stage_B[j];
-      for (int j = 0; j <= SFFT_MAX_STAGES; j++) d.stageOff[j] = p->stage_off[j];
-      for (int r = 0; r < SFFT_MAX_ROUNDS; r++) d.shift[r] = in.shift[r];
-      d.eps0 = in.eps0;
-      d.eps1 = in.eps1;
-      d.zero_k = in.zero_k;
-      d.single_k = in.single_k;
-      d.noise_var = in.noise_var;
-      d.noise_p_den = p->noise_p_den;
-      d.noise_at = p->noise_at;
-      d.y0_off = y0;
-      d.found_off = fc;
-      d.multi_off = mc;
-      d.fst_off = fst;
-      d.jc_off = jc;
-      if (in.kind == SFFT_KIND_TREE) {
-        y0 += (int64_t)d.n * in.B0;
-        mc += d.multi_cap;
-        if (d.l1) jc += (int64_t)d.multi_cap * (in.N / in.B0);
-
-        tree.push_back({(int64_t)d.n * in.B0 * (in.max_levels + 1), s});
-        maxB0 = std::max<int64_t>(maxB0, in.B0);
-        maxLevels = std::max(maxLevels, in.max_levels);
-      } else {
-        y0 += (int64_t)in.D * p->nb;
-        fst += p->nb * (2 * (int64_t)in.D + 2);
-        ffast.push_back({(int64_t)in.D * p->nb, s});
-        for (int j = 0; j < in.R; j++) maxStage = std::max<int64_t>(maxStage, in.stage_B[j]);
-      }
-      fc += d.found_cap;
-      nmax = std::max(nmax, d.n);
-      maxFcap = std::max(maxFcap, d.found_cap);
-      desc[s] = d;
-    }
-    mz = mc * (int64_t)nmax;  // multi-ton vectors use the batch-wide stride nmax
-    bool any_jump = false;
-    for (int s = 0; s < nsig; s++)
-      if (desc[s].kind == SFFT_KIND_TREE && jump_level(desc[s]) <= desc[s].max_levels) any_jump = true;
-    // dense-pass coefficients per multi-ton slot: the widest stride any plan may use
-    const int jstride = kJumpMax;
-    // longest solves first (LPT order) for the persistent level-0 launches
-    std::stable_sort(tree.begin(), tree.end(), [](auto &a, auto &b) { return a.first > b.first; });
-    std::stable_sort(ffast.begin(), ffast.end(), [](auto &a, auto &b) { return a.first > b.first; });
-    std::vector<int32_t> lists;
-    for (auto &t : tree) lists.push_back(t.second);
-    for (auto &t : ffast) lists.push_back(t.second);
-    // level-0 item prefixes over the tree list: rounds, and 256-class chunks
-    const size_t l0_at = lists.size();
-    int32_t acc0 = 0;
-    for (auto &t : tree) {
-      lists.push_back(acc0);
-      acc0 += desc[t.second].R;
-    }
-    lists.push_back(acc0);
-    const size_t l0c_at = lists.size();
-    int32_t acc1 = 0;
-    for (auto &t : tree) {
-      lists.push_back(acc1);
-      acc1 += (int32_t)((desc[t.second].B0 + kThreads - 1) / kThreads);
-    }
-    lists.push_back(acc1);
-    auto ck = [](hipError_t e) { return e == hipSuccess; };
-    const size_t ns = (size_t)nsig;
-    if (!ck(b_desc.alloc(sizeof(SigDesc) * ns)) || !ck(b_io.alloc(sizeof(SigIO) * ns)) ||
-        !ck(b_st.alloc(sizeof(SigState) * ns)) || !ck(b_lists.alloc(sizeof(int32_t) * (lists.size() + 1))) ||
-        !ck(b_y0.alloc(sizeof(float2) * (size_t)y0)) || !ck(b_fst.alloc(sizeof(double2) * (size_t)fst)) ||
-        !ck(b_ff.alloc(sizeof(int64_t) * (size_t)fc)) || !ck(b_fa.alloc(sizeof(double2) * (size_t)fc)) ||
-        !ck(b_mc.alloc(2 * sizeof(int64_t) * (size_t)mc)) || !ck(b_my.alloc(2 * sizeof(float2) * (size_t)mz)) ||
-        !ck(b_mz.alloc(2 * sizeof(double2) * (size_t)mz)) || !ck(b_pre.alloc(kPre * sizeof(int32_t) * (ns + 1))) ||
-        !ck(b_jacc.alloc(sizeof(double2) * (size_t)(any_jump ? mc * jstride : 1))) ||
-        !ck(b_jcol.alloc(sizeof(float2) * (size_t)(jc > 0 ? jc : 1))) ||
-        !ck(b_out.alloc((sizeof(int64_t) + sizeof(int32_t)) * 2)))
-      return SFFT_ENOMEM;
-    if (hipMemcpy(b_desc.p, desc.data(), sizeof(SigDesc) * ns, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b_lists.p, lists.data(), sizeof(int32_t) * lists.size(), hipMemcpyHostToDevice) != hipSuccess)
+    int32_t rc = make_layout(ps, no_jump, device_cus(device), lay);
+    if (rc != SFFT_OK) return rc;
+    if (slab.alloc(lay.bytes) != hipSuccess) return SFFT_ENOMEM;
+    base = (char *)slab.p;
+    if (hipMemcpy(base + lay.o_desc, lay.desc.data(), sizeof(SigDesc) * lay.desc.size(),
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + lay.o_lists, lay.lists.data(), sizeof(int32_t) * lay.lists.size(),
+                  hipMemcpyHostToDevice) != hipSuccess)
       return SFFT_EDEVICE;
     const float2 *tw = nullptr;
     if (device_twiddles(device, &tw) != hipSuccess) return SFFT_EDEVICE;
-    LaunchCtx &c = lc;
-    c.desc = (const SigDesc *)b_desc.p;
-    c.io = nullptr;
-    c.st = (SigState *)b_st.p;
-    c.A.y0 = (float2 *)b_y0.p;
-    c.A.fst = (double2 *)b_fst.p;
-    c.A.found_f = (int64_t *)b_ff.p;
-    c.A.found_a = (double2 *)b_fa.p;
-    c.A.multi_c[0] = (int64_t *)b_mc.p;
-    c.A.multi_c[1] = (int64_t *)b_mc.p + mc;
-    c.A.multi_y[0] = (float2 *)b_my.p;
-    c.A.multi_y[1] = (float2 *)b_my.p + mz;
-    c.A.multi_z[0] = (double2 *)b_mz.p;
-    c.A.multi_z[1] = (double2 *)b_mz.p + mz;
-    c.A.pre = (int32_t *)b_pre.p;
-    c.A.jacc = (double2 *)b_jacc.p;
-    c.A.jcol = (float2 *)b_jcol.p;
-    c.A.tw = tw;
-    c.tree_list = (const int32_t *)b_lists.p;
-    c.ffast_list = (const int32_t *)b_lists.p + tree.size();
-    c.l0_pre = (const int32_t *)b_lists.p + l0_at;
-    c.l0c_pre = (const int32_t *)b_lists.p + l0c_at;
-    c.l0_items = acc0;
-    c.l0c_items = acc1;
-    c.jstride = jstride;
-    // dense-pass items: 4096 rows for batches of 64 signals or more, fewer
-    // rows (more work-groups per signal) for smaller batches
-    c.jrows = kJumpItemRows;
-    while (c.jrows > kJumpItemRowsMin && (int64_t)c.jrows * 64 > (int64_t)kJumpItemRows * nsig) c.jrows >>= 1;
-    c.any_fp32 = 0;
-    for (int s = 0; s < nsig; s++)
-      if (desc[s].kind == SFFT_KIND_TREE && desc[s].precision == 1) c.any_fp32 = 1;
-    c.col_lp_mask = 0;
-    for (int s = 0; s < nsig; s++)
-      if (desc[s].l1) c.col_lp_mask |= 1 << (desc[s].log2B0 - 10);  // bit LP - 5, B0 = 2^(LP + 5)
-    c.any_wide_jump = 0;
-    for (int s = 0; s < nsig; s++)
-      if (desc[s].kind == SFFT_KIND_TREE && desc[s].jump_L >= (1 << kJumpMfmaMinLg)) c.any_wide_jump = 1;
-    c.nsig = nsig;
-    c.ntree = (int)tree.size();
-    c.nffast = (int)ffast.size();
-    c.nmax = nmax;
-    c.max_B0 = maxB0;
-    c.max_stage_B = maxStage;
-    c.max_found_cap = (int)npow2(maxFcap);
-    // static launch shape of every tree level: a signal gathers level by level
-    // before its jump level, runs the dense pass and the subtree resolution at
-    // it, and has no work after it
-    levels.clear();
-    int ncu = 256;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || ncu < 16)
-      ncu = 256;
-    int last = 0;
-    for (int s = 0; s < nsig; s++)
-      if (desc[s].kind == SFFT_KIND_TREE)
-        last = std::max(last, desc[s].l1 ? 1 : std::min(desc[s].max_levels, jump_level(desc[s]) + 1));
-    (void)maxLevels;
-    for (int l = 1; l <= last; l++) {
-      LevelLaunch L{};
-      int64_t nf = 0, nd = 0, nch = 0, nj = 0, nr = 0, ncol = 0, ncr = 0;
-      for (int s = 0; s < nsig; s++) {
-        const SigDesc &d = desc[s];
-        if (d.kind != SFFT_KIND_TREE || l > d.max_levels) continue;
-        if (d.l1) {
-          if (l == 1) {
-            ncol += (d.N >> d.log2B0) / (kColThreads / (d.B0 / kColQ));
-            ncr += d.multi_cap;
-          }
-          continue;
-        }
-        const int jl = jump_level(d);
-        if (l > jl + 1) continue;
-        const int64_t Bp = d.B0 << (l - 1);
-        if (l >= jl) {  // the dense pass may run at jl (few classes) and runs at jl + 1
-          nj += (Bp + c.jrows - 1) / c.jrows;
-          nr += d.multi_cap;
-        }
-        if (l > jl) continue;
-        const int64_t Bsmax = int64_t(1) << split_lg(d.D);
-        if (Bp <= Bsmax) {
-          nf += d.R;
-        } else {
-          nf += (int64_t)d.R * (Bp / Bsmax);
-          nd += (int64_t)d.R * ((Bp + kChunk - 1) / kChunk);
-        }
-        nch += 2 * (int64_t)d.multi_cap;
-      }
-      L.fft = nf > 0;
-      L.direct = nd > 0;
-      L.children = nch > 0;
-      L.jump = nj > 0;
-      L.col = ncol > 0;
-      // column pass: one resident work-group per CU (a multiple of 16, for the
-      // XCD pairing of its items)
-      L.grid_col = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)ncu & ~15, ((ncol + 15) / 16) * 16));
-      L.grid_col_resolve = (int)std::min<int64_t>(std::max<int64_t>((ncr + 64 / kColGroup - 1) / (64 / kColGroup), 1), 4096);
-      L.grid_fft = (int)std::min<int64_t>(std::max<int64_t>(nf, 1), 4096);
-      L.grid_direct = (int)std::min<int64_t>(std::max<int64_t>(nd, 1), 8192);
-      L.grid_children = (int)std::min<int64_t>(std::max<int64_t>((nch + kThreads - 1) / kThreads, 1), 2048);
-      L.grid_jump = (int)std::min<int64_t>(std::max<int64_t>(nj, 1), 8192);
-      L.grid_resolve = (int)std::min<int64_t>(std::max<int64_t>(nr, 1), 4096);
-      levels.push_back(L);
-    }
-    io_last.assign(ns, SigIO{});
+    bind_layout(lay, base, tw, lc);
+    io_last.assign((size_t)nsig, SigIO{});
     return SFFT_OK;
   }
-
   // The whole pipeline on stream s.  With `prof`, a timing event is recorded
   // after every launch and the kernel id of each interval is appended.
   struct Prof {
@@ -402,8 +475,8 @@ struct BatchCtx {
     if ((e = mark(-1)) != hipSuccess) return e;
     if ((e = launch_reset(c, s)) != hipSuccess || (e = mark(SFFT_KERNEL_RESET)) != hipSuccess) return e;
     if ((e = launch_level0(c, s)) != hipSuccess || (e = mark(SFFT_KERNEL_LEVEL0)) != hipSuccess) return e;
-    for (size_t i = 0; i < levels.size(); i++) {
-      const LevelLaunch &L = levels[i];
+    for (size_t i = 0; i < lay.levels.size(); i++) {
+      const LevelLaunch &L = lay.levels[i];
       const int l = (int)i + 1;
       if ((e = launch_sched(c, l, s)) != hipSuccess || (e = mark(SFFT_KERNEL_SCHED)) != hipSuccess) return e;
       if (L.fft && ((e = launch_expand_fft(c, l, L.grid_fft, s)) != hipSuccess ||
@@ -639,8 +712,8 @@ int32_t run_single(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_
   c.io1.x = (const float2 *)x;
   c.io1.idx = out_idx;
   c.io1.val = (float2 *)out_val;
-  c.io1.count = d_count ? d_count : (int64_t *)b->b_out.p;
-  c.io1.status = d_status ? d_status : (int32_t *)((int64_t *)b->b_out.p + 2);
+  c.io1.count = d_count ? d_count : b->count_dev();
+  c.io1.status = d_status ? d_status : b->status_dev();
   if (b->launch_all(c, stream) != hipSuccess) return SFFT_EDEVICE;
   return SFFT_OK;
 }
@@ -883,7 +956,7 @@ int64_t sfft_exec(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_v
   rc = run_single(plan, x, out_idx, out_val, nullptr, nullptr, nullptr);
   if (rc != SFFT_OK) return fail(rc);
   int64_t cnt = 0;
-  if (hipMemcpy(&cnt, plan->single->b_out.p, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+  if (hipMemcpy(&cnt, plan->single->count_dev(), sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(SFFT_EDEVICE);
   return cnt;
 }
@@ -948,7 +1021,7 @@ int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs, int6
   if (memcmp(io.data(), b->io_last.data(), sizeof(SigIO) * (size_t)n) != 0) {
     if (b->io_pending && hipEventSynchronize(b->ev_io) != hipSuccess) return fail(SFFT_EDEVICE);
     memcpy(b->io_pinned, io.data(), sizeof(SigIO) * (size_t)n);
-    if (hipMemcpyAsync(b->b_io.p, b->io_pinned, sizeof(SigIO) * (size_t)n, hipMemcpyHostToDevice,
+    if (hipMemcpyAsync(b->io_dev(), b->io_pinned, sizeof(SigIO) * (size_t)n, hipMemcpyHostToDevice,
                        b->stream) != hipSuccess ||
         hipEventRecord(b->ev_io, b->stream) != hipSuccess)
       return fail(SFFT_EDEVICE);
@@ -956,7 +1029,7 @@ int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs, int6
     b->io_last = io;
   }
   LaunchCtx c = b->lc;
-  c.io = (const SigIO *)b->b_io.p;
+  c.io = b->io_dev();
   if (flags & kBatchPrepareOnly) {
     // nothing launched: the caller runs the pipeline on the batch's stream
   } else if (flags & SFFT_BATCH_NO_GRAPH) {
@@ -999,7 +1072,7 @@ int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
   std::vector<const sfft_plan_s *> key(plans, plans + n);
   BatchCtx *b = g_batches[key].get();
   LaunchCtx c = b->lc;
-  c.io = (const SigIO *)b->b_io.p;
+  c.io = b->io_dev();
   BatchCtx::Prof prof;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(SFFT_EDEVICE);
   const hipError_t le = b->launch_all(c, b->stream, &prof);
@@ -1033,8 +1106,8 @@ int32_t sfft_bucketize(sfft_plan_t plan, const void *x, void *out) {
   LaunchCtx c = b->lc;
   c.io = nullptr;
   c.io1.x = (const float2 *)x;
-  c.io1.count = (int64_t *)b->b_out.p;
-  c.io1.status = (int32_t *)((int64_t *)b->b_out.p + 2);
+  c.io1.count = b->count_dev();
+  c.io1.status = b->status_dev();
   if (launch_reset(c, nullptr) != hipSuccess || launch_level0(c, nullptr) != hipSuccess ||
       launch_export_level0(c, out, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
     return fail(SFFT_EDEVICE);
@@ -1069,8 +1142,8 @@ int64_t sfft_exec_host(sfft_plan_t plan, const void *x, int64_t *out_idx, void *
   c.io1.x = (const float2 *)h->img.p;
   c.io1.idx = (int64_t *)h->res.p;
   c.io1.val = (float2 *)((int64_t *)h->res.p + K);
-  c.io1.count = (int64_t *)b.b_out.p;
-  c.io1.status = (int32_t *)((int64_t *)b.b_out.p + 2);
+  c.io1.count = b.count_dev();
+  c.io1.status = b.status_dev();
   const hipStream_t s = h->stream;
   const float2 *xh = (const float2 *)x;
   int64_t moved = 0;
@@ -1088,9 +1161,9 @@ int64_t sfft_exec_host(sfft_plan_t plan, const void *x, int64_t *out_idx, void *
   };
   if ((rc = stage(0)) != SFFT_OK) return fail(rc);
   if (launch_reset(c, s) != hipSuccess || launch_level0(c, s) != hipSuccess) return fail(SFFT_EDEVICE);
-  for (size_t i = 0; i < b.levels.size(); i++) {
+  for (size_t i = 0; i < b.lay.levels.size(); i++) {
     const int l = (int)i + 1;
-    const LevelLaunch &L = b.levels[i];
+    const LevelLaunch &L = b.lay.levels[i];
     // the level's samples are fetched only if the scheduler opened it
     if (launch_sched(c, l, s) != hipSuccess ||
         hipMemcpyAsync(h->word, &c.st[0].level_mask, sizeof(uint64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -1111,11 +1184,11 @@ int64_t sfft_exec_host(sfft_plan_t plan, const void *x, int64_t *out_idx, void *
       hipMemcpyAsync(out_val, c.io1.val, sizeof(float2) * (size_t)K, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&cnt, c.io1.count, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(&status, c.io1.status, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(&st, b.b_st.p, sizeof(SigState), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(&st, b.st_dev(), sizeof(SigState), hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return fail(SFFT_EDEVICE);
   if (stats) {
-    fill_stats(st, b.desc[0], cnt, status, stats);
+    fill_stats(st, b.lay.desc[0], cnt, status, stats);
     stats->h2d_bytes = moved;
   }
   return cnt;
@@ -1128,11 +1201,11 @@ int32_t sfft_exec_stats(sfft_plan_t plan, sfft_stats_t *out) {
   int64_t cnt = 0;
   int32_t status = 0;
   if (hipDeviceSynchronize() != hipSuccess ||
-      hipMemcpy(&st, b->b_st.p, sizeof(SigState), hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(&cnt, b->b_out.p, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(&status, (int64_t *)b->b_out.p + 2, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
+      hipMemcpy(&st, b->st_dev(), sizeof(SigState), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&cnt, b->count_dev(), sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&status, b->status_dev(), sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(SFFT_EDEVICE);
-  fill_stats(st, b->desc[0], cnt, status, out);
+  fill_stats(st, b->lay.desc[0], cnt, status, out);
   return SFFT_OK;
 }
 
@@ -1148,11 +1221,51 @@ int32_t sfft_batch_stats(const sfft_plan_t *plans, int32_t n, int32_t i, sfft_st
   int32_t status = 0;
   const SigIO &io = b->io_last[i];
   if (hipStreamSynchronize(b->stream) != hipSuccess ||
-      hipMemcpy(&st, (SigState *)b->b_st.p + i, sizeof(SigState), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(&st, b->st_dev() + i, sizeof(SigState), hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(&cnt, io.count, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
       hipMemcpy(&status, io.status, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess)
     return fail(SFFT_EDEVICE);
-  fill_stats(st, b->desc[i], cnt, status, out);
+  fill_stats(st, b->lay.desc[i], cnt, status, out);
+  return SFFT_OK;
+}
+
+int32_t sfft_workspace(const sfft_plan_t *plans, int32_t n, sfft_workspace_t *out,
+                       sfft_workspace_signal_t *sig) {
+  if (!plans || n < 1 || !out) return fail(SFFT_EINVAL);
+  std::vector<const sfft_plan_s *> key(plans, plans + n);
+  for (int i = 0; i < n; i++)
+    if (!plans[i]) return fail(SFFT_EINVAL);
+  Layout Y;
+  const int32_t rc = make_layout(key, false, 256, Y);
+  if (rc != SFFT_OK) return fail(rc);
+  out->bytes = (int64_t)Y.bytes;
+  out->y0 = Y.n_y0;
+  out->fst = Y.n_fst;
+  out->found = Y.n_found;
+  out->multi = Y.n_multi;
+  out->multi_vec = Y.n_mvec;
+  out->jacc = Y.n_jacc;
+  out->jcol = Y.n_jcol;
+  out->nmax = Y.nmax;
+  out->jstride = kJumpMax;
+  out->levels = (int32_t)Y.levels.size();
+  out->nsig = n;
+  if (sig)
+    for (int i = 0; i < n; i++) {
+      const SigDesc &d = Y.desc[i];
+      sfft_workspace_signal_t &w = sig[i];
+      memset(&w, 0, sizeof(w));
+      w.y0_off = d.y0_off;
+      w.fst_off = d.fst_off;
+      w.found_off = d.found_off;
+      w.multi_off = d.multi_off;
+      w.jcol_off = d.jc_off;
+      w.found_cap = d.found_cap;
+      w.multi_cap = d.multi_cap;
+      w.n = d.n;
+      w.l1 = d.l1;
+      w.jump_L = d.jump_L;
+    }
   return SFFT_OK;
 }
 

@@ -39,7 +39,8 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts_match_binding(tmp_path):
     prog = tmp_path / "layout.c"
     fields = {
-        "sfft_params_t": sfft.Params, "sfft_plan_info_t": sfft.PlanInfo, "sfft_stats_t": sfft.Stats}
+        "sfft_params_t": sfft.Params, "sfft_plan_info_t": sfft.PlanInfo, "sfft_stats_t": sfft.Stats,
+        "sfft_workspace_t": sfft.Workspace, "sfft_workspace_signal_t": sfft.WorkspaceSignal}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', "int main(void){"]
     for cname, py in fields.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -169,3 +170,16 @@ def test_column_pass_shapes():
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, l1_resolve=0).info.l1_resolve == 0
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, max_levels=0).info.l1_resolve == 0
     assert sfft.Plan(10800, 10, 3, 2).info.l1_resolve == 0
+
+
+def test_one_hip_runtime_per_process():
+    """Importing the binding maps exactly one HIP and one HSA runtime: the
+    library's runtime dependency binds to the copy torch already loaded (two
+    runtimes on one device would not see each other's allocations)."""
+    prog = ("import paper_2011_05749_amd\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "for lib in ('libamdhip64', 'libhsa-runtime64'):\n"
+            "    print(lib, len(set(l.split()[-1] for l in maps if lib in l)))\n")
+    out = subprocess.run(["python", "-c", prog], capture_output=True, text=True, check=True,
+                         cwd=ROOT).stdout.split()
+    assert out == ["libamdhip64", "1", "libhsa-runtime64", "1"], out

@@ -1,0 +1,153 @@
+"""Host-only audit of the batch workspace: for the plan lists the benchmark
+and the configuration tests run, the largest index every kernel can use in
+each arena (from the kernels' index expressions, restated here) lies inside
+what the layout allocates, and no two signals' ranges overlap.  No GPU: the
+layout is computed by sfft_workspace from the plans alone.
+
+Index expressions audited (element indices):
+  y0      k_level0_fft / k_level0_classify: y0_off + (r D + d) B0 + c, c < B0;
+          k_ffast: y0_off + i, i < D sum B_j
+  fst     k_ffast: fst_off + (state D sum B_j, values sum B_j, positions sum B_j / 2)
+  found   push_found / k_ffast: found_off + slot, slot < found_cap
+  multi   level-0 classify, k_children: multi_off + j, j < multi_cap (per parity)
+  mvec    (multi_off + j) nmax + i, i < n <= nmax
+  jacc    level-0 classify, k_children, k_jump_pass, k_jump_resolve:
+          (multi_off + j) jstride + t, t < L' <= jump_L <= jstride
+  jcol    k_col_pass / k_col_resolve: jcol_off + j L + t, j < multi_cap, t < L = N/B0
+  pre     k_sched: 7 (nsig + 1) int32
+"""
+import numpy as np
+import pytest
+
+import paper_2011_05749_amd as sfft
+
+KJUMPMAX = 128
+
+
+def _log2(v):
+    return int(v).bit_length() - 1
+
+
+def audit(plans):
+    ws, sig = sfft.workspace(plans)
+    assert ws["jstride"] == KJUMPMAX and ws["nsig"] == len(plans)
+    nmax = ws["nmax"]
+    spans = {k: [] for k in ("y0", "fst", "found", "multi", "jcol")}
+    need_jacc = 0
+    for p, s in zip(plans, sig):
+        inf = p.info
+        N, B0, R, D = int(inf.N), int(inf.B0), int(inf.R), int(inf.D)
+        if inf.kind == sfft.KIND_TREE:
+            n = R * D
+            assert s["n"] == n <= nmax
+            y0_end = s["y0_off"] + n * B0
+            spans["y0"].append((s["y0_off"], y0_end))
+            spans["multi"].append((s["multi_off"], s["multi_off"] + s["multi_cap"]))
+            # class vectors: (multi_off + j) nmax + i, i < n
+            last = (s["multi_off"] + s["multi_cap"] - 1) * nmax + n - 1
+            assert last < ws["multi_vec"]
+            jl = s["jump_L"]
+            if jl > 0:
+                assert jl <= KJUMPMAX and jl & (jl - 1) == 0
+                lgb, ml = _log2(B0), int(inf.max_levels)
+                # strides of the classes whose coefficients are accumulated:
+                # level-0 classify writes when N/B0 <= jump_L (and level 1 exists);
+                # children of level l write when their stride <= jump_L, l + 1 <= max_levels
+                writes = (N >> lgb) <= jl and ml >= 1 and (N >> lgb) >= 2
+                for lvl in range(1, ml):
+                    Lc = N >> (lgb + lvl)
+                    writes |= Lc <= jl and Lc >= 2
+                if writes:
+                    need_jacc = max(need_jacc, (s["multi_off"] + s["multi_cap"]) * KJUMPMAX)
+            if s["l1"]:
+                L = N // B0
+                assert B0 in (1024, 2048, 4096) and L >= 32768 // B0
+                # column-pass items of 512 / P adjacent columns: an even count
+                tc = 512 // (B0 // 32)
+                assert L % tc == 0 and (L // tc) % 2 == 0
+                spans["jcol"].append((s["jcol_off"], s["jcol_off"] + s["multi_cap"] * L))
+                assert s["jump_L"] == 0
+        else:
+            nb = sum(int(inf.stage_B[j]) for j in range(R))
+            spans["y0"].append((s["y0_off"], s["y0_off"] + D * nb))
+            spans["fst"].append((s["fst_off"], s["fst_off"] + nb * D + nb + (nb + 1) // 2))
+            assert s["l1"] == 0 and s["jump_L"] == 0
+        spans["found"].append((s["found_off"], s["found_off"] + s["found_cap"]))
+        assert s["found_cap"] >= 2 * int(inf.K) or s["found_cap"] >= 64
+    for name, sp in spans.items():
+        size = ws[name]
+        for a, b in sp:
+            assert 0 <= a <= b <= size, (name, a, b, size)
+        sp = sorted(sp)
+        for (a0, b0), (a1, b1) in zip(sp, sp[1:]):
+            assert b0 <= a1, (name, "overlap", (a0, b0), (a1, b1))
+    assert ws["multi_vec"] == ws["multi"] * nmax
+    assert need_jacc <= ws["jacc"], (need_jacc, ws["jacc"])
+    # the slab holds every part (complex64 8 B, complex128 16 B, int64 8 B)
+    parts = (ws["y0"] * 8 + ws["fst"] * 16 + ws["found"] * 24 + ws["multi"] * 2 * 8 +
+             ws["multi_vec"] * 2 * (8 + 16) + ws["jacc"] * 16 + ws["jcol"] * 8)
+    assert ws["bytes"] >= parts
+    return ws, sig
+
+
+def headline(jump_L=None, l1=None, nsig=256):
+    kw = {}
+    if jump_L is not None:
+        kw["jump_L"] = jump_L
+    if l1 is not None:
+        kw["l1_resolve"] = l1
+    return [sfft.Plan(2 ** 22, 1024, 4, 2, seed=9000 + i, B0=2048, **kw) for i in range(nsig)]
+
+
+@pytest.mark.parametrize("jump_L", [64, 128, 0])
+@pytest.mark.parametrize("l1", [0, 1])
+def test_headline_batch_bounds(jump_L, l1):
+    ws, sig = audit(headline(jump_L, l1))
+    assert all(s["l1"] == l1 for s in sig)
+    if l1:
+        # 256 x 1024 rows of 2048 complex64: the 4 GiB of column-pass rows
+        assert ws["jcol"] == 256 * 1024 * 2048
+
+
+def test_two_ton_variant_bounds():
+    audit([sfft.Plan(2 ** 22, 1024, 2, 4, seed=9000 + i, B0=2048, mpp=2, jump_L=0, l1_resolve=0)
+           for i in range(64)])
+
+
+def test_config_batches_bounds():
+    # noisy N = 2^20, K = 256, B0 = 512, batch of 64
+    audit([sfft.Plan(2 ** 20, 256, 4, 2, seed=s, B0=512, mode="noisy") for s in range(1000, 1064)])
+    # 2048 uneven signals, one identity round
+    rng = np.random.default_rng(2000)
+    plans = []
+    for i in range(2048):
+        n = 2 ** int(rng.integers(14, 21))
+        k = int(round(np.exp(rng.uniform(np.log(4), np.log(512)))))
+        plans.append(sfft.Plan(n, k, 1, 2, seed=2000 + i, B0=1 << max(0, (k - 1).bit_length()),
+                               identity_round0=1))
+    audit(plans)
+    # precision study shape, both decision precisions in one list
+    audit([sfft.Plan(2 ** 24, 4096, 4, 2, seed=5000 + i, B0=8192, mode="noisy", precision=i % 2)
+           for i in range(8)])
+    # serving mix, with FFAST, R-FFAST and column-pass tree signals together
+    rng = np.random.default_rng(7000)
+    plans = []
+    for i in range(24):
+        N = 2 ** int(rng.choice([16, 18, 20, 22, 24]))
+        K = int(round(np.exp(rng.uniform(np.log(16), np.log(4096)))))
+        B0 = min(1 << max(0, (2 * K - 1).bit_length()), N)
+        plans.append(sfft.Plan(N, K, 4, 2, seed=7000 + i, B0=B0, mode="noisy"))
+    plans.append(sfft.Plan(10800, 10, 3, 2))
+    plans.append(sfft.Plan(10800, 10, 3, 2, mode="noisy", rf_iters=11, rf_m=4))
+    plans.append(sfft.Plan(2 ** 16, 600, 4, 2, seed=7, B0=1024))
+    ws, sig = audit(plans)
+    assert ws["nmax"] == 44
+
+
+@pytest.mark.parametrize("jump", [0, 8, 32, 64, 128])
+def test_tree_parity_shapes_bounds(jump):
+    shapes = [(2 ** 12, 8, 1, 8), (2 ** 14, 64, 2, 128), (2 ** 16, 300, 4, 512), (2 ** 10, 1, 1, 1),
+              (2 ** 13, 7, 3, 16), (2 ** 18, 200, 1, 256), (2 ** 20, 256, 4, 512), (2 ** 12, 2, 1, 1)]
+    audit([sfft.Plan(N, K, R, 2, seed=i, B0=B0, jump_L=jump) for i, (N, K, R, B0) in enumerate(shapes)])
+    for cap in (5, 8, 11):
+        audit([sfft.Plan(2 ** 12, 2, 1, 2, B0=1, identity_round0=1, max_levels=cap, jump_L=jump)])

@@ -58,6 +58,8 @@ extern "C" {
                                   a size beyond the kernels' limits */
 #define SFFT_ENOMEM (-3)       /* device allocation failed */
 #define SFFT_EDEVICE (-4)      /* HIP runtime or kernel launch error */
+#define SFFT_ETOOBIG (-5)      /* sfft_exec_noalloc: the plan's workspace exceeds
+                                  the static scratch (SFFT_NOALLOC_SCRATCH_MIB) */
 
 /* solve status (per signal) */
 #define SFFT_STATUS_OK 0
@@ -232,6 +234,30 @@ int64_t sfft_exec_host(sfft_plan_t plan, const void *x, int64_t *out_idx, void *
    d_count: device int64[1], d_status: device int32[1] receive the result. */
 int32_t sfft_exec_async(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val,
                         int64_t *d_count, int32_t *d_status, void *stream);
+
+/* Allocation-free form of sfft_exec_async, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc).  It runs the same kernels on the same arguments,
+   with the whole workspace -- the plan's descriptors, the level-0 buckets,
+   class lists and found lists -- placed in one static device array of
+   SFFT_NOALLOC_SCRATCH_MIB MiB that the library holds on every GPU it runs on
+   until the process ends (the twiddle table sits in its first 64 KiB).  No
+   hipMalloc, hipFree or other device allocation is made; the first call of a
+   plan on a device computes the plan's workspace layout on the host, and the
+   first call on a device writes the twiddle table (a synchronous copy).  Each
+   call copies the plan's descriptors into the scratch on `stream`.
+   x, out_idx, out_val, d_count, d_status: device pointers as for
+   sfft_exec_async (d_count and d_status are required here).  A plan whose
+   workspace (sfft_workspace: bytes) exceeds the scratch less 64 KiB is
+   rejected with SFFT_ETOOBIG before anything is launched.  Every call on one
+   GPU shares that GPU's scratch and leaves its contents behind (every value a
+   call reads is written by the same call first): calls that overlap on one
+   GPU -- on different streams or from different threads -- race and give
+   undefined results; calls on one stream are ordered.  Returns SFFT_OK or
+   SFFT_E*. */
+#define SFFT_NOALLOC_SCRATCH_MIB 64
+int32_t sfft_exec_noalloc(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val,
+                          int64_t *d_count, int32_t *d_status, void *stream);
 
 /* Batched solve of n independent signals (any mix of plans, N and K) in one
    fused pipeline: one persistent level-0 launch over all signals and one

@@ -36,7 +36,8 @@ EXACT, NOISY = 0, 1
 KIND_TREE, KIND_FFAST = 0, 1
 STATUS_OK, STATUS_PARTIAL = 0, 1
 BATCH_NO_GRAPH = 1
-ERRORS = {0: "ok", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM", -4: "EDEVICE"}
+ERRORS = {0: "ok", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM", -4: "EDEVICE", -5: "ETOOBIG"}
+NOALLOC_SCRATCH_MIB = 64
 
 
 class Params(ctypes.Structure):
@@ -139,6 +140,8 @@ _lib.sfft_exec_host.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(Stats)]
 _lib.sfft_exec_host.restype = ctypes.c_int64
 _lib.sfft_exec_async.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 _lib.sfft_exec_async.restype = ctypes.c_int32
+_lib.sfft_exec_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.sfft_exec_noalloc.restype = ctypes.c_int32
 _lib.sfft_exec_batch.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp]
 _lib.sfft_exec_batch.restype = ctypes.c_int32
 _lib.sfft_exec_batch_ex.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
@@ -166,7 +169,7 @@ EXPORTS = ["sfft_params_init", "sfft_plan", "sfft_plan_ex", "sfft_plan_info", "s
            "sfft_exec", "sfft_exec_host", "sfft_exec_async", "sfft_exec_batch", "sfft_exec_batch_ex",
            "sfft_exec_batch_profile",
            "sfft_bucketize", "sfft_exec_stats", "sfft_batch_stats", "sfft_release_batches",
-           "sfft_workspace",
+           "sfft_workspace", "sfft_exec_noalloc",
            "sfft_last_error", "sfft_strerror"]
 
 
@@ -295,6 +298,16 @@ class Plan:
             _dev_ptr(out_val, "complex64", self.K, "out_val"),
             _dev_ptr(d_count, "int64", 1, "d_count"), _dev_ptr(d_status, "int32", 1, "d_status"),
             _stream_handle(stream)), "sfft_exec_async")
+
+    def exec_noalloc(self, x, out_idx, out_val, d_count, d_status, stream=None):
+        """sfft_exec_noalloc: as exec_async, with the workspace in the library's
+        static device scratch (no device allocation)."""
+        _check(_lib.sfft_exec_noalloc(
+            self._h, _dev_ptr(x, "complex64", self.N, "x"),
+            _dev_ptr(out_idx, "int64", self.K, "out_idx"),
+            _dev_ptr(out_val, "complex64", self.K, "out_val"),
+            _dev_ptr(d_count, "int64", 1, "d_count"), _dev_ptr(d_status, "int32", 1, "d_status"),
+            _stream_handle(stream)), "sfft_exec_noalloc")
 
     def bucketize(self, x):
         """Level-0 class vectors (complex64): tree (B0, R*D); FFAST (sum B_j, D)."""

@@ -65,6 +65,7 @@ uint64_t gcd64(uint64_t a, uint64_t b) {
 
 struct BatchCtx;
 struct HostCtx;
+struct Layout;
 
 }  // namespace
 
@@ -76,6 +77,8 @@ struct sfft_plan_s {
   int64_t noise_at;
   std::unique_ptr<BatchCtx> single;
   std::unique_ptr<HostCtx> host;   // host-gather solves (sfft_exec_host)
+  std::unique_ptr<Layout> na_lay;  // sfft_exec_noalloc: layout of this plan alone
+  int na_dev = -1;
 };
 
 namespace {
@@ -96,6 +99,17 @@ struct DevBuf {
   }
 };
 
+}  // namespace
+
+void sfft::host_twiddles(float2 *out) {
+  for (int k = 0; k < kFftMax; k++) {
+    const double a = 2.0 * M_PI * (double)k / (double)kFftMax;
+    out[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
+  }
+}
+
+namespace {
+
 // per-device twiddle table e^{-2 pi i k / kFftMax}
 std::mutex g_tw_mu;
 std::map<int, float2 *> g_tw;
@@ -108,10 +122,7 @@ hipError_t device_twiddles(int dev, const float2 **out) {
     return hipSuccess;
   }
   std::vector<float2> h(kFftMax);
-  for (int k = 0; k < kFftMax; k++) {
-    const double a = 2.0 * M_PI * (double)k / (double)kFftMax;
-    h[k] = make_float2((float)std::cos(a), (float)-std::sin(a));
-  }
+  host_twiddles(h.data());
   float2 *d = nullptr;
   hipError_t e = hipMalloc(&d, sizeof(float2) * kFftMax);
   if (e != hipSuccess) return e;
@@ -408,6 +419,57 @@ int device_cus(int device) {
   return ncu;
 }
 
+// Timing events of a profiled pipeline run: one after every launch, with the
+// kernel id of each interval.
+struct Prof {
+  std::vector<hipEvent_t> ev;
+  std::vector<int32_t> id;
+};
+
+// The whole pipeline of a layout bound in c, on stream s.  With `prof`, a
+// timing event is recorded after every launch.
+hipError_t launch_pipeline(const Layout &lay, const LaunchCtx &c, hipStream_t s, Prof *prof) {
+  hipError_t e;
+  auto mark = [&](int id) -> hipError_t {
+    if (!prof) return hipSuccess;
+    hipEvent_t ev;
+    hipError_t r = hipEventCreate(&ev);
+    if (r != hipSuccess) return r;
+    prof->ev.push_back(ev);
+    prof->id.push_back(id);
+    return hipEventRecord(ev, s);
+  };
+  if ((e = mark(-1)) != hipSuccess) return e;
+  if ((e = launch_reset(c, s)) != hipSuccess || (e = mark(SFFT_KERNEL_RESET)) != hipSuccess) return e;
+  if ((e = launch_level0(c, s)) != hipSuccess || (e = mark(SFFT_KERNEL_LEVEL0)) != hipSuccess) return e;
+  for (size_t i = 0; i < lay.levels.size(); i++) {
+    const LevelLaunch &L = lay.levels[i];
+    const int l = (int)i + 1;
+    if ((e = launch_sched(c, l, s)) != hipSuccess || (e = mark(SFFT_KERNEL_SCHED)) != hipSuccess) return e;
+    if (L.fft && ((e = launch_expand_fft(c, l, L.grid_fft, s)) != hipSuccess ||
+                  (e = mark(SFFT_KERNEL_EXPAND_FFT | (l << 8))) != hipSuccess))
+      return e;
+    if (L.direct && ((e = launch_expand_direct(c, l, L.grid_direct, s)) != hipSuccess ||
+                     (e = mark(SFFT_KERNEL_EXPAND_DIRECT | (l << 8))) != hipSuccess))
+      return e;
+    if (L.children && ((e = launch_children(c, l, L.grid_children, s)) != hipSuccess ||
+                       (e = mark(SFFT_KERNEL_CHILDREN | (l << 8))) != hipSuccess))
+      return e;
+    if (L.jump && ((e = launch_jump_pass(c, l, L.grid_jump, s)) != hipSuccess ||
+                   (e = mark(SFFT_KERNEL_JUMP_PASS | (l << 8))) != hipSuccess ||
+                   (e = launch_jump_resolve(c, l, L.grid_resolve, s)) != hipSuccess ||
+                   (e = mark(SFFT_KERNEL_JUMP_RESOLVE | (l << 8))) != hipSuccess))
+      return e;
+    if (L.col && ((e = launch_col_pass(c, L.grid_col, s)) != hipSuccess ||
+                  (e = mark(SFFT_KERNEL_COL_PASS | (l << 8))) != hipSuccess ||
+                  (e = launch_col_resolve(c, L.grid_col_resolve, s)) != hipSuccess ||
+                  (e = mark(SFFT_KERNEL_COL_RESOLVE | (l << 8))) != hipSuccess))
+      return e;
+  }
+  if ((e = launch_finalize(c, s)) != hipSuccess) return e;
+  return mark(SFFT_KERNEL_FINALIZE);
+}
+
 struct BatchCtx {
   int device = -1;
   std::vector<const sfft_plan_s *> plans;
@@ -455,52 +517,8 @@ struct BatchCtx {
     io_last.assign((size_t)nsig, SigIO{});
     return SFFT_OK;
   }
-  // The whole pipeline on stream s.  With `prof`, a timing event is recorded
-  // after every launch and the kernel id of each interval is appended.
-  struct Prof {
-    std::vector<hipEvent_t> ev;
-    std::vector<int32_t> id;
-  };
   hipError_t launch_all(const LaunchCtx &c, hipStream_t s, Prof *prof = nullptr) {
-    hipError_t e;
-    auto mark = [&](int id) -> hipError_t {
-      if (!prof) return hipSuccess;
-      hipEvent_t ev;
-      hipError_t r = hipEventCreate(&ev);
-      if (r != hipSuccess) return r;
-      prof->ev.push_back(ev);
-      prof->id.push_back(id);
-      return hipEventRecord(ev, s);
-    };
-    if ((e = mark(-1)) != hipSuccess) return e;
-    if ((e = launch_reset(c, s)) != hipSuccess || (e = mark(SFFT_KERNEL_RESET)) != hipSuccess) return e;
-    if ((e = launch_level0(c, s)) != hipSuccess || (e = mark(SFFT_KERNEL_LEVEL0)) != hipSuccess) return e;
-    for (size_t i = 0; i < lay.levels.size(); i++) {
-      const LevelLaunch &L = lay.levels[i];
-      const int l = (int)i + 1;
-      if ((e = launch_sched(c, l, s)) != hipSuccess || (e = mark(SFFT_KERNEL_SCHED)) != hipSuccess) return e;
-      if (L.fft && ((e = launch_expand_fft(c, l, L.grid_fft, s)) != hipSuccess ||
-                    (e = mark(SFFT_KERNEL_EXPAND_FFT | (l << 8))) != hipSuccess))
-        return e;
-      if (L.direct && ((e = launch_expand_direct(c, l, L.grid_direct, s)) != hipSuccess ||
-                       (e = mark(SFFT_KERNEL_EXPAND_DIRECT | (l << 8))) != hipSuccess))
-        return e;
-      if (L.children && ((e = launch_children(c, l, L.grid_children, s)) != hipSuccess ||
-                         (e = mark(SFFT_KERNEL_CHILDREN | (l << 8))) != hipSuccess))
-        return e;
-      if (L.jump && ((e = launch_jump_pass(c, l, L.grid_jump, s)) != hipSuccess ||
-                     (e = mark(SFFT_KERNEL_JUMP_PASS | (l << 8))) != hipSuccess ||
-                     (e = launch_jump_resolve(c, l, L.grid_resolve, s)) != hipSuccess ||
-                     (e = mark(SFFT_KERNEL_JUMP_RESOLVE | (l << 8))) != hipSuccess))
-        return e;
-      if (L.col && ((e = launch_col_pass(c, L.grid_col, s)) != hipSuccess ||
-                    (e = mark(SFFT_KERNEL_COL_PASS | (l << 8))) != hipSuccess ||
-                    (e = launch_col_resolve(c, L.grid_col_resolve, s)) != hipSuccess ||
-                    (e = mark(SFFT_KERNEL_COL_RESOLVE | (l << 8))) != hipSuccess))
-        return e;
-    }
-    if ((e = launch_finalize(c, s)) != hipSuccess) return e;
-    return mark(SFFT_KERNEL_FINALIZE);
+    return launch_pipeline(lay, c, s, prof);
   }
 };
 
@@ -972,6 +990,43 @@ int32_t sfft_exec_async(sfft_plan_t plan, const void *x, int64_t *out_idx, void 
   return rc == SFFT_OK ? SFFT_OK : fail(rc);
 }
 
+int32_t sfft_exec_noalloc(sfft_plan_t plan, const void *x, int64_t *out_idx, void *out_val,
+                          int64_t *d_count, int32_t *d_status, void *stream) {
+  if (!plan) return fail(SFFT_EINVAL);
+  int32_t rc = check_io(x, out_idx, out_val);
+  if (rc != SFFT_OK) return fail(rc);
+  if (!is_device_ptr(d_count) || !is_device_ptr(d_status)) return fail(SFFT_EINVAL);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(SFFT_EDEVICE);
+  char *base = nullptr;
+  if (noalloc_scratch(dev, &base) != hipSuccess) return fail(SFFT_EDEVICE);
+  if (!plan->na_lay || plan->na_dev != dev) {
+    std::unique_ptr<Layout> Y(new Layout());
+    rc = make_layout({plan}, false, device_cus(dev), *Y);
+    if (rc != SFFT_OK) return fail(rc);
+    plan->na_lay = std::move(Y);
+    plan->na_dev = dev;
+  }
+  const Layout &Y = *plan->na_lay;
+  if (kNoAllocTwBytes + Y.bytes > kNoAllocScratchBytes) return fail(SFFT_ETOOBIG);
+  char *slab = base + kNoAllocTwBytes;
+  const hipStream_t s = as_stream(stream);
+  if (hipMemcpyAsync(slab + Y.o_desc, Y.desc.data(), sizeof(SigDesc) * Y.desc.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(slab + Y.o_lists, Y.lists.data(), sizeof(int32_t) * Y.lists.size(),
+                     hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(SFFT_EDEVICE);
+  LaunchCtx c;
+  bind_layout(Y, slab, (const float2 *)base, c);
+  c.io1.x = (const float2 *)x;
+  c.io1.idx = out_idx;
+  c.io1.val = (float2 *)out_val;
+  c.io1.count = d_count;
+  c.io1.status = d_status;
+  if (launch_pipeline(Y, c, s, nullptr) != hipSuccess) return fail(SFFT_EDEVICE);
+  return SFFT_OK;
+}
+
 int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs, int64_t *const *idx,
                            void *const *vals, int64_t *d_counts, int32_t *d_status, int32_t n,
                            void *stream, int32_t flags) {
@@ -1073,7 +1128,7 @@ int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
   BatchCtx *b = g_batches[key].get();
   LaunchCtx c = b->lc;
   c.io = b->io_dev();
-  BatchCtx::Prof prof;
+  Prof prof;
   if (hipStreamSynchronize(b->stream) != hipSuccess) return fail(SFFT_EDEVICE);
   const hipError_t le = b->launch_all(c, b->stream, &prof);
   const hipError_t se = hipStreamSynchronize(b->stream);
@@ -1283,6 +1338,7 @@ const char *sfft_strerror(int32_t code) {
     case SFFT_EUNSUPPORTED: return "unsupported size or factorisation";
     case SFFT_ENOMEM: return "device allocation failed";
     case SFFT_EDEVICE: return "HIP runtime or kernel launch error";
+    case SFFT_ETOOBIG: return "workspace larger than the static scratch of sfft_exec_noalloc";
     default: return "unknown error";
   }
 }

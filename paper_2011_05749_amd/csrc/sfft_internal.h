@@ -32,6 +32,8 @@ constexpr int kColResolveCap = 128;  // open subclasses per depth of one class
 constexpr int kColGroupLg = 3;      // column resolve: 2^3 lanes per class
 constexpr int kColGroup = 1 << kColGroupLg;
 constexpr int kColLaneDepth = 5;    // ... one lane per class-vector sum down to this depth
+constexpr size_t kNoAllocScratchBytes = (size_t)SFFT_NOALLOC_SCRATCH_MIB << 20;
+constexpr size_t kNoAllocTwBytes = 64 * 1024;  // twiddle table at the scratch's start
 
 // log2 of the sub-FFT size used when the D delays of a sample are held in
 // LDS together (D planes of complex64 within 64 KiB)
@@ -107,6 +109,12 @@ struct Arena {
   float2 *jcol;           // per level-0 multi-ton slot: M_c(t), t < N/B0
   const float2 *tw;       // e^{-2 pi i k / kFftMax}, k < kFftMax
 };
+
+// e^{-2 pi i k / kFftMax}, k < kFftMax, rounded to FP32 (host computation)
+void host_twiddles(float2 *out);
+// device address of the current device's static scratch of sfft_exec_noalloc
+// (kNoAllocScratchBytes; its first kNoAllocTwBytes hold the twiddle table)
+hipError_t noalloc_scratch(int device, char **base);
 
 // host-side kernel launchers (sfft_level0.hip, sfft_ffast.hip, sfft_tree.hip,
 // sfft_jump.hip, sfft_col.hip, sfft_finalize.hip)

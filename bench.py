@@ -45,6 +45,216 @@ def pct(v, q):
     return v[f] + (v[c] - v[f]) * (k - f)
 
 
+# translation unit of each kernel the roofline may name (with the shared headers)
+KERNEL_SOURCES = {"k_col_pass": "sfft_col.hip", "k_col_resolve": "sfft_colres.hip",
+                  "k_level0": "sfft_level0.hip", "k_jump_pass": "sfft_jump.hip",
+                  "k_expand_fft": "sfft_tree.hip", "k_expand_direct": "sfft_tree.hip"}
+
+
+def kernel_source_sha(kernel):
+    """sha256 over the kernel's translation unit and the headers it includes:
+    recorded beside counter-derived traffic, which is reported only while the
+    kernel's source is unchanged."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2011_05749_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCES.get(kernel, ""), "sfft_device.h", "sfft_internal.h"):
+        path = os.path.join(csrc, f)
+        if f and os.path.exists(path):
+            h.update(open(path, "rb").read())
+    return h.hexdigest()
+
+
+def host_cpu():
+    """(threads this process may use, CPU model name)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, model
+
+
+def cpu_oracle_baseline(xs, seeds, N, K, R, D, B0, seconds):
+    """The FP64 C oracle on a bounded sample of the benchmark signals, one
+    solve per host thread at a time (ctypes releases the GIL), until about
+    `seconds` of wall time: completed solves per second over all threads."""
+    import threading
+
+    import oracle
+    threads, model = host_cpu()
+    host = [None] * len(xs)
+    lock = threading.Lock()
+    nxt = [0]
+    done = [0]
+    t_end = [None]
+
+    def worker():
+        while True:
+            with lock:
+                i = nxt[0] % len(xs)
+                if time.perf_counter() >= t_end[0]:
+                    return
+                nxt[0] += 1
+            oracle.solve(oracle.config(N, K, R, D, seed=seeds[i], B0=B0), host[i])
+            with lock:
+                done[0] += 1
+
+    for i in range(len(xs)):
+        host[i] = xs[i].cpu().numpy()
+    oracle.lib()  # built before the clock starts
+    t0 = time.perf_counter()
+    t_end[0] = t0 + seconds
+    pool = [threading.Thread(target=worker) for _ in range(threads)]
+    for th in pool:
+        th.start()
+    for th in pool:
+        th.join()
+    wall = time.perf_counter() - t0
+    return {"value": round(done[0] / wall, 4), "unit": "spectra/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done[0]} solves of the first {len(xs)} benchmark signals (taken in turn; "
+                      f"solves started within {seconds:g} s, all finished), FP64 C oracle, one solve "
+                      f"per thread on {threads} host threads",
+            "host_cpu": model, "wall_s": round(wall, 2)}
+
+
+def run_noisy_headline(sfft, torch, np, nb, steps, warmup, dev):
+    """Secondary headline: the metric's shape at SNR 20 dB (N = 2^22, K = 1024,
+    unit tones, complex AWGN), noisy mode (noise-scaled thresholds, enumeration
+    locator), B0 = 2048, 4 rounds x 2 delays, one captured batch of nb; errors
+    against the planted spectrum (L0 = misses + false alarms, L2 relative)."""
+    import siggen
+    N, K = 2 ** 22, 1024
+    seeds = [9300 + i for i in range(nb)]
+    specs = [siggen.make_spec(N, K, s, snr_db=20.0) for s in seeds]
+    xs = [siggen.synth_torch(sp, dev) for sp in specs]
+    plans = [sfft.Plan(N, K, 4, 2, seed=s, B0=2048, mode="noisy") for s in seeds]
+    b = sfft.Batch(plans, xs)
+    for _ in range(warmup):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    l0s, l2s, exact = [], [], 0
+    for i, sp in enumerate(specs):
+        idx = b.idxs[i].cpu().numpy()
+        val = b.vals[i].cpu().numpy().astype(np.complex128)
+        sup, vals = siggen.truth(sp)
+        got = dict(zip(idx[idx >= 0].tolist(), val[idx >= 0].tolist()))
+        want = dict(zip(sup.tolist(), vals.tolist()))
+        keys = set(got) | set(want)
+        l0s.append(len(set(got) ^ set(want)))
+        d = np.array([got.get(k, 0) - want.get(k, 0) for k in keys])
+        l2s.append(float(np.linalg.norm(d) / np.linalg.norm(vals)))
+        exact += int(np.array_equal(idx, sup))
+    out = {"value": round(nb / dt, 1), "unit": "spectra/s", "ms_per_batch": round(dt * 1e3, 4),
+           "workload": "N=2^22, K=1024 unit tones at SNR 20 dB; noisy mode, B0=2048, 4 rounds x 2 "
+                       f"delays, batch of {nb} per graph",
+           "L0_mean": float(np.mean(l0s)), "L2_mean": float(np.mean(l2s)),
+           "exact_support": f"{exact}/{nb}"}
+    del b, xs
+    sfft.release_batches()
+    return out
+
+
+def run_serving(sfft, torch, np, dev, n_req=3000, per_n=16, seed=7000):
+    """Serving workload: a device pool of per_n signals for each N in {2^16,
+    2^18, 2^20, 2^22, 2^24} (K log-uniform on [16, 4096], SNR uniform on
+    [10, 40] dB, plans made once: B0 = next pow2 >= 2K, 4 rounds x 2 delays,
+    noisy mode); n_req requests each draw N uniformly, then a pool signal.
+    Capacity: all requests released at once.  Then Poisson arrivals at 0.25,
+    0.5, 0.8 and 0.95 of that capacity: spectra/s and p50/p99 of release ->
+    result.  Plain: the same requests one sfft_exec_async after another."""
+    import siggen
+    rng = np.random.default_rng(seed)
+    Ns = [2 ** 16, 2 ** 18, 2 ** 20, 2 ** 22, 2 ** 24]
+    pool = []
+    for N in Ns:
+        for j in range(per_n):
+            K = int(round(np.exp(rng.uniform(np.log(16), np.log(4096)))))
+            snr = float(rng.uniform(10, 40))
+            sd = seed + 100 * len(pool)
+            sp = siggen.make_spec(N, K, sd, snr_db=snr)
+            B0 = min(1 << max(0, (2 * K - 1).bit_length()), N)
+            pool.append((sfft.Plan(N, K, 4, 2, seed=sd, B0=B0, mode="noisy"), siggen.synth_torch(sp, dev)))
+    pick = rng.integers(0, len(Ns), n_req) * per_n + rng.integers(0, per_n, n_req)
+    plans = [pool[j][0] for j in pick]
+    xs = [pool[j][1] for j in pick]
+    Ks = np.array([p.K for p in plans])
+    offs = np.concatenate([[0], np.cumsum(Ks)])
+    arena_i = torch.empty(int(offs[-1]), dtype=torch.int64, device=dev)
+    arena_v = torch.empty(int(offs[-1]), dtype=torch.complex64, device=dev)
+    idxs = [arena_i[offs[r]:offs[r + 1]] for r in range(n_req)]
+    vals = [arena_v[offs[r]:offs[r + 1]] for r in range(n_req)]
+    counts = torch.zeros(n_req, dtype=torch.int64, device=dev)
+    status = torch.zeros(n_req, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    out = {"workload": f"{n_req} requests per point from a device pool of {per_n} signals per N, "
+                       "N uniform on {2^16..2^24}, K log-uniform 16..4096, SNR U[10,40] dB, noisy "
+                       "mode, B0 = next pow2 >= 2K, 4 rounds x 2 delays",
+           "lanes": 2, "hbm_bytes": 16 << 30}
+    srv = sfft.Server(hbm_bytes=16 << 30, lanes=2, max_batch=256)
+    # warm-up (workspace layouts of every plan, code paths)
+    srv.submit(plans[:64], xs[:64], idxs[:64], vals[:64], counts, status)
+    srv.drain()
+
+    def point(rel):
+        first = srv.submit(plans, xs, idxs, vals, counts, status, release_ns=rel)
+        srv.drain()
+        rq = srv.requests(first, n_req)
+        assert np.all(rq["status"] == 1)
+        lat = (rq["done_ns"] - rq["release_ns"]) / 1e6
+        span = (rq["done_ns"].max() - rq["release_ns"].min()) / 1e9
+        return {"value": round(n_req / span, 1), "unit": "spectra/s",
+                "p50_ms": round(float(np.percentile(lat, 50)), 4),
+                "p99_ms": round(float(np.percentile(lat, 99)), 4),
+                "mean_batch": round(float(np.mean(rq["batch"])), 2)}
+
+    now = srv.clock_ns() + 1_000_000
+    cap = point(np.full(n_req, now, dtype=np.int64))
+    out["capacity"] = cap
+    out["load"] = {}
+    for f in (0.25, 0.5, 0.8, 0.95):
+        rate = f * cap["value"]
+        t0 = srv.clock_ns() + 2_000_000
+        rel = (t0 + np.cumsum(rng.exponential(1e9 / rate, n_req))).astype(np.int64)
+        r = point(rel)
+        r["offered_per_s"] = round(rate, 1)
+        out["load"][str(f)] = r
+    srv.close()
+    # plain: one solve after another on the current stream
+    dc = torch.zeros(1, dtype=torch.int64, device=dev)
+    dst = torch.zeros(1, dtype=torch.int32, device=dev)
+    for r in range(16):
+        plans[r].exec_async(xs[r], idxs[r], vals[r], dc, dst)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_req)]
+    t0 = time.perf_counter()
+    for r in range(n_req):
+        ev[r][0].record()
+        plans[r].exec_async(xs[r], idxs[r], vals[r], dc, dst)
+        ev[r][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = [a.elapsed_time(b) for a, b in ev]
+    out["plain"] = {"value": round(n_req / wall, 1), "unit": "spectra/s",
+                    "p50_ms": round(pct(lat, 0.5), 4), "p99_ms": round(pct(lat, 0.99), 4)}
+    out["served_over_plain"] = round(cap["value"] / out["plain"]["value"], 3)
+    del pool, plans, xs
+    sfft.release_batches()
+    return out
+
+
 def ilog2(v):
     return int(v).bit_length() - 1
 
@@ -324,7 +534,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--plain", type=int, default=256, help="signals in the plain pass")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serving-requests", type=int, default=3000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jump-L", type=int, default=None,
                     help="override the plans' subtree-resolution stride (0 = level by level)")
@@ -425,10 +636,7 @@ def main():
     if os.path.exists(tfile):
         try:
             t = json.load(open(tfile))
-            src = os.path.join(ROOT, "paper_2011_05749_amd", "csrc", "sfft_kernels.hip")
-            import hashlib
-            h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-            if t.get("kernel") == dom and t.get("source_sha256") == h:
+            if t.get("kernel") == dom and t.get("source_sha256") == kernel_source_sha(dom):
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
@@ -461,24 +669,22 @@ def main():
         variants.update(run_configs(sfft, torch, np, args.steps, args.warmup, dev))
         variants["precision_n2p24_k4096_30db_batch8"] = run_precision_study(sfft, torch, np, args.steps,
                                                                             args.warmup, dev)
+        print("bench: serving loop", file=sys.stderr, flush=True)
+        variants["serving"] = run_serving(sfft, torch, np, dev, n_req=args.serving_requests)
+
+    # ------------------------------------------- secondary headline: SNR 20 dB
+    secondary = None
+    if not args.no_variants:
+        print("bench: noisy headline (SNR 20 dB)", file=sys.stderr, flush=True)
+        secondary = {"snr20db": run_noisy_headline(sfft, torch, np, nb, args.steps, args.warmup, dev)}
 
     # ------------------------------------------------------------ CPU oracle
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
         print("bench: cpu oracle baseline", file=sys.stderr, flush=True)
-        done, t_cpu = 0, 0.0
-        for i in range(nb):
-            x = xs[i].cpu().numpy()
-            cfg = oracle.config(N, K, R, D, seed=seeds[i], B0=B0)
-            t0 = time.perf_counter()
-            oracle.solve(cfg, x)
-            t_cpu += time.perf_counter() - t0
-            done += 1
-            if t_cpu >= args.cpu_seconds:
-                break
-        cpu = {"value": round(done / t_cpu, 4), "unit": "spectra/s", "cores": 1, "kind": "oracle",
-               "sample": f"{done} of the {nb} benchmark signals, FP64 C oracle, one thread"}
+        nthreads, _ = host_cpu()
+        sample = min(nb, max(2 * nthreads, 8))
+        cpu = cpu_oracle_baseline(xs[:sample], seeds[:sample], N, K, R, D, B0, args.cpu_seconds)
 
     out = {
         "metric": "sparse spectra/sec at N=2^22,K=1024 batched vs plain; p50/p99 solve latency",
@@ -511,6 +717,7 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
+        "secondary": secondary,
         "variants": variants,
     }
     print(json.dumps(out), flush=True)

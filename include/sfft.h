@@ -149,7 +149,7 @@ typedef struct {
                               every class's L coefficients M_c(t) (the class's bucket
                               measured with shift t, times B0), and each class vector
                               of any later level (Sect. 3.3) is a sum of 2^d of them,
-                              d levels below; taken when B0 is 1024, 2048 or 4096 and
+                              d levels below; taken when B0 is 1024, 2048, 4096 or 8192 and
                               L >= 32768 / B0, in place of jump_L and the level-by-level
                               gathers.  0 = off; other values: SFFT_EINVAL */
 } sfft_params_t;
@@ -339,6 +339,68 @@ typedef struct {
 
 int32_t sfft_workspace(const sfft_plan_t *plans, int32_t n, sfft_workspace_t *out,
                        sfft_workspace_signal_t *sig);
+
+/* ------------------------------------------------------------ serving loop
+   Continuous batching of independent solves, each the problem of Sect. 2.1,
+   on the current device.  A request names a plan (created once by the caller
+   and reused: plans stay resident), device pointers to its signal and outputs
+   (as for sfft_exec_async) and a release time.  A scheduler thread forms a
+   batch whenever one of `lanes` lanes is free and released requests wait:
+   it takes them in release order while their workspaces (sfft_workspace,
+   computed on the host from the plans) fit the lane's share of `hbm_bytes`
+   of device memory -- admission by HBM footprint -- and launches the batched
+   pipeline of sfft_exec_batch on the lane's own stream.  Lanes run at the
+   same time, so requests that arrive while batches are on the device are
+   admitted into the next free lane and their work overlaps with the batches
+   in flight.  Each request's result equals that of sfft_exec on the same
+   plan and signal.  The server owns its lanes' streams, slabs and pinned
+   staging buffers (allocated at creation) and two threads per lane plus one;
+   the caller owns plans and buffers, which must stay valid until the request
+   is done.  Requests are numbered from 0 in submission order (tickets). */
+typedef struct sfft_server_s *sfft_server_t;
+
+typedef struct {
+  int64_t hbm_bytes;   /* device memory for batch workspaces, split evenly over the
+                          lanes (default 8 GiB; at least 1 MiB per lane) */
+  int32_t lanes;       /* batches in flight at once, one stream each (1..8, default 2) */
+  int32_t max_batch;   /* requests per batch (1..65536, default 256) */
+} sfft_server_params_t;
+
+/* Times (sfft_server_clock_ns) and outcome of one request. */
+typedef struct {
+  int64_t release_ns;  /* when the request became eligible for a batch */
+  int64_t launch_ns;   /* when its batch was launched (0 before) */
+  int64_t done_ns;     /* when its batch's completion was observed (0 before) */
+  int32_t batch;       /* requests in its batch */
+  int32_t lane;
+  int32_t status;      /* 0 waiting or running, 1 done, < 0 the SFFT_E* its batch failed with */
+  int32_t pad;
+} sfft_request_t;
+
+void sfft_server_params_init(sfft_server_params_t *p);
+/* NULL on error: SFFT_EINVAL (parameters), SFFT_ENOMEM, SFFT_EDEVICE. */
+sfft_server_t sfft_server_create(const sfft_server_params_t *p);
+/* The server's clock (monotonic nanoseconds), for release times. */
+int64_t sfft_server_clock_ns(void);
+/* Queue n requests: plans[i] with device pointers xs[i], idx[i], vals[i],
+   d_counts + i, d_status + i, eligible from release_ns[i] (server clock; 0 or
+   a NULL array = now).  tickets (optional) receives their numbers.  A request
+   whose workspace alone exceeds a lane's share is rejected with SFFT_ETOOBIG
+   and nothing is queued.  Returns SFFT_OK or SFFT_E*. */
+int32_t sfft_server_submit_many(sfft_server_t s, int32_t n, const sfft_plan_t *plans,
+                                const void *const *xs, int64_t *const *idx, void *const *vals,
+                                int64_t *d_counts, int32_t *d_status, const int64_t *release_ns,
+                                int64_t *tickets);
+/* One request; returns its ticket (>= 0) or SFFT_E*. */
+int64_t sfft_server_submit(sfft_server_t s, sfft_plan_t plan, const void *x, int64_t *out_idx,
+                           void *out_val, int64_t *d_count, int32_t *d_status, int64_t release_ns);
+/* Records of tickets first .. first + n - 1. */
+int32_t sfft_server_requests(sfft_server_t s, int64_t first, int32_t n, sfft_request_t *out);
+/* Block until one request, or every request submitted so far, is done. */
+int32_t sfft_server_wait(sfft_server_t s, int64_t ticket);
+int32_t sfft_server_drain(sfft_server_t s);
+/* Waits for every submitted request, then releases the server. */
+void sfft_server_destroy(sfft_server_t s);
 
 /* Release every cached batch context (graphs, workspaces). */
 void sfft_release_batches(void);

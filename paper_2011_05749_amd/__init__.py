@@ -117,6 +117,17 @@ class WorkspaceSignal(ctypes.Structure):
     ]
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [("hbm_bytes", ctypes.c_int64), ("lanes", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("release_ns", ctypes.c_int64), ("launch_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("batch", ctypes.c_int32), ("lane", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
 KERNEL_NAMES = {0: "k_reset", 1: "k_level0", 2: "k_sched", 3: "k_expand_fft",
                 4: "k_expand_direct", 5: "k_children", 6: "k_finalize", 7: "k_jump_pass",
                 8: "k_jump_resolve", 9: "k_col_pass", 10: "k_col_resolve"}
@@ -158,6 +169,24 @@ _lib.sfft_batch_stats.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.PO
 _lib.sfft_batch_stats.restype = ctypes.c_int32
 _lib.sfft_workspace.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(Workspace), _vp]
 _lib.sfft_workspace.restype = ctypes.c_int32
+_lib.sfft_server_params_init.argtypes = [ctypes.POINTER(ServerParams)]
+_lib.sfft_server_params_init.restype = None
+_lib.sfft_server_create.argtypes = [ctypes.POINTER(ServerParams)]
+_lib.sfft_server_create.restype = _vp
+_lib.sfft_server_clock_ns.argtypes = []
+_lib.sfft_server_clock_ns.restype = ctypes.c_int64
+_lib.sfft_server_submit_many.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+_lib.sfft_server_submit_many.restype = ctypes.c_int32
+_lib.sfft_server_submit.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int64]
+_lib.sfft_server_submit.restype = ctypes.c_int64
+_lib.sfft_server_requests.argtypes = [_vp, ctypes.c_int64, ctypes.c_int32, _vp]
+_lib.sfft_server_requests.restype = ctypes.c_int32
+_lib.sfft_server_wait.argtypes = [_vp, ctypes.c_int64]
+_lib.sfft_server_wait.restype = ctypes.c_int32
+_lib.sfft_server_drain.argtypes = [_vp]
+_lib.sfft_server_drain.restype = ctypes.c_int32
+_lib.sfft_server_destroy.argtypes = [_vp]
+_lib.sfft_server_destroy.restype = None
 _lib.sfft_release_batches.argtypes = []
 _lib.sfft_release_batches.restype = None
 _lib.sfft_last_error.argtypes = []
@@ -169,7 +198,9 @@ EXPORTS = ["sfft_params_init", "sfft_plan", "sfft_plan_ex", "sfft_plan_info", "s
            "sfft_exec", "sfft_exec_host", "sfft_exec_async", "sfft_exec_batch", "sfft_exec_batch_ex",
            "sfft_exec_batch_profile",
            "sfft_bucketize", "sfft_exec_stats", "sfft_batch_stats", "sfft_release_batches",
-           "sfft_workspace", "sfft_exec_noalloc",
+           "sfft_workspace", "sfft_exec_noalloc", "sfft_server_params_init", "sfft_server_create",
+           "sfft_server_clock_ns", "sfft_server_submit_many", "sfft_server_submit",
+           "sfft_server_requests", "sfft_server_wait", "sfft_server_drain", "sfft_server_destroy",
            "sfft_last_error", "sfft_strerror"]
 
 
@@ -400,6 +431,73 @@ def workspace(plans):
                                ctypes.cast(sig, ctypes.c_void_p)), "sfft_workspace")
     return ({f: getattr(w, f) for f, _ in Workspace._fields_},
             [{f: getattr(x, f) for f, _ in WorkspaceSignal._fields_} for x in sig])
+
+
+class Server:
+    """Serving loop (sfft_server_*): continuous batching of independent solves
+    with admission by HBM footprint.  submit() queues requests with release
+    times on the server clock (clock_ns()); requests() returns their times."""
+
+    def __init__(self, hbm_bytes: int = 8 << 30, lanes: int = 2, max_batch: int = 256):
+        p = ServerParams()
+        _lib.sfft_server_params_init(ctypes.byref(p))
+        p.hbm_bytes, p.lanes, p.max_batch = int(hbm_bytes), int(lanes), int(max_batch)
+        h = _lib.sfft_server_create(ctypes.byref(p))
+        if not h:
+            raise SfftError(_lib.sfft_last_error(), "sfft_server_create")
+        self._h = ctypes.c_void_p(h)
+        self._keep = []
+
+    @staticmethod
+    def clock_ns() -> int:
+        return int(_lib.sfft_server_clock_ns())
+
+    def submit(self, plans, xs, idxs, vals, counts, status, release_ns=None):
+        """Queue len(plans) requests; counts / status are device int64 / int32
+        tensors with one entry per request.  Returns the first ticket."""
+        import numpy as np
+        n = len(plans)
+        rel = None
+        if release_ns is not None:
+            rel = np.ascontiguousarray(np.asarray(release_ns, dtype=np.int64))
+            assert rel.shape == (n,)
+        tk = np.zeros(n, dtype=np.int64)
+        args = (_ptr_array([p.handle for p in plans]),
+                _ptr_array([_dev_ptr(x, "complex64", p.N, "x") for p, x in zip(plans, xs)]),
+                _ptr_array([_dev_ptr(t, "int64", p.K, "idx") for p, t in zip(plans, idxs)]),
+                _ptr_array([_dev_ptr(t, "complex64", p.K, "val") for p, t in zip(plans, vals)]))
+        _check(_lib.sfft_server_submit_many(
+            self._h, n, *args, _dev_ptr(counts, "int64", n, "counts"),
+            _dev_ptr(status, "int32", n, "status"),
+            ctypes.c_void_p(rel.ctypes.data) if rel is not None else None,
+            ctypes.c_void_p(tk.ctypes.data)), "sfft_server_submit_many")
+        self._keep.append((plans, xs, idxs, vals, counts, status))
+        return int(tk[0])
+
+    def requests(self, first: int, n: int):
+        """dict of numpy arrays: release_ns, launch_ns, done_ns, batch, lane, status."""
+        import numpy as np
+        arr = (Request * n)()
+        _check(_lib.sfft_server_requests(self._h, first, n, arr), "sfft_server_requests")
+        return {f: np.array([getattr(r, f) for r in arr]) for f, _ in Request._fields_ if f != "pad"}
+
+    def wait(self, ticket: int):
+        _check(_lib.sfft_server_wait(self._h, ticket), "sfft_server_wait")
+
+    def drain(self):
+        _check(_lib.sfft_server_drain(self._h), "sfft_server_drain")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sfft_server_destroy(self._h)
+            self._h = None
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def release_batches():

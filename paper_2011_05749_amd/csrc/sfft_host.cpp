@@ -13,7 +13,7 @@
 #include <thread>
 #include <vector>
 
-#include "sfft_internal.h"
+#include "sfft_host.h"
 
 using namespace sfft;
 
@@ -65,7 +65,6 @@ uint64_t gcd64(uint64_t a, uint64_t b) {
 
 struct BatchCtx;
 struct HostCtx;
-struct Layout;
 
 }  // namespace
 
@@ -108,7 +107,7 @@ void sfft::host_twiddles(float2 *out) {
   }
 }
 
-namespace {
+namespace sfft {
 
 // per-device twiddle table e^{-2 pi i k / kFftMax}
 std::mutex g_tw_mu;
@@ -133,11 +132,6 @@ hipError_t device_twiddles(int dev, const float2 **out) {
   return hipSuccess;
 }
 
-struct LevelLaunch {
-  bool fft, direct, children, jump, col;
-  int grid_fft, grid_direct, grid_children, grid_jump, grid_resolve, grid_col, grid_col_resolve;
-};
-
 // first tree level whose parents' stride N / (B0 2^{l-1}) is <= jump_L, or a
 // level beyond max_levels when the subtree resolution is off
 int jump_level(const SigDesc &d) {
@@ -149,27 +143,6 @@ int jump_level(const SigDesc &d) {
 
 constexpr size_t kSlabAlign = 256;
 size_t align_up(size_t v) { return (v + kSlabAlign - 1) & ~(kSlabAlign - 1); }
-
-// Workspace of one batch, decided on the host from its plans alone: every
-// signal's descriptor with its offsets into the arenas, the work lists, the
-// size of every arena and its byte offset in one device slab, and the static
-// launch shape of every tree level.  No device call.
-struct Layout {
-  std::vector<SigDesc> desc;
-  std::vector<int32_t> lists;
-  int ntree = 0, nffast = 0;
-  size_t l0_at = 0, l0c_at = 0;
-  int32_t l0_items = 0, l0c_items = 0;
-  int nmax = 1, max_B0 = 1, max_stage = 1, max_found_cap = 64;
-  int32_t jrows = kJumpItemRows, any_fp32 = 0, col_lp_mask = 0, any_wide_jump = 0;
-  bool any_jump = false;
-  std::vector<LevelLaunch> levels;
-  // arena sizes in elements
-  int64_t n_y0 = 0, n_fst = 0, n_found = 0, n_multi = 0, n_mvec = 0, n_jacc = 0, n_jcol = 0;
-  // byte offsets of the parts of the slab, and its size
-  size_t o_desc = 0, o_io = 0, o_st = 0, o_lists = 0, o_pre = 0, o_out = 0, o_y0 = 0, o_fst = 0,
-         o_ff = 0, o_fa = 0, o_mc = 0, o_my = 0, o_mz = 0, o_jacc = 0, o_jcol = 0, bytes = 0;
-};
 
 int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, int ncu, Layout &Y) {
   const int nsig = (int)ps.size();
@@ -419,13 +392,6 @@ int device_cus(int device) {
   return ncu;
 }
 
-// Timing events of a profiled pipeline run: one after every launch, with the
-// kernel id of each interval.
-struct Prof {
-  std::vector<hipEvent_t> ev;
-  std::vector<int32_t> id;
-};
-
 // The whole pipeline of a layout bound in c, on stream s.  With `prof`, a
 // timing event is recorded after every launch.
 hipError_t launch_pipeline(const Layout &lay, const LaunchCtx &c, hipStream_t s, Prof *prof) {
@@ -469,6 +435,22 @@ hipError_t launch_pipeline(const Layout &lay, const LaunchCtx &c, hipStream_t s,
   if ((e = launch_finalize(c, s)) != hipSuccess) return e;
   return mark(SFFT_KERNEL_FINALIZE);
 }
+
+bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+int32_t set_last_error(int32_t code) { return fail(code); }
+
+}  // namespace sfft
+
+namespace {
 
 struct BatchCtx {
   int device = -1;
@@ -521,16 +503,6 @@ struct BatchCtx {
     return launch_pipeline(lay, c, s, prof);
   }
 };
-
-bool is_device_ptr(const void *p) {
-  if (!p) return false;
-  hipPointerAttribute_t a;
-  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
-}
 
 std::mutex g_batch_mu;
 std::map<std::vector<const sfft_plan_s *>, std::unique_ptr<BatchCtx>> g_batches;
@@ -604,7 +576,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     in.max_levels = (p.max_levels < 0 || p.max_levels > full) ? full : p.max_levels;
     // level-1 column pass: B0 = P x 32 with P in {32, 64, 128}, and an even
     // number of column blocks of 512 / P columns
-    in.l1_resolve = p.l1_resolve && (B0 == 1024 || B0 == 2048 || B0 == 4096) &&
+    in.l1_resolve = p.l1_resolve && (B0 == 1024 || B0 == 2048 || B0 == 4096 || B0 == 8192) &&
                     p.N / B0 >= 32768 / B0 && in.max_levels >= 1;
     SplitMix64 g{p.seed};
     for (int r = 0; r < p.stages; r++) {

@@ -40,7 +40,8 @@ def test_struct_layouts_match_binding(tmp_path):
     prog = tmp_path / "layout.c"
     fields = {
         "sfft_params_t": sfft.Params, "sfft_plan_info_t": sfft.PlanInfo, "sfft_stats_t": sfft.Stats,
-        "sfft_workspace_t": sfft.Workspace, "sfft_workspace_signal_t": sfft.WorkspaceSignal}
+        "sfft_workspace_t": sfft.Workspace, "sfft_workspace_signal_t": sfft.WorkspaceSignal,
+        "sfft_server_params_t": sfft.ServerParams, "sfft_request_t": sfft.Request}
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HDR}"', "int main(void){"]
     for cname, py in fields.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -157,7 +158,7 @@ def test_noisy_plan_allows_one_delay_and_window():
 
 
 def test_column_pass_shapes():
-    """The level-1 column pass is taken for B0 = 1024, 2048, 4096 with at
+    """The level-1 column pass is taken for B0 = 1024, 2048, 4096, 8192 with at
     least 32768 / B0 columns and one tree level, never for FFAST plans."""
     assert sfft.Plan(2 ** 22, 1024, 4, 2, B0=2048).info.l1_resolve == 1
     assert sfft.Plan(2 ** 15, 300, 2, 2, B0=2048).info.l1_resolve == 1
@@ -166,7 +167,8 @@ def test_column_pass_shapes():
     assert sfft.Plan(2 ** 14, 300, 2, 2, B0=1024).info.l1_resolve == 0
     assert sfft.Plan(2 ** 15, 300, 2, 2, B0=4096).info.l1_resolve == 1
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512).info.l1_resolve == 0
-    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=8192).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=8192).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 14, 300, 2, 2, B0=8192).info.l1_resolve == 0
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, l1_resolve=0).info.l1_resolve == 0
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, max_levels=0).info.l1_resolve == 0
     assert sfft.Plan(10800, 10, 3, 2).info.l1_resolve == 0

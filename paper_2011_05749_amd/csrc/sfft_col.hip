@@ -84,7 +84,7 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const 
   return (const __attribute__((address_space(4))) T *)p;
 }
 
-// Level-1 column pass (power-of-two N, B0 = 32 P, P = 2^LP in {32, 64, 128}):
+// Level-1 column pass (power-of-two N, B0 = 32 P, P = 2^LP in {32, 64, 128, 256}):
 // viewing x as B0 rows m of L = N/B0 samples, class c's coefficients
 //   M_c(t) = sum_{m < B0} x[m L + t] e^{-2 pi i c m / B0},   t < L
 // are the B0-point DFT down column t, evaluated at c.  With m = p + P q and
@@ -286,6 +286,7 @@ hipError_t launch_col_pass(const LaunchCtx &c, int grid, hipStream_t s) {
   if (c.col_lp_mask & 1) hipLaunchKernelGGL(k_col_pass<5>, dim3(grid), dim3(kColThreads), 0, s, c);
   if (c.col_lp_mask & 2) hipLaunchKernelGGL(k_col_pass<6>, dim3(grid), dim3(kColThreads), 0, s, c);
   if (c.col_lp_mask & 4) hipLaunchKernelGGL(k_col_pass<7>, dim3(grid), dim3(kColThreads), 0, s, c);
+  if (c.col_lp_mask & 8) hipLaunchKernelGGL(k_col_pass<8>, dim3(grid), dim3(kColThreads), 0, s, c);
   return hipGetLastError();
 }
 

@@ -74,6 +74,28 @@ def assert_parity(g, o, tol=VAL_TOL):
         assert rel_l2(gv[m].astype(np.complex128), ov[m]) <= tol
 
 
+def assert_elementwise(Yg, Yo, tol=VAL_TOL):
+    """Every bucket within tol of the table's RMS: near-zero buckets are held
+    to the same absolute bar as the occupied ones (FP32 bucketization)."""
+    rms = np.sqrt(np.mean(np.abs(Yo) ** 2))
+    err = np.abs(Yg - Yo)
+    worst = np.unravel_index(np.argmax(err), err.shape)
+    assert err[worst] <= tol * rms, (worst, err[worst] / rms)
+
+
+def oracle_many(jobs):
+    """oracle.solve over (cfg, x) pairs on all host threads (the C oracle
+    releases the GIL): list of (idx, val, count, trace)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+    try:
+        nt = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nt = os.cpu_count() or 1
+    with ThreadPoolExecutor(max_workers=max(1, min(nt, 16, len(jobs)))) as ex:
+        return list(ex.map(lambda j: oracle.solve(*j), jobs))
+
+
 # ------------------------------------------------------- bucketization (a2, a3)
 @pytest.mark.parametrize("N,K,R,D,B0,seed", [
     (2 ** 14, 40, 4, 2, 128, 1), (2 ** 12, 8, 1, 2, 8, 2), (2 ** 16, 300, 3, 3, 1024, 3),
@@ -86,6 +108,7 @@ def test_bucketize_tree(sfft, N, K, R, D, B0, seed):
     Yo = oracle.level0(oracle_cfg(N, K, R, D, seed=seed, B0=B0), x)
     assert Yg.shape == Yo.shape
     assert rel_l2(Yg, Yo) <= VAL_TOL
+    assert_elementwise(Yg, Yo)
 
 
 def test_bucketize_ffast(sfft):
@@ -95,6 +118,7 @@ def test_bucketize_ffast(sfft):
     Yg = plan.bucketize(to_dev(x)).cpu().numpy().astype(np.complex128)
     Yo = oracle.level0(oracle_cfg(10800, 10, 3, 2), x)
     assert rel_l2(Yg, Yo) <= VAL_TOL
+    assert_elementwise(Yg, Yo)
 
 
 # ----------------------------------------------------------- FFAST peeling (a6)
@@ -211,7 +235,7 @@ def test_noisy_tree(sfft, window, seed, jump):
     sp = siggen.make_spec(N, K, seed, snr_db=20.0)
     x = siggen.synth(sp)
     g, o = solve_both(sfft, x, N, K, 4, 2, seed=8, mode=1, window=window, jump_L=jump)
-    assert_parity(g, o, tol=1e-4)
+    assert_parity(g, o)
     assert abs(g[3]["noise_var"] / o[3].noise_var - 1) < 1e-4
 
 
@@ -269,6 +293,36 @@ def test_headline_shape_sampled(sfft):
         np.testing.assert_array_equal(g[0], siggen.truth(sp)[0])
 
 
+def test_headline_batch_graph_vs_oracle(sfft):
+    """The benchmark's launch configuration at reduced count: 32 signals of
+    N = 2^22, K = 1024 (B0 = 2048, 4 rounds x 2 delays, level-1 column pass,
+    work-groups pairing items of adjacent signals' row segments) in one batch
+    replayed from its captured graph; every signal against the oracle, on
+    every replay."""
+    N, K, nb = 2 ** 22, 1024, 32
+    seeds = [9000 + i for i in range(nb)]
+    specs = [siggen.make_spec(N, K, s) for s in seeds]
+    xs = [siggen.synth_torch(sp, torch.device("cuda")) for sp in specs]
+    plans = [sfft.Plan(N, K, 4, 2, seed=s, B0=2048) for s in seeds]
+    assert all(p.info.l1_resolve == 1 for p in plans)
+    ref = oracle_many([(oracle_cfg(N, K, 4, 2, seed=s, B0=2048), x.cpu().numpy())
+                       for s, x in zip(seeds, xs)])
+    b = sfft.Batch(plans, xs)
+    for rep in range(3):
+        b.run(graph=True)
+        torch.cuda.synchronize()
+        counts, status = b.counts.cpu().numpy(), b.status.cpu().numpy()
+        for i, (oi, ov, oc, tr) in enumerate(ref):
+            assert counts[i] == oc and status[i] == tr.status, (rep, i)
+            gi = b.idxs[i].cpu().numpy()
+            np.testing.assert_array_equal(gi, oi)
+            np.testing.assert_array_equal(gi, siggen.truth(specs[i])[0])
+            assert rel_l2(b.vals[i].cpu().numpy().astype(np.complex128), ov) <= VAL_TOL
+        _ = (xs[0].abs() * 2).sum().item()   # eager work between replays
+    del b
+    sfft.release_batches()
+
+
 # ------------------------------------------------- configuration-scale parity
 def _l_errors(idx, val, sup, vals):
     """L0 (support misses + false alarms), L1 (mean abs error over the union),
@@ -307,7 +361,7 @@ def test_config2_noisy_batch64(sfft):
         oi, ov, oc, tr = oracle.solve(cfg, xs[i])
         np.testing.assert_array_equal(b.idxs[i].cpu().numpy(), oi)
         m = oi >= 0
-        assert rel_l2(b.vals[i].cpu().numpy()[m].astype(np.complex128), ov[m]) <= 1e-4
+        assert rel_l2(b.vals[i].cpu().numpy()[m].astype(np.complex128), ov[m]) <= VAL_TOL
 
 
 def test_config3_uneven_2048_batch(sfft):
@@ -357,25 +411,46 @@ def test_config3_uneven_2048_batch(sfft):
 
 def test_config4_precision_shape(sfft):
     """N = 2^24, K = 4096, magnitudes 10^U[0,2], SNR 30 dB, B0 = 8192, 4 rounds
-    x 2 delays, noisy mode: one signal against the oracle (indices bit-exact,
-    values within 1e-4), L0/L1/L2 against the planted spectrum reported."""
+    x 2 delays, noisy mode: FP32 buckets with FP64 locate / value / residual
+    (precision 0) and all-FP32 (precision 1), each against the FP64 oracle:
+    index agreement and value error reported per variant; the FP64 variant is
+    held to bit-exact indices and 1e-5, the FP32 variant to its measured
+    agreement."""
     N, K = 2 ** 24, 4096
     sp = siggen.make_spec(N, K, 5000, mag="loguniform", mag_lo=0.0, mag_hi=2.0, snr_db=30.0)
     x = siggen.synth(sp)
-    g, o = solve_both(sfft, x, N, K, 4, 2, seed=5000, B0=8192, mode=1)
-    assert_parity(g, o, tol=1e-4)
-    l0, l1, l2 = _l_errors(g[0], g[1], *siggen.truth(sp))
-    print(f"config4: L0={l0} L1={l1:.3e} L2={l2:.3e} count={g[2]}")
-    assert l2 < 0.05
+    oi, ov, oc, tr = oracle.solve(oracle_cfg(N, K, 4, 2, seed=5000, mode=1, B0=8192), x)
+    xd = to_dev(x)
+    for prec in (0, 1):
+        plan = sfft.Plan(N, K, 4, 2, seed=5000, B0=8192, mode="noisy", precision=prec)
+        gi, gv, gc = plan.exec(xd)
+        gi, gv = gi.cpu().numpy(), gv.cpu().numpy().astype(np.complex128)
+        go, oo = set(gi[gi >= 0].tolist()), set(oi[oi >= 0].tolist())
+        common = sorted(go & oo)
+        gm = dict(zip(gi.tolist(), gv.tolist()))
+        om = dict(zip(oi.tolist(), ov.tolist()))
+        a = np.array([gm[f] for f in common])
+        o = np.array([om[f] for f in common])
+        l0, l1, l2 = _l_errors(gi, gv, *siggen.truth(sp))
+        print(f"config4 precision={prec}: index disagreement vs oracle {len(go ^ oo)} of {len(oo)}, "
+              f"value rel L2 on common {rel_l2(a, o):.2e}; vs planted L0={l0} L2={l2:.3e}")
+        if prec == 0:
+            assert gc == oc
+            np.testing.assert_array_equal(gi, oi)
+            assert rel_l2(gv[oi >= 0], ov[oi >= 0]) <= VAL_TOL
+        else:
+            assert len(go ^ oo) <= 4
+            assert rel_l2(a, o) <= 1e-5
+        assert l2 < 0.05
+        plan.close()
 
 
 def test_config5_serving_mix(sfft):
     """24 requests of the serving mix: N uniform on {2^16, ..., 2^24}, K
     log-uniform on [16, 4096], SNR uniform on [10, 40] dB, B0 = next pow2 >=
     2K, 4 rounds x 2 delays, noisy mode, all in one batch (graph replay).
-    Every request against its planted spectrum; those the oracle finishes in
-    seconds (N <= 2^18, or N = 2^20 with K < 1024) against the oracle, with
-    indices bit-exact."""
+    Every request against its planted spectrum and against the oracle
+    (indices bit-exact, values within 1e-5)."""
     rng = np.random.default_rng(7000)
     reqs = []
     for i in range(24):
@@ -393,16 +468,16 @@ def test_config5_serving_mix(sfft):
     for _ in range(2):
         b.run(graph=True)
     torch.cuda.synchronize()
+    ref = oracle_many([(oracle_cfg(N, K, 4, 2, seed=7000 + i, mode=1, B0=int(plans[i].info.B0)),
+                        xs[i].cpu().numpy()) for i, (N, K, snr) in enumerate(reqs)])
     exact = 0
     for i, sp in enumerate(specs):
         gi = b.idxs[i].cpu().numpy()
         exact += int(np.array_equal(gi, siggen.truth(sp)[0]))
-        N, K, snr = reqs[i]
-        if N <= 2 ** 18 or (N == 2 ** 20 and K < 1024):
-            cfg = oracle_cfg(N, K, 4, 2, seed=7000 + i, mode=1, B0=int(plans[i].info.B0))
-            oi, ov, oc, tr = oracle.solve(cfg, xs[i].cpu().numpy())
-            np.testing.assert_array_equal(gi, oi)
-            m = oi >= 0
-            assert rel_l2(b.vals[i].cpu().numpy()[m].astype(np.complex128), ov[m]) <= 1e-4
+        oi, ov, oc, tr = ref[i]
+        np.testing.assert_array_equal(gi, oi, err_msg=f"request {i} {reqs[i]}")
+        m = oi >= 0
+        assert rel_l2(b.vals[i].cpu().numpy()[m].astype(np.complex128), ov[m]) <= VAL_TOL
+    assert any(r[0] == 2 ** 22 for r in reqs) and any(r[0] == 2 ** 24 for r in reqs)
     print(f"config5: {exact}/24 requests recover the planted support exactly")
     assert exact >= 20   # low-SNR requests (10-15 dB) may lose a tone

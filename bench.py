@@ -458,21 +458,43 @@ def run_configs(sfft, torch, np, steps, warmup, dev):
     return out
 
 
-def run_precision_study(sfft, torch, np, steps, warmup, dev, nsig=8):
+def run_precision_study(sfft, torch, np, steps, warmup, dev, nsig=8, n_oracle=2):
     """N = 2^24, K = 4096, magnitudes 10^U[0,2], 30 dB, B0 = 8192, 4 rounds x 2
-    delays, noisy mode: FP64 against FP32 locate / value / residual, speed and
-    errors against the planted spectrum (L0 = support misses + false alarms,
-    L2 = relative error)."""
+    delays, noisy mode, three variants: FP32 buckets with FP64 locate / value
+    / residual (fp64), all FP32 (fp32), and FP16-stored samples with FP32
+    sums and FP64 decisions (fp16_samples, signals packed on the device by
+    sfft_pack_fp16).  Speed over a batch of nsig; errors against the planted
+    spectrum (L0 = misses + false alarms, L2 relative) on all of them and
+    against the FP64 oracle on the complex64 signal for the first n_oracle
+    (index disagreements, value relative L2 on the common indices); the
+    oracle solves run on host threads while the GPU variants are timed."""
+    import threading
+
+    import oracle
     import siggen
     N, K = 2 ** 24, 4096
     seeds = [5000 + i for i in range(nsig)]
     specs = [siggen.make_spec(N, K, s, mag="loguniform", mag_lo=0.0, mag_hi=2.0, snr_db=30.0)
              for s in seeds]
     xs = [siggen.synth_torch(sp, dev) for sp in specs]
+    ref = [None] * n_oracle
+
+    def solve_ref(i, x):
+        ref[i] = oracle.solve(oracle.config(N, K, 4, 2, seed=seeds[i], mode=1, B0=8192), x)
+
+    oracle.lib()
+    ths = [threading.Thread(target=solve_ref, args=(i, xs[i].cpu().numpy())) for i in range(n_oracle)]
+    for t in ths:
+        t.start()
+    packed = [sfft.pack_fp16(x) for x in xs]
+    torch.cuda.synchronize()
+    variants = {"fp64": (dict(precision=0), xs), "fp32": (dict(precision=1), xs),
+                "fp16_samples": (dict(precision=0, sample_format=1), packed)}
     out = {}
-    for prec in (0, 1):
-        plans = [sfft.Plan(N, K, 4, 2, seed=s, B0=8192, mode="noisy", precision=prec) for s in seeds]
-        b = sfft.Batch(plans, xs)
+    results = {}
+    for name, (kw, inp) in variants.items():
+        plans = [sfft.Plan(N, K, 4, 2, seed=s, B0=8192, mode="noisy", **kw) for s in seeds]
+        b = sfft.Batch(plans, inp)
         for _ in range(warmup):
             b.run(graph=True)
         torch.cuda.synchronize()
@@ -482,9 +504,11 @@ def run_precision_study(sfft, torch, np, steps, warmup, dev, nsig=8):
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
         l0s, l2s = [], []
+        res = []
         for i, sp in enumerate(specs):
             idx = b.idxs[i].cpu().numpy()
             val = b.vals[i].cpu().numpy().astype(np.complex128)
+            res.append((idx, val))
             sup, vals = siggen.truth(sp)
             got = dict(zip(idx[idx >= 0].tolist(), val[idx >= 0].tolist()))
             want = dict(zip(sup.tolist(), vals.tolist()))
@@ -492,11 +516,27 @@ def run_precision_study(sfft, torch, np, steps, warmup, dev, nsig=8):
             l0s.append(len(set(got) ^ set(want)))
             d = np.array([got.get(k, 0) - want.get(k, 0) for k in keys])
             l2s.append(float(np.linalg.norm(d) / np.linalg.norm(vals)))
-        out["fp64" if prec == 0 else "fp32"] = {
-            "value": round(nsig / dt, 2), "unit": "spectra/s", "L0_mean": float(np.mean(l0s)),
-            "L2_mean": float(np.mean(l2s))}
+        results[name] = res
+        out[name] = {"value": round(nsig / dt, 2), "unit": "spectra/s", "L0_mean": float(np.mean(l0s)),
+                     "L2_mean": float(np.mean(l2s))}
         del b
         sfft.release_batches()
+    for t in ths:
+        t.join()
+    for name in variants:
+        dis, err = [], []
+        for i in range(n_oracle):
+            oi, ov, oc, tr = ref[i]
+            gi, gv = results[name][i]
+            go, oo = set(gi[gi >= 0].tolist()), set(oi[oi >= 0].tolist())
+            common = sorted(go & oo)
+            gm, om = dict(zip(gi.tolist(), gv.tolist())), dict(zip(oi.tolist(), ov.tolist()))
+            a = np.array([gm[f] for f in common])
+            o = np.array([om[f] for f in common])
+            dis.append(len(go ^ oo))
+            err.append(float(np.linalg.norm(a - o) / max(np.linalg.norm(o), 1e-30)))
+        out[name]["vs_oracle"] = {"signals": n_oracle, "index_disagreements": dis,
+                                  "value_rel_l2_common": err}
     return out
 
 

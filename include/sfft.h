@@ -72,6 +72,11 @@ extern "C" {
 #define SFFT_NOISY 1 /* general sparse: noise-scaled thresholds T0, T1 and
                         enumeration of the L candidates (Sect. 3.1, Method 2) */
 
+/* signal storage (sfft_params_t.sample_format) */
+#define SFFT_SAMPLES_C64 0   /* interleaved complex64 */
+#define SFFT_SAMPLES_F16 1   /* packed FP16 with a per-signal scale (sfft_pack_fp16) */
+#define SFFT_F16_HEADER_BYTES 16
+
 /* plan kinds */
 #define SFFT_KIND_TREE 0  /* N a power of two: binary tree search */
 #define SFFT_KIND_FFAST 1 /* N a product of co-prime stages: peeling */
@@ -149,9 +154,16 @@ typedef struct {
                               every class's L coefficients M_c(t) (the class's bucket
                               measured with shift t, times B0), and each class vector
                               of any later level (Sect. 3.3) is a sum of 2^d of them,
-                              d levels below; taken when B0 is 1024, 2048, 4096 or 8192 and
+                              d levels below; taken when B0 is 512, 1024, 2048, 4096 or 8192 and
                               L >= 32768 / B0, in place of jump_L and the level-by-level
                               gathers.  0 = off; other values: SFFT_EINVAL */
+  int32_t sample_format;   /* tree: SFFT_SAMPLES_C64 (default) = x holds N complex64;
+                              SFFT_SAMPLES_F16 = x holds the packed FP16 form that
+                              sfft_pack_fp16 writes (a 16-byte header whose first
+                              float is a scale s, then N pairs (re, im) of IEEE
+                              binary16, sample n = s (re + i im)): half the bytes of
+                              the signal; every sum stays FP32.  FFAST plans and
+                              sfft_exec_host: SFFT_EUNSUPPORTED */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -179,6 +191,7 @@ typedef struct {
   uint64_t rf_off[SFFT_MAX_ROUNDS];   /* r_c */
   int32_t precision;       /* 0: FP64 decisions, 1: FP32 */
   int32_t l1_resolve;      /* 1 when the level-1 column pass is taken */
+  int32_t sample_format;   /* SFFT_SAMPLES_C64 or SFFT_SAMPLES_F16 */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */
@@ -292,6 +305,17 @@ int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
                                 int64_t *const *idx, void *const *vals, int64_t *d_counts,
                                 int32_t *d_status, int32_t n, float *ms, int32_t *kernel,
                                 int32_t cap);
+
+/* Packed FP16 form of a complex64 signal, for plans with sample_format =
+   SFFT_SAMPLES_F16: out (device, SFFT_F16_HEADER_BYTES + 4 N bytes) receives
+   a header whose first float is the scale s = 2^(e - 15), e the exponent with
+   2^(e-1) <= m < 2^e for the largest component magnitude m of x (s = 1 when
+   x = 0), so every scaled component lies below 2^15 and inside binary16's
+   range whatever the signal's level; then sample n as the binary16 values of
+   re / s and im / s, rounded to nearest even.  Bytes 4..15 of the header
+   are scratch of the routine.  x: device complex64[N].  Asynchronous on
+   `stream` (NULL = null stream).  Returns SFFT_OK or SFFT_E*. */
+int32_t sfft_pack_fp16(const void *x, int64_t N, void *out, void *stream);
 
 /* Bucketization alone (Eq. 5-6, level 0): out (device complex64) receives,
    for a tree plan, B0 class vectors of R*D values (class-major: out[c*R*D +

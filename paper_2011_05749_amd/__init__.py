@@ -60,6 +60,7 @@ class Params(ctypes.Structure):
         ("peel_starts", ctypes.c_int32),
         ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
         ("l1_resolve", ctypes.c_int32),
+        ("sample_format", ctypes.c_int32),
     ]
 
 
@@ -85,6 +86,7 @@ class PlanInfo(ctypes.Structure):
         ("rf_off", ctypes.c_uint64 * MAX_ROUNDS),
         ("precision", ctypes.c_int32),
         ("l1_resolve", ctypes.c_int32),
+        ("sample_format", ctypes.c_int32),
     ]
 
 
@@ -187,6 +189,8 @@ _lib.sfft_server_drain.argtypes = [_vp]
 _lib.sfft_server_drain.restype = ctypes.c_int32
 _lib.sfft_server_destroy.argtypes = [_vp]
 _lib.sfft_server_destroy.restype = None
+_lib.sfft_pack_fp16.argtypes = [_vp, ctypes.c_int64, _vp, _vp]
+_lib.sfft_pack_fp16.restype = ctypes.c_int32
 _lib.sfft_release_batches.argtypes = []
 _lib.sfft_release_batches.restype = None
 _lib.sfft_last_error.argtypes = []
@@ -201,6 +205,7 @@ EXPORTS = ["sfft_params_init", "sfft_plan", "sfft_plan_ex", "sfft_plan_info", "s
            "sfft_workspace", "sfft_exec_noalloc", "sfft_server_params_init", "sfft_server_create",
            "sfft_server_clock_ns", "sfft_server_submit_many", "sfft_server_submit",
            "sfft_server_requests", "sfft_server_wait", "sfft_server_drain", "sfft_server_destroy",
+           "sfft_pack_fp16",
            "sfft_last_error", "sfft_strerror"]
 
 
@@ -222,6 +227,32 @@ def _stream_handle(stream):
         import torch
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+
+
+F16_HEADER_BYTES = 16
+SAMPLES_C64, SAMPLES_F16 = 0, 1
+
+
+def _sig_ptr(plan, x, what="x"):
+    """Device pointer of a signal in the plan's sample format: complex64[N],
+    or the packed FP16 form (uint8[16 + 4 N], see pack_fp16)."""
+    if plan.info.sample_format == SAMPLES_F16:
+        return _dev_ptr(x, "uint8", F16_HEADER_BYTES + 4 * plan.N, what)
+    return _dev_ptr(x, "complex64", plan.N, what)
+
+
+def pack_fp16(x, out=None, stream=None):
+    """Packed FP16 form of a complex64 device signal (sfft_pack_fp16): uint8
+    tensor of 16 + 4 N bytes (header with the power-of-two scale, then
+    binary16 pairs)."""
+    import torch
+    n = x.numel()
+    if out is None:
+        out = torch.empty(F16_HEADER_BYTES + 4 * n, dtype=torch.uint8, device=x.device)
+    _check(_lib.sfft_pack_fp16(_dev_ptr(x, "complex64", n, "x"), n,
+                               _dev_ptr(out, "uint8", F16_HEADER_BYTES + 4 * n, "out"),
+                               _stream_handle(stream)), "sfft_pack_fp16")
+    return out
 
 
 def _dev_ptr(t, dtype_name, n=None, what="tensor"):
@@ -297,7 +328,7 @@ class Plan:
     def exec(self, x, out_idx=None, out_val=None):
         """Synchronous solve: returns (idx int64[K], val complex64[K], count)."""
         import torch
-        xp = _dev_ptr(x, "complex64", self.N, "x")
+        xp = _sig_ptr(self, x)
         if out_idx is None:
             out_idx = torch.empty(self.K, dtype=torch.int64, device=x.device)
         if out_val is None:
@@ -324,7 +355,7 @@ class Plan:
 
     def exec_async(self, x, out_idx, out_val, d_count, d_status, stream=None):
         _check(_lib.sfft_exec_async(
-            self._h, _dev_ptr(x, "complex64", self.N, "x"),
+            self._h, _sig_ptr(self, x),
             _dev_ptr(out_idx, "int64", self.K, "out_idx"),
             _dev_ptr(out_val, "complex64", self.K, "out_val"),
             _dev_ptr(d_count, "int64", 1, "d_count"), _dev_ptr(d_status, "int32", 1, "d_status"),
@@ -334,7 +365,7 @@ class Plan:
         """sfft_exec_noalloc: as exec_async, with the workspace in the library's
         static device scratch (no device allocation)."""
         _check(_lib.sfft_exec_noalloc(
-            self._h, _dev_ptr(x, "complex64", self.N, "x"),
+            self._h, _sig_ptr(self, x),
             _dev_ptr(out_idx, "int64", self.K, "out_idx"),
             _dev_ptr(out_val, "complex64", self.K, "out_val"),
             _dev_ptr(d_count, "int64", 1, "d_count"), _dev_ptr(d_status, "int32", 1, "d_status"),
@@ -349,7 +380,7 @@ class Plan:
         else:
             shape = (int(sum(inf.stage_B[j] for j in range(inf.R))), int(inf.D))
         out = torch.empty(shape, dtype=torch.complex64, device=x.device)
-        _check(_lib.sfft_bucketize(self._h, _dev_ptr(x, "complex64", self.N, "x"),
+        _check(_lib.sfft_bucketize(self._h, _sig_ptr(self, x),
                                    _dev_ptr(out, "complex64", None, "out")), "sfft_bucketize")
         return out
 
@@ -384,7 +415,7 @@ class Batch:
         self.counts = torch.zeros(n, dtype=torch.int64, device=dev)
         self.status = torch.zeros(n, dtype=torch.int32, device=dev)
         self._plans = _ptr_array([p.handle for p in plans])
-        self._xs = _ptr_array([_dev_ptr(x, "complex64", p.N, "x") for p, x in zip(plans, self.xs)])
+        self._xs = _ptr_array([_sig_ptr(p, x) for p, x in zip(plans, self.xs)])
         self._idx = _ptr_array([_dev_ptr(t, "int64", p.K, "idx") for p, t in zip(plans, self.idxs)])
         self._val = _ptr_array([_dev_ptr(t, "complex64", p.K, "val")
                                 for p, t in zip(plans, self.vals)])
@@ -463,7 +494,7 @@ class Server:
             assert rel.shape == (n,)
         tk = np.zeros(n, dtype=np.int64)
         args = (_ptr_array([p.handle for p in plans]),
-                _ptr_array([_dev_ptr(x, "complex64", p.N, "x") for p, x in zip(plans, xs)]),
+                _ptr_array([_sig_ptr(p, x) for p, x in zip(plans, xs)]),
                 _ptr_array([_dev_ptr(t, "int64", p.K, "idx") for p, t in zip(plans, idxs)]),
                 _ptr_array([_dev_ptr(t, "complex64", p.K, "val") for p, t in zip(plans, vals)]))
         _check(_lib.sfft_server_submit_many(

@@ -25,7 +25,7 @@ OUT = os.path.join(HERE, "_lib", "libsfft.so")
 OBJ = os.path.join(HERE, "_lib", "obj")
 SOURCES = ["sfft_level0.hip", "sfft_ffast.hip", "sfft_tree.hip", "sfft_jump.hip", "sfft_col.hip",
            "sfft_colres.hip", "sfft_finalize.hip", "sfft_noalloc.hip", "sfft_host.cpp",
-           "sfft_server.cpp"]
+           "sfft_server.cpp", "sfft_pack.hip"]
 HEADERS = [os.path.join(CSRC, "sfft_internal.h"), os.path.join(CSRC, "sfft_device.h"),
            os.path.join(CSRC, "sfft_host.h"),
            os.path.join(ROOT, "include", "sfft.h")]

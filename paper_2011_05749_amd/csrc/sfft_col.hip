@@ -84,7 +84,7 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const 
   return (const __attribute__((address_space(4))) T *)p;
 }
 
-// Level-1 column pass (power-of-two N, B0 = 32 P, P = 2^LP in {32, 64, 128, 256}):
+// Level-1 column pass (power-of-two N, B0 = 32 P, P = 2^LP in {16, 32, 64, 128, 256}):
 // viewing x as B0 rows m of L = N/B0 samples, class c's coefficients
 //   M_c(t) = sum_{m < B0} x[m L + t] e^{-2 pi i c m / B0},   t < L
 // are the B0-point DFT down column t, evaluated at c.  With m = p + P q and
@@ -95,8 +95,9 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const 
 // 32 rows and takes the inner DFT over q in registers; after an LDS exchange
 // of the whole item, thread (t, k1, h), h < H2 = P / 32, takes the 32 values
 // p = h + H2 p' of one outer DFT, a 32-point register DFT over p' and, for
-// P > 32, a radix-H2 step across adjacent lanes; the results go back to the
-// LDS places the thread read.  Only the classes left open at level 0 are then
+// P > 32, a radix-H2 step across adjacent lanes (for P = 16, thread (t, k1)
+// takes the 16-point outer DFTs of k1 and k1 + 16); the results go back to
+// the LDS places the thread read.  Only the classes left open at level 0 are then
 // stored (raw M_c(t), complex64, one row of L per multi-ton slot).
 // One resident work-group per CU walks a contiguous range of items: the
 // rows of item k + 1 are in flight while item k is transformed, and no other
@@ -104,18 +105,20 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const 
 // loaded ahead).  Work-groups 8 apart run on one XCD; such a pair takes the
 // two items of each adjacent pair, in step, so that both read the same
 // 128-byte lines through one L2.
-template <int LP>
+// F16: the instance for signals stored in the packed FP16 form (binary16 rows,
+// the scale applied to the stored coefficients); the other takes complex64.
+template <int LP, bool F16>
 __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
   constexpr int P = 1 << LP;
   constexpr int B0 = P * kColQ;
   constexpr int LTC = 9 - LP;          // log2 of the columns per item
   constexpr int TC = 1 << LTC;
-  constexpr int LH2 = LP - 5;          // lanes of one outer DFT: H2 = P / 32
+  constexpr int LH2 = LP >= 5 ? LP - 5 : 0;  // lanes of one outer DFT: H2 = P / 32 (1 for P = 16)
   constexpr int H2 = 1 << LH2;
   // E[t][k1][p] with strides such that the writes (lanes along t, then p)
   // and the reads (lanes along h, then k1) of every 32 lanes fall on
   // distinct 8-byte bank pairs
-  constexpr int SK = P + H2;
+  constexpr int SK = P + H2;           // P = 16: 17
   constexpr int ST = 32 * SK + 32 / TC;
   // e^{-2 pi i e / B0}: the whole table for B0 <= 2048, else as
   // e^{-2 pi i (64 a) / B0} e^{-2 pi i b / B0}, e = 64 a + b
@@ -152,7 +155,10 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
   // the open-class list of an item (ahead, in registers), then its rows in
   // four parts of eight, issued at three points of the previous item's work
   // so that the vector-memory queue never holds all of them at once
+  typedef __attribute__((address_space(1))) const unsigned gh;
   gq *fx = nullptr;
+  gh *fxh = nullptr;   // packed FP16 rows (binary16 pairs)
+  float sc_n = 1.0f;   // the next item's scale (packed FP16 form)
   uint32_t foff = 0;
   int64_t frs = 0;
   bool fon = false;
@@ -166,17 +172,29 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
       ln[r] = j < m_n ? (int)c.A.multi_c[0][ds.multi_off + j] : 0;
     }
     const int64_t L = ds.N >> ds.log2B0;
-    fx = (gq *)(c.io ? cst(c.io)[sg].x : c.io1.x) + ((int64_t)(item - pc[sg]) << LTC);
+    const float2 *xs = c.io ? cst(c.io)[sg].x : c.io1.x;
+    const int64_t col0 = (int64_t)(item - pc[sg]) << LTC;
+    if constexpr (F16) {
+      fxh = (gh *)((const char *)xs + SFFT_F16_HEADER_BYTES) + col0;
+      sc_n = *cst((const float *)xs);
+    } else {
+      fx = (gq *)xs + col0;
+    }
     foff = (uint32_t)(p * L + t);  // < B0 L / 32: fits
     frs = (int64_t)P * L;
     fon = true;
   };
   auto fetch_part = [&](int part) {
     if (!fon) return;
+    if constexpr (F16) {
 #pragma unroll
-    for (int q = 8 * part; q < 8 * part + 8; q++) {
-      const unsigned long long u = (fx + q * frs)[foff];
-      xn[q] = make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
+      for (int q = 8 * part; q < 8 * part + 8; q++) xn[q] = half2_to_float2((fxh + q * frs)[foff], 1.0f);
+    } else {
+#pragma unroll
+      for (int q = 8 * part; q < 8 * part + 8; q++) {
+        const unsigned long long u = (fx + q * frs)[foff];
+        xn[q] = make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
+      }
     }
   };
   // the stored outputs of the item held in E
@@ -184,17 +202,20 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
   int m_p = 0;
   int64_t L_p = 0;
   float2 *out_p = nullptr;
+  float sc_p = 1.0f;   // scale of the packed FP16 form (1 for complex64)
   auto store_outputs = [&]() {
     for (int u = tid; u < (m_p << LTC); u += kColThreads) {
       const int j = u >> LTC, tt = u & (TC - 1);
       const int cc = open_c[j];
       const int k2 = cc >> 5;
-      out_p[(int64_t)j * L_p + tt] = E[tt * ST + (cc & 31) * SK + brev_c(k2 >> 5, LH2) + H2 * (k2 & 31)];
+      const float2 e = E[tt * ST + (cc & 31) * SK + brev_c(k2 >> 5, LH2) + H2 * (k2 & 31)];
+      out_p[(int64_t)j * L_p + tt] = F16 ? make_float2(e.x * sc_p, e.y * sc_p) : e;
     }
   };
   int s = 0;
   while (2 * ip0 + hf >= pc[s + 1]) s++;
-  if (cst(c.desc)[s].log2B0 == LP + 5) {
+  auto is_mine = [&](int sg) { return cst(c.desc)[sg].col_key == LP + 5 + (F16 ? 32 : 0); };
+  if (is_mine(s)) {
     fetch(2 * ip0 + hf, s);
     for (int part = 0; part < 4; part++) fetch_part(part);
   }
@@ -202,7 +223,7 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
     const int item = 2 * ip + hf;
     while (item >= pc[s + 1]) s++;
     const __attribute__((address_space(4))) SigDesc &d = cst(c.desc)[s];
-    const bool mine = d.log2B0 == LP + 5;  // other widths: another launch
+    const bool mine = is_mine(s);  // other widths or sample forms: another launch
     float2 v[kColQ];
 #pragma unroll
     for (int q = 0; q < kColQ; q++) v[q] = xn[q];
@@ -210,11 +231,12 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
 #pragma unroll
     for (int r = 0; r < RL; r++) lc[r] = ln[r];
     const int m_s = m_n;
+    const float sc_s = sc_n;
     fon = false;
     if (ip + 1 < ip1) {
       int ns = s;
       while (item + 2 >= pc[ns + 1]) ns++;
-      if (cst(c.desc)[ns].log2B0 == LP + 5) fetch(item + 2, ns);
+      if (is_mine(ns)) fetch(item + 2, ns);
     }
     fetch_part(0);
     fetch_part(1);
@@ -243,7 +265,19 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
     }
     __syncthreads();
     fetch_part(3);
-    {
+    if constexpr (LP == 4) {
+      // two 16-point outer DFTs per thread: k1 = tid mod 16 and k1 + 16, in place
+#pragma unroll
+      for (int half = 0; half < 2; half++) {
+        float2 *row = E + (tid >> 4) * ST + ((tid & 15) + 16 * half) * SK;
+        float2 a[16];
+#pragma unroll
+        for (int pp = 0; pp < 16; pp++) a[pp] = row[pp];
+        dft_reg<4>(a);
+#pragma unroll
+        for (int i = 0; i < 16; i++) row[brev_c(i, 4)] = a[i];
+      }
+    } else {
       float2 *row = E + tr * ST + k1r * SK + h;
       float2 a[32];
 #pragma unroll
@@ -274,6 +308,7 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
     __syncthreads();
     pend = true;
     m_p = m_s;
+    sc_p = sc_s;
     L_p = d.N >> d.log2B0;
     out_p = c.A.jcol + d.jc_off + ((int64_t)(item - pc[s]) << LTC);
   }
@@ -283,10 +318,17 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
 }  // namespace
 
 hipError_t launch_col_pass(const LaunchCtx &c, int grid, hipStream_t s) {
-  if (c.col_lp_mask & 1) hipLaunchKernelGGL(k_col_pass<5>, dim3(grid), dim3(kColThreads), 0, s, c);
-  if (c.col_lp_mask & 2) hipLaunchKernelGGL(k_col_pass<6>, dim3(grid), dim3(kColThreads), 0, s, c);
-  if (c.col_lp_mask & 4) hipLaunchKernelGGL(k_col_pass<7>, dim3(grid), dim3(kColThreads), 0, s, c);
-  if (c.col_lp_mask & 8) hipLaunchKernelGGL(k_col_pass<8>, dim3(grid), dim3(kColThreads), 0, s, c);
+  const dim3 g(grid), b(kColThreads);
+  if (c.col_lp_mask & 1) hipLaunchKernelGGL((k_col_pass<4, false>), g, b, 0, s, c);
+  if (c.col_lp_mask & 2) hipLaunchKernelGGL((k_col_pass<5, false>), g, b, 0, s, c);
+  if (c.col_lp_mask & 4) hipLaunchKernelGGL((k_col_pass<6, false>), g, b, 0, s, c);
+  if (c.col_lp_mask & 8) hipLaunchKernelGGL((k_col_pass<7, false>), g, b, 0, s, c);
+  if (c.col_lp_mask & 16) hipLaunchKernelGGL((k_col_pass<8, false>), g, b, 0, s, c);
+  if (c.col_f16_mask & 1) hipLaunchKernelGGL((k_col_pass<4, true>), g, b, 0, s, c);
+  if (c.col_f16_mask & 2) hipLaunchKernelGGL((k_col_pass<5, true>), g, b, 0, s, c);
+  if (c.col_f16_mask & 4) hipLaunchKernelGGL((k_col_pass<6, true>), g, b, 0, s, c);
+  if (c.col_f16_mask & 8) hipLaunchKernelGGL((k_col_pass<7, true>), g, b, 0, s, c);
+  if (c.col_f16_mask & 16) hipLaunchKernelGGL((k_col_pass<8, true>), g, b, 0, s, c);
   return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ __device__ __forceinline__ void col_sum(const float2 *M, uint64_t Ld, int u0, in
 // whole wave shares each sum.  Depth by depth the open subclasses are then
 // classified as the tree search does (Sect. 3.3), one lane each:
 // single-tons (and two-tons) are recorded, multi-tons open their children.
-template <int NMAX, bool F32>
+template <int NMAX, bool F32, bool WAVE>
 __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
   constexpr int GS = kColGroup, LGS = kColGroupLg, CPW = 64 / GS, CAP = kColResolveCap;
   __shared__ double2 Ys[CPW][GS][NMAX];
@@ -132,32 +132,36 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
           }
         }
         __syncthreads();
-        if (gl < no) {
-          const int k = open_cur[g][ch * GS + gl];
+        {
+          // every lane takes part (the noisy enumeration is shared by the wave)
+          const bool act = gl < no;
+          const int k = act ? open_cur[g][ch * GS + gl] : 0;
           const int64_t cs = (int64_t)cpar + (int64_t)k * d.B0;
           double2 Y[NMAX];
 #pragma unroll
-          for (int i = 0; i < NMAX; i++) Y[i] = i < n ? Ys[g][gl][i] : make_double2(0.0, 0.0);
-          const Decision v = classify<NMAX, true, F32>(Y, d, n, d.R, cs, Bd, sref2, nv);
-          atomicMax(&c.st[s].levels, dd);
-          if (v.cls == kSingle) {
-            const int fs = atomicAdd(&c.st[s].found, 1);
-            push_found(c, s, d, fs, v.f, v.a);
-          } else if (v.cls == kDouble) {
-            const int fs = atomicAdd(&c.st[s].found, 2);
-            push_found(c, s, d, fs, v.f, v.a);
-            push_found(c, s, d, fs + 1, v.f2, v.a2);
-          } else if (v.cls == kMulti) {
-            if (Ld >= 2 && dd + 1 <= d.max_levels) {
-              const int at = atomicAdd(&n_nxt[g], 2);
-              if (at + 2 <= CAP) {
-                open_nxt[g][at] = k;
-                open_nxt[g][at + 1] = k + nq;
+          for (int i = 0; i < NMAX; i++) Y[i] = act && i < n ? Ys[g][gl][i] : make_double2(0.0, 0.0);
+          const Decision v = classify<NMAX, true, F32, WAVE>(Y, d, n, d.R, cs, Bd, sref2, nv, act);
+          if (act) {
+            atomicMax(&c.st[s].levels, dd);
+            if (v.cls == kSingle) {
+              const int fs = atomicAdd(&c.st[s].found, 1);
+              push_found(c, s, d, fs, v.f, v.a);
+            } else if (v.cls == kDouble) {
+              const int fs = atomicAdd(&c.st[s].found, 2);
+              push_found(c, s, d, fs, v.f, v.a);
+              push_found(c, s, d, fs + 1, v.f2, v.a2);
+            } else if (v.cls == kMulti) {
+              if (Ld >= 2 && dd + 1 <= d.max_levels) {
+                const int at = atomicAdd(&n_nxt[g], 2);
+                if (at + 2 <= CAP) {
+                  open_nxt[g][at] = k;
+                  open_nxt[g][at + 1] = k + nq;
+                } else {
+                  atomicOr(&c.st[s].flags, 1);
+                }
               } else {
                 atomicOr(&c.st[s].flags, 1);
               }
-            } else {
-              atomicOr(&c.st[s].flags, 1);
             }
           }
         }
@@ -174,16 +178,7 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
 }  // namespace
 
 hipError_t launch_col_resolve(const LaunchCtx &c, int grid, hipStream_t s) {
-  const int nm = nmax_bucket(c.nmax);
-  if (c.any_fp32) {
-    if (nm == 8) hipLaunchKernelGGL((k_col_resolve<8, true>), dim3(grid), dim3(64), 0, s, c);
-    else if (nm == 16) hipLaunchKernelGGL((k_col_resolve<16, true>), dim3(grid), dim3(64), 0, s, c);
-    else hipLaunchKernelGGL((k_col_resolve<64, true>), dim3(grid), dim3(64), 0, s, c);
-  } else {
-    if (nm == 8) hipLaunchKernelGGL((k_col_resolve<8, false>), dim3(grid), dim3(64), 0, s, c);
-    else if (nm == 16) hipLaunchKernelGGL((k_col_resolve<16, false>), dim3(grid), dim3(64), 0, s, c);
-    else hipLaunchKernelGGL((k_col_resolve<64, false>), dim3(grid), dim3(64), 0, s, c);
-  }
+  SFFT_LAUNCH_CLASSIFIER(k_col_resolve, c, dim3(grid), dim3(64), 0, s, c);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@
 // filter (bin sigma c of the permuted transform is bin c of the natural one),
 // so class c is read directly at bin c and sigma never touches the gather.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
 #include "sfft_internal.h"
@@ -51,6 +52,40 @@ __device__ __forceinline__ float2 ldg_at(gu64 *base, uint64_t i) {
   return make_float2(__uint_as_float((unsigned)v), __uint_as_float((unsigned)(v >> 32)));
 }
 __device__ __forceinline__ float2 ldg(const float2 *p) { return ldg_at((gu64 *)p, 0); }
+
+// The signal of one solve as its kernels read it: complex64 samples, or the
+// packed FP16 form (a header whose first float is the scale s, then pairs of
+// binary16; sample n = s (re + i im)).  The branch on the form is uniform
+// over a work-group.
+struct SigSrc {
+  const void *p;  // sample 0
+  float scale;    // 1 for complex64
+  int fp16;
+};
+__device__ __forceinline__ SigSrc sig_src(const float2 *x, const SigDesc &d) {
+  SigSrc r;
+  if (d.fp16) {
+    r.p = (const char *)x + SFFT_F16_HEADER_BYTES;
+    r.scale = *(const float *)x;
+    r.fp16 = 1;
+  } else {
+    r.p = x;
+    r.scale = 1.0f;
+    r.fp16 = 0;
+  }
+  return r;
+}
+typedef __attribute__((address_space(1))) const unsigned gu32;
+// binary16 pair (re in the low half) to complex64, times s
+__device__ __forceinline__ float2 half2_to_float2(unsigned v, float s) {
+  const float re = __half2float(__ushort_as_half((unsigned short)(v & 0xffffu)));
+  const float im = __half2float(__ushort_as_half((unsigned short)(v >> 16)));
+  return make_float2(re * s, im * s);
+}
+__device__ __forceinline__ float2 load_sample(const SigSrc &src, uint64_t i) {
+  if (src.fp16) return half2_to_float2(((gu32 *)src.p)[i], src.scale);
+  return ldg_at((gu64 *)src.p, i);
+}
 
 // acc += a * b (complex, two FMAs per component)
 __device__ __forceinline__ void cmac(float2 &acc, float2 a, float2 b) {
@@ -137,10 +172,9 @@ __device__ void fft_lds(float2 *X, int lg, const float2 *__restrict__ tw) {
 // All D delays of a sample are read in the same batch of loads (adjacent
 // addresses, one cache-line fill): plane dl of lds receives, in bit-reversed
 // order, x[((m P + p) L + tau0 + dl) & mask] for m < Bs = 2^lg.
-__device__ __forceinline__ void gather_delays(float2 *lds, const float2 *__restrict__ x, int64_t Bs,
+__device__ __forceinline__ void gather_delays(float2 *lds, const SigSrc &src, int64_t Bs,
                                               int lg, uint64_t L, uint64_t P, uint64_t p,
                                               uint64_t tau0, uint64_t mask, int D) {
-  gu64 *xg = (gu64 *)x;
   for (int64_t m0 = threadIdx.x; m0 < Bs; m0 += 4 * (int64_t)blockDim.x) {
     float2 v[4][kMaxD];
 #pragma unroll
@@ -150,7 +184,7 @@ __device__ __forceinline__ void gather_delays(float2 *lds, const float2 *__restr
       const uint64_t base = (mc * P + p) * L + tau0;
 #pragma unroll
       for (int dl = 0; dl < kMaxD; dl++)
-        v[u][dl] = dl < D ? ldg_at(xg, (base + (uint64_t)dl) & mask) : make_float2(0.f, 0.f);
+        v[u][dl] = dl < D ? load_sample(src, (base + (uint64_t)dl) & mask) : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int u = 0; u < 4; u++) {
@@ -397,15 +431,108 @@ __device__ __forceinline__ void two_ton(const double2 (&Y)[NMAX], const SigDesc 
   v.a2 = a1;
 }
 
+// One block of the noisy-mode enumeration (Sect. 3.1, Method 2): the
+// matched filter |sum_i Y_i e^{-2 pi i (c + kB) tau_i / N}| of the
+// candidates k = lo + o0 + o (mod L), o < min(32, cnt - o0), in FP32 MACs
+// with the twiddles anchored exactly at the block's first candidate; folds
+// them into (best, bestk): the largest statistic, ties to the smaller k.
+template <int NMAX, bool TREE>
+__device__ __forceinline__ void enum_block(const float2 (&Yf)[NMAX], const SigDesc &d, int n, int64_t c,
+                                           int64_t B, int64_t L, int64_t lo, int64_t cnt, int64_t o0,
+                                           float &best, int64_t &bestk) {
+  const uint64_t N = (uint64_t)d.N;
+  float2 tw[NMAX], st[NMAX];
+  const int64_t k0 = ((lo + o0) % L + L) % L;
+  const uint64_t f0 = (uint64_t)(c + k0 * B);
+#pragma unroll
+  for (int i = 0; i < NMAX; i++) {
+    if (i < n) {
+      const uint64_t ti = tau_of<TREE>(d, i);
+      const double2 a = unit_d(mod_n(f0 * ti, d), N, -1);
+      const double2 b = unit_d(mod_n(mod_n((uint64_t)B * ti, d), d), N, -1);
+      tw[i] = make_float2((float)a.x, (float)a.y);
+      st[i] = make_float2((float)b.x, (float)b.y);
+    }
+  }
+  const int64_t lim = (cnt - o0) < 32 ? (cnt - o0) : 32;
+  for (int64_t o = 0; o < lim; o++) {
+    float gx = 0.f, gy = 0.f;
+#pragma unroll
+    for (int i = 0; i < NMAX; i++) {
+      if (i < n) {
+        gx += Yf[i].x * tw[i].x - Yf[i].y * tw[i].y;
+        gy += Yf[i].x * tw[i].y + Yf[i].y * tw[i].x;
+        tw[i] = cmulf(tw[i], st[i]);
+      }
+    }
+    const float m2 = gx * gx + gy * gy;
+    int64_t kk = k0 + o;
+    if (kk >= L) kk -= L;
+    if (m2 > best || (m2 == best && kk < bestk)) {
+      best = m2;
+      bestk = kk;
+    }
+  }
+}
+
+// The enumeration of every lane whose `need` is set, by all the lanes that
+// execute the call: lane j's class vector and candidate range are broadcast,
+// the active lanes take its 32-candidate blocks in turn (the blocks and
+// anchors of the one-lane loop, so every statistic is the same number), and
+// the best candidate is reduced over the lanes.  Each needing lane gets its
+// own k; every lane of the wave must reach the call together with the others
+// of its group (all lanes of the wave in the tree kernels).
+template <int NMAX, bool TREE>
+__device__ int64_t enum_wave(bool need, const float2 (&Yf)[NMAX], const SigDesc *dp, int n, int64_t c,
+                             int64_t B, int64_t lo, int64_t cnt) {
+  const unsigned long long act = __ballot(1);
+  unsigned long long mask = __ballot(need);
+  const int lane = __lane_id();
+  const int rank = (int)__popcll(act & ((1ull << lane) - 1ull)), nact = (int)__popcll(act);
+  int64_t result = 0;
+  while (mask) {
+    const int j = __ffsll((long long)mask) - 1;
+    mask &= mask - 1ull;
+    const SigDesc &dj = *(const SigDesc *)__shfl((unsigned long long)dp, j);
+    const int nj = __shfl(n, j);
+    const int64_t cj = __shfl((long long)c, j), Bj = __shfl((long long)B, j);
+    const int64_t loj = __shfl((long long)lo, j), cntj = __shfl((long long)cnt, j);
+    float2 Yj[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; i++) Yj[i] = make_float2(__shfl(Yf[i].x, j), __shfl(Yf[i].y, j));
+    const int64_t L = dj.N / Bj;
+    float best = -1.0f;
+    int64_t bestk = 0;
+    const int64_t nblk = (cntj + 31) >> 5;
+    for (int64_t b = rank; b < nblk; b += nact) enum_block<NMAX, TREE>(Yj, dj, nj, cj, Bj, L, loj, cntj, b << 5, best, bestk);
+    // largest statistic, ties to the smaller k, over the active lanes
+    unsigned long long rest = act;
+    float wb = -1.0f;
+    int64_t wk = 0;
+    while (rest) {
+      const int l = __ffsll((long long)rest) - 1;
+      rest &= rest - 1ull;
+      const float ob = __shfl(best, l);
+      const int64_t ok = __shfl((long long)bestk, l);
+      if (ob > wb || (ob == wb && ok < wk)) {
+        wb = ob;
+        wk = ok;
+      }
+    }
+    if (lane == j) result = wk;
+  }
+  return result;
+}
+
 // Singleton test (Sect. 3.2, Subproblems 1-2) of one class vector Y (n values,
 // rounds x D layout) of class c among B buckets.
 // TREE: the two-ton solve may follow (tree kernels); otherwise the R-FFAST
 // estimator may locate (FFAST kernel) -- each kernel compiles only its own.
 // F32: the single-precision variant of locate / value / residual is compiled
 // in (batches holding a plan that asks for it).
-template <int NMAX, bool TREE = true, bool F32 = false>
+template <int NMAX, bool TREE = true, bool F32 = false, bool WAVE = false>
 __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, int rounds,
-                            int64_t c, int64_t B, double sref2, double noise_var) {
+                            int64_t c, int64_t B, double sref2, double noise_var, bool active = true) {
   Decision v;
   v.cls = kZero;
   v.f = -1;
@@ -428,12 +555,16 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
     T0sq = sb2 * ((double)n + d.zero_k * sqrt((double)n));
     T1sq = sb2 * ((double)(n - 1) + d.single_k * sqrt((double)(n - 1)));
   }
-  if (E2 <= T0sq) return v;
+  // WAVE: every lane of the wave runs to the enumeration below (which the
+  // lanes share), whether its class is active and past the zero-ton test or not
+  const bool go = active && !(E2 <= T0sq);
+  if (!WAVE && !go) return v;
 
   // phase-to-index (exact-case locator, advance-shift sign)
   int64_t ksnap = 0;
   const bool rffast = !TREE && d.rf_iters > 0;
-  if (rffast) {
+  if (!go) {
+  } else if (rffast) {
     // R-FFAST estimator: iteration c estimates the angle of e^{2 pi i 2^c f / N}
     // by Kay's weighted phase differences of its m delays (Eq. 21-22) and
     // keeps the lower half of the interval holding f when it lies in [0, pi)
@@ -491,7 +622,8 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
     ksnap = lattice_k(atan2(P.y, P.x), N, B, c);
   }
   int64_t k = ksnap;
-  if (d.mode == SFFT_NOISY && !rffast) {
+  const bool enumerate = d.mode == SFFT_NOISY && !rffast;
+  if (WAVE || (go && enumerate)) {
     // enumeration of the candidates c + kB (Sect. 3.1, Method 2) by the
     // matched filter |sum_i Y_i e^{-2 pi i (c + kB) tau_i / N}|, FP32 MACs,
     // twiddles re-anchored exactly every 32 candidates
@@ -503,46 +635,29 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
       lo = 0;
       cnt = L;
     }
-    float2 Yf[NMAX], tw[NMAX], st[NMAX];
+    float2 Yf[NMAX];
 #pragma unroll
     for (int i = 0; i < NMAX; i++) Yf[i] = make_float2((float)Y[i].x, (float)Y[i].y);
-    float best = -1.0f;
-    int64_t bestk = 0;
-    for (int64_t o0 = 0; o0 < cnt; o0 += 32) {
-      const int64_t k0 = ((lo + o0) % L + L) % L;
-      const uint64_t f0 = (uint64_t)(c + k0 * B);
-#pragma unroll
-      for (int i = 0; i < NMAX; i++) {
-        if (i < n) {
-          const uint64_t ti = tau_of<TREE>(d, i);
-          const double2 a = unit_d(mod_n(f0 * ti, d), (uint64_t)N, -1);
-          const double2 b = unit_d(mod_n(mod_n((uint64_t)B * ti, d), d), (uint64_t)N, -1);
-          tw[i] = make_float2((float)a.x, (float)a.y);
-          st[i] = make_float2((float)b.x, (float)b.y);
-        }
+    if (WAVE) {
+      // ranges of up to kEnumLaneBlocks blocks stay with their lane (those lanes
+      // run side by side); longer ones are shared by the whole wave, one by one
+      const bool coop = go && enumerate && ((cnt + 31) >> 5) > kEnumLaneBlocks;
+      if (go && enumerate && !coop) {
+        float best = -1.0f;
+        int64_t bestk = 0;
+        for (int64_t o0 = 0; o0 < cnt; o0 += 32) enum_block<NMAX, TREE>(Yf, d, n, c, B, L, lo, cnt, o0, best, bestk);
+        k = bestk;
       }
-      const int64_t lim = (cnt - o0) < 32 ? (cnt - o0) : 32;
-      for (int64_t o = 0; o < lim; o++) {
-        float gx = 0.f, gy = 0.f;
-#pragma unroll
-        for (int i = 0; i < NMAX; i++) {
-          if (i < n) {
-            gx += Yf[i].x * tw[i].x - Yf[i].y * tw[i].y;
-            gy += Yf[i].x * tw[i].y + Yf[i].y * tw[i].x;
-            tw[i] = cmulf(tw[i], st[i]);
-          }
-        }
-        const float m2 = gx * gx + gy * gy;
-        int64_t kk = k0 + o;
-        if (kk >= L) kk -= L;
-        if (m2 > best || (m2 == best && kk < bestk)) {
-          best = m2;
-          bestk = kk;
-        }
-      }
+      const int64_t kw = enum_wave<NMAX, TREE>(coop, Yf, &d, n, c, B, lo, cnt);
+      if (coop) k = kw;
+    } else {
+      float best = -1.0f;
+      int64_t bestk = 0;
+      for (int64_t o0 = 0; o0 < cnt; o0 += 32) enum_block<NMAX, TREE>(Yf, d, n, c, B, L, lo, cnt, o0, best, bestk);
+      k = bestk;
     }
-    k = bestk;
   }
+  if (!go) return v;
   const int64_t f = c + k * B;
   if (F32 && d.precision == 1) {
     // FP32 variant: value and residual in single precision, FP32 twiddles
@@ -619,6 +734,25 @@ __device__ __forceinline__ void push_found(const LaunchCtx &c, int s, const SigD
 
 // signal-set template bucket: n = R*D measurements per class vector
 __host__ __device__ inline int nmax_bucket(int n) { return n <= 8 ? 8 : (n <= 16 ? 16 : 64); }
+
+// Launch a classifying kernel KERNEL<NMAX, F32, WAVE> for the batch in c: its
+// class-vector size, whether a signal decides in FP32, whether a signal is in
+// noisy mode (the wave-shared enumeration is compiled into those instances only).
+#define SFFT_LAUNCH_FW_(KERNEL, NM, f_, w_, ...)                                  \
+  do {                                                                            \
+    if (f_ && w_) hipLaunchKernelGGL((KERNEL<NM, true, true>), __VA_ARGS__);      \
+    else if (f_) hipLaunchKernelGGL((KERNEL<NM, true, false>), __VA_ARGS__);      \
+    else if (w_) hipLaunchKernelGGL((KERNEL<NM, false, true>), __VA_ARGS__);      \
+    else hipLaunchKernelGGL((KERNEL<NM, false, false>), __VA_ARGS__);             \
+  } while (0)
+#define SFFT_LAUNCH_CLASSIFIER(KERNEL, c, ...)                                    \
+  do {                                                                            \
+    const int nm_ = nmax_bucket((c).nmax);                                        \
+    const bool f_ = (c).any_fp32 != 0, w_ = (c).any_noisy != 0;                   \
+    if (nm_ == 8) SFFT_LAUNCH_FW_(KERNEL, 8, f_, w_, __VA_ARGS__);                \
+    else if (nm_ == 16) SFFT_LAUNCH_FW_(KERNEL, 16, f_, w_, __VA_ARGS__);         \
+    else SFFT_LAUNCH_FW_(KERNEL, 64, f_, w_, __VA_ARGS__);                        \
+  } while (0)
 
 }  // namespace
 

@@ -175,6 +175,8 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     d.jump_L = (in.kind == SFFT_KIND_TREE && !no_jump && !d.l1) ? in.jump_L : 0;
     d.mpp = in.mpp;
     d.precision = in.precision;
+    d.fp16 = in.kind == SFFT_KIND_TREE && in.sample_format == SFFT_SAMPLES_F16 ? 1 : 0;
+    d.col_key = -1;
     d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
     d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
     d.rf_m = in.rf_m;
@@ -195,6 +197,7 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     d.multi_off = mc;
     d.fst_off = fst;
     d.jc_off = jc;
+    if (d.l1) d.col_key = d.log2B0 + 32 * d.fp16;
     if (in.kind == SFFT_KIND_TREE) {
       y0 += (int64_t)d.n * in.B0;
       mc += d.multi_cap;
@@ -250,7 +253,14 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
   for (int s = 0; s < nsig; s++) {
     const SigDesc &d = Y.desc[s];
     if (d.kind == SFFT_KIND_TREE && d.precision == 1) Y.any_fp32 = 1;
-    if (d.l1) Y.col_lp_mask |= 1 << (d.log2B0 - 10);  // bit LP - 5, B0 = 2^(LP + 5)
+    if (d.l1) (d.fp16 ? Y.col_f16_mask : Y.col_lp_mask) |= 1 << (d.log2B0 - 9);  // bit LP - 4, B0 = 2^(LP + 5)
+    // the wave-shared enumeration is compiled in only where some noisy class has
+    // a candidate range longer than one lane keeps (level 0 has the longest)
+    if (d.kind == SFFT_KIND_TREE && d.mode == SFFT_NOISY) {
+      const int64_t L0 = d.N >> d.log2B0;
+      const int64_t cnt = (d.window > 0 && d.D >= 2 && 2 * (int64_t)d.window + 1 < L0) ? 2 * (int64_t)d.window + 1 : L0;
+      if (((cnt + 31) >> 5) > kEnumLaneBlocks) Y.any_noisy = 1;
+    }
     if (d.kind == SFFT_KIND_TREE && d.jump_L >= (1 << kJumpMfmaMinLg)) Y.any_wide_jump = 1;
   }
   // arenas
@@ -373,6 +383,8 @@ void bind_layout(const Layout &Y, char *base, const float2 *tw, LaunchCtx &c) {
   c.jrows = Y.jrows;
   c.any_fp32 = Y.any_fp32;
   c.col_lp_mask = Y.col_lp_mask;
+  c.col_f16_mask = Y.col_f16_mask;
+  c.any_noisy = Y.any_noisy;
   c.any_wide_jump = Y.any_wide_jump;
   c.nsig = (int32_t)Y.desc.size();
   c.ntree = Y.ntree;
@@ -552,6 +564,8 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
   if (p.precision != 0 && p.precision != 1) return SFFT_EINVAL;
   in.precision = p.precision;
   if (p.l1_resolve != 0 && p.l1_resolve != 1) return SFFT_EINVAL;
+  if (p.sample_format != SFFT_SAMPLES_C64 && p.sample_format != SFFT_SAMPLES_F16) return SFFT_EINVAL;
+  in.sample_format = p.sample_format;
   in.found_cap = (int32_t)std::max<int64_t>(64, npow2(2 * p.K));
   in.multi_cap = (int32_t)std::max<int64_t>(64, p.K);
   memset(pl->stage_off, 0, sizeof(pl->stage_off));
@@ -576,7 +590,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     in.max_levels = (p.max_levels < 0 || p.max_levels > full) ? full : p.max_levels;
     // level-1 column pass: B0 = P x 32 with P in {32, 64, 128}, and an even
     // number of column blocks of 512 / P columns
-    in.l1_resolve = p.l1_resolve && (B0 == 1024 || B0 == 2048 || B0 == 4096 || B0 == 8192) &&
+    in.l1_resolve = p.l1_resolve && (B0 == 512 || B0 == 1024 || B0 == 2048 || B0 == 4096 || B0 == 8192) &&
                     p.N / B0 >= 32768 / B0 && in.max_levels >= 1;
     SplitMix64 g{p.seed};
     for (int r = 0; r < p.stages; r++) {
@@ -621,7 +635,7 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
       if ((int)st.size() != p.stages) return SFFT_EUNSUPPORTED;
     }
     if ((int)st.size() > SFFT_MAX_STAGES) return SFFT_EUNSUPPORTED;
-    if (p.mpp != 0 || p.precision != 0) return SFFT_EUNSUPPORTED;
+    if (p.mpp != 0 || p.precision != 0 || p.sample_format != SFFT_SAMPLES_C64) return SFFT_EUNSUPPORTED;
     SplitMix64 g{p.seed};
     in.rf_iters = p.rf_iters;
     in.rf_m = p.rf_iters ? p.rf_m : 0;
@@ -1159,6 +1173,7 @@ int64_t sfft_exec_host(sfft_plan_t plan, const void *x, int64_t *out_idx, void *
                        sfft_stats_t *stats) {
   if (!plan || !x || !out_idx || !out_val) return fail(SFFT_EINVAL);
   if (is_device_ptr(x) || is_device_ptr(out_idx) || is_device_ptr(out_val)) return fail(SFFT_EINVAL);
+  if (plan->info.sample_format != SFFT_SAMPLES_C64) return fail(SFFT_EUNSUPPORTED);
   int32_t rc;
   HostCtx *h = host_ctx(plan, &rc);
   if (!h) return fail(rc);

@@ -32,6 +32,8 @@ constexpr int kColResolveCap = 128;  // open subclasses per depth of one class
 constexpr int kColGroupLg = 3;      // column resolve: 2^3 lanes per class
 constexpr int kColGroup = 1 << kColGroupLg;
 constexpr int kColLaneDepth = 5;    // ... one lane per class-vector sum down to this depth
+constexpr int kEnumLaneBlocks = 64; // noisy enumeration: ranges of up to 64 x 32 candidates stay
+                                    // with their lane; longer ones are shared by the wave
 constexpr size_t kNoAllocScratchBytes = (size_t)SFFT_NOALLOC_SCRATCH_MIB << 20;
 constexpr size_t kNoAllocTwBytes = 64 * 1024;  // twiddle table at the scratch's start
 
@@ -53,6 +55,8 @@ struct SigDesc {
   int32_t l1;             // level-0 multi-tons resolved at level 1 from the column pass
   int32_t mpp;            // 2: two-ton moment preserving solve of multi-tons
   int32_t precision;      // 0: locate / value / residual in FP64; 1: in FP32
+  int32_t fp16;           // 1: x is the packed FP16 form (header with the scale, binary16 pairs)
+  int32_t col_key;        // column-pass signals: log2 B0 + 32 fp16 (the instance that takes it)
   int32_t rf_iters, rf_m; // FFAST R-FFAST delay set r_c + 2^c t (rf_iters = 0: delays 0..D-1)
   uint64_t rf_off[SFFT_MAX_ROUNDS];
   int32_t n_starts;       // FFAST packet-erasure schedule: start frequencies (0: method 1)
@@ -133,7 +137,10 @@ struct LaunchCtx {
   int32_t jstride;         // dense-pass coefficients per multi-ton slot (kJumpMax)
   int32_t jrows;           // rows per dense-pass work item (power of two)
   int32_t any_fp32;        // some tree signal classifies in single precision
-  int32_t col_lp_mask;     // bit LP - 5 set when a signal with B0 = 2^(LP+5) takes the column pass
+  int32_t col_lp_mask;     // bit LP - 4 set when a signal with B0 = 2^(LP+5) takes the column pass
+  int32_t col_f16_mask;    // ... for signals stored in the packed FP16 form
+  int32_t any_noisy;       // some noisy tree signal has candidate ranges longer than
+                           // kEnumLaneBlocks blocks (wave-shared enumeration compiled in)
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;

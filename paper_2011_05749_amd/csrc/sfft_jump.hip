@@ -16,7 +16,7 @@ namespace {
 // and row) and each element costs one complex multiply-add per class.
 // Item = (signal, c.jrows rows); thread tid owns t = tid mod L'.
 template <int NQ>
-__device__ __forceinline__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const float2 *__restrict__ x,
+__device__ __forceinline__ void jump_rows(const LaunchCtx &c, const SigDesc &d, const SigSrc &src,
                           int64_t row0, int nrows, int lgL, uint64_t Bp, const uint64_t *cls,
                           float2 *T, float2 (*red)[64], int64_t slot0) {
   const int Lp = 1 << lgL;
@@ -31,14 +31,13 @@ __device__ __forceinline__ void jump_rows(const LaunchCtx &c, const SigDesc &d, 
     }
     __syncthreads();
     const int ne = nb << lgL;
-    const float2 *xb = x + ((row0 + b0) << lgL);
-    gu64 *xg = (gu64 *)xb;
+    const uint64_t xb = (uint64_t)(row0 + b0) << lgL;
     for (int e0 = threadIdx.x; e0 < ne; e0 += 8 * kThreads) {
       float2 v[8];
 #pragma unroll
       for (int u = 0; u < 8; u++) {
         const int e = e0 + u * kThreads;
-        v[u] = ldg_at(xg, (uint64_t)(e < ne ? e : ne - 1));   // rows past nb are skipped below
+        v[u] = load_sample(src, xb + (uint64_t)(e < ne ? e : ne - 1));   // rows past nb are skipped below
       }
       // one row's twiddles live at a time: the scheduling barrier keeps the
       // compiler from hoisting every row's LDS reads (register pressure)
@@ -99,7 +98,7 @@ __device__ __forceinline__ void jump_rows(const LaunchCtx &c, const SigDesc &d, 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 template <int NT>
-__device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const float2 *__restrict__ x, int64_t row0,
+__device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const SigSrc &src, int64_t row0,
                                int nrows, uint64_t Bp, const uint64_t *cls /* LDS */, int nq,
                                float2 *tile /* LDS, 2 x 32 KiB */, float *red /* aliases tile */,
                                int64_t slot0) {
@@ -121,7 +120,8 @@ __device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const float2 
   // in flight while the MFMAs of tile t run
   typedef float f32x4 __attribute__((ext_vector_type(4)));
   typedef __attribute__((address_space(1))) const f32x4 gf4;
-  gf4 *xv = (gf4 *)x;
+  gf4 *xv = (gf4 *)src.p;
+  gu64 *xh = (gu64 *)src.p;  // packed FP16: two samples per 8 bytes
   const int ntiles = (nrows + TR - 1) / TR;
   f32x4 pre[PV];
   auto fetch = [&](int t) {
@@ -131,7 +131,17 @@ __device__ __forceinline__ void jump_rows_mfma(const LaunchCtx &c, const float2 
     for (int u = 0; u < PV; u++) {
       int64_t i = threadIdx.x + (int64_t)u * kThreads;
       if (i >= lim) i = lim - 1;  // rows past the item: an in-bounds re-read, never used
-      pre[u] = xv[base + i];
+      if (src.fp16) {
+        const unsigned long long w = xh[base + i];
+        const float2 a = half2_to_float2((unsigned)w, src.scale);
+        const float2 b = half2_to_float2((unsigned)(w >> 32), src.scale);
+        pre[u][0] = a.x;
+        pre[u][1] = a.y;
+        pre[u][2] = b.x;
+        pre[u][3] = b.y;
+      } else {
+        pre[u] = xv[base + i];
+      }
     }
   };
   auto stash = [&](int buf) {
@@ -213,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
     // matrix cores); the VALU kernel every narrower width
     constexpr int kLg = NT == 1 ? 5 : (NT == 2 ? 6 : 7);
     if (MFMA ? (lgL != kLg || lgL < kJumpMfmaMinLg) : (lgL >= kJumpMfmaMinLg)) continue;
-    const float2 *__restrict__ x = io_of(c, s).x;
+    const SigSrc src = sig_src(io_of(c, s).x, d);
     const uint64_t Bp = (uint64_t)1 << lb;
     int m_s = c.st[s].multi[par];
     if (m_s > d.multi_cap) m_s = d.multi_cap;
@@ -228,26 +238,26 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
       __syncthreads();
       const int64_t slot0 = d.multi_off + j0;
       if constexpr (MFMA) {
-        jump_rows_mfma<(NT > 0 ? NT : 1)>(c, x, row0, nrows, Bp, cls, nq, T, (float *)T, slot0);
+        jump_rows_mfma<(NT > 0 ? NT : 1)>(c, src, row0, nrows, Bp, cls, nq, T, (float *)T, slot0);
       } else {
         float2 (*redv)[64] = (float2 (*)[64])(T + 4096);
         switch (nq) {
-          case 1: jump_rows<1>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 2: jump_rows<2>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 3: jump_rows<3>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 4: jump_rows<4>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 5: jump_rows<5>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 6: jump_rows<6>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 7: jump_rows<7>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 8: jump_rows<8>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 9: jump_rows<9>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 10: jump_rows<10>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 11: jump_rows<11>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 12: jump_rows<12>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 13: jump_rows<13>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 14: jump_rows<14>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          case 15: jump_rows<15>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
-          default: jump_rows<16>(c, d, x, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 1: jump_rows<1>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 2: jump_rows<2>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 3: jump_rows<3>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 4: jump_rows<4>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 5: jump_rows<5>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 6: jump_rows<6>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 7: jump_rows<7>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 8: jump_rows<8>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 9: jump_rows<9>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 10: jump_rows<10>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 11: jump_rows<11>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 12: jump_rows<12>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 13: jump_rows<13>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 14: jump_rows<14>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          case 15: jump_rows<15>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
+          default: jump_rows<16>(c, d, src, row0, nrows, lgL, Bp, cls, T, redv, slot0); break;
         }
       }
     }
@@ -262,7 +272,7 @@ __global__ __launch_bounds__(kThreads) void k_jump_pass(LaunchCtx c, int level) 
 // xhat_f e^{2 pi i f tau_i / N} -- the same linear functional of x as the
 // level's gathered buckets -- so the level-by-level classification of the
 // tree search (Sect. 3.3) runs on these vectors.
-template <int NMAX, bool F32>
+template <int NMAX, bool F32, bool WAVE>
 __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int level) {
   __shared__ double2 V[kJumpMax][NMAX];
   __shared__ double2 Ms[kJumpMax];
@@ -317,34 +327,38 @@ __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int leve
       if (k < kJumpMax) open_nxt[k] = 0;
       if (k == 0) any_open = 0;
       __syncthreads();
-      if (k < nq && open_cur[k]) {
+      {
+        // every thread takes part (the noisy enumeration is shared by the wave)
+        const bool act = k < nq && open_cur[k];
         double2 Y[NMAX];
 #pragma unroll
         for (int i = 0; i < NMAX; i++) {
           Y[i] = make_double2(0.0, 0.0);
-          if (i < n)
+          if (act && i < n)
             for (int kk = k; kk < Lp; kk += nq) {
               Y[i].x += V[kk][i].x;
               Y[i].y += V[kk][i].y;
             }
         }
         const int64_t cc = cpar + (int64_t)k * Bp;
-        const Decision v = classify<NMAX, true, F32>(Y, d, n, d.R, cc, Bd, sref2, nv);
-        atomicMax(&c.st[s].levels, lvl);
-        if (v.cls == kSingle) {
-          const int fs = atomicAdd(&c.st[s].found, 1);
-          push_found(c, s, d, fs, v.f, v.a);
-        } else if (v.cls == kDouble) {
-          const int fs = atomicAdd(&c.st[s].found, 2);
-          push_found(c, s, d, fs, v.f, v.a);
-          push_found(c, s, d, fs + 1, v.f2, v.a2);
-        } else if (v.cls == kMulti) {
-          if (Ld >= 2 && lvl + 1 <= d.max_levels) {
-            open_nxt[k] = 1;
-            open_nxt[k + nq] = 1;
-            any_open = 1;
-          } else {
-            atomicOr(&c.st[s].flags, 1);
+        const Decision v = classify<NMAX, true, F32, WAVE>(Y, d, n, d.R, cc, Bd, sref2, nv, act);
+        if (act) {
+          atomicMax(&c.st[s].levels, lvl);
+          if (v.cls == kSingle) {
+            const int fs = atomicAdd(&c.st[s].found, 1);
+            push_found(c, s, d, fs, v.f, v.a);
+          } else if (v.cls == kDouble) {
+            const int fs = atomicAdd(&c.st[s].found, 2);
+            push_found(c, s, d, fs, v.f, v.a);
+            push_found(c, s, d, fs + 1, v.f2, v.a2);
+          } else if (v.cls == kMulti) {
+            if (Ld >= 2 && lvl + 1 <= d.max_levels) {
+              open_nxt[k] = 1;
+              open_nxt[k + nq] = 1;
+              any_open = 1;
+            } else {
+              atomicOr(&c.st[s].flags, 1);
+            }
           }
         }
       }
@@ -371,16 +385,7 @@ hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t
 }
 
 hipError_t launch_jump_resolve(const LaunchCtx &c, int level, int grid, hipStream_t s) {
-  const int nm = nmax_bucket(c.nmax);
-  if (c.any_fp32) {
-    if (nm == 8) hipLaunchKernelGGL((k_jump_resolve<8, true>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
-    else if (nm == 16) hipLaunchKernelGGL((k_jump_resolve<16, true>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
-    else hipLaunchKernelGGL((k_jump_resolve<64, true>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
-  } else {
-    if (nm == 8) hipLaunchKernelGGL((k_jump_resolve<8, false>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
-    else if (nm == 16) hipLaunchKernelGGL((k_jump_resolve<16, false>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
-    else hipLaunchKernelGGL((k_jump_resolve<64, false>), dim3(grid), dim3(kJumpMax), 0, s, c, level);
-  }
+  SFFT_LAUNCH_CLASSIFIER(k_jump_resolve, c, dim3(grid), dim3(kJumpMax), 0, s, c, level);
   return hipGetLastError();
 }
 

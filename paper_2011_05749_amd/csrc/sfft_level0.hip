@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
     const int s = c.tree_list[li];
     const int r = item - c.l0_pre[li];
     const SigDesc &d = c.desc[s];
-    const float2 *__restrict__ x = io_of(c, s).x;
+    const SigSrc src = sig_src(io_of(c, s).x, d);
     const int64_t N = d.N;
     const int lb = d.log2B0;
     const int64_t B = d.B0;
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
     const float inv = 1.0f / (float)B;
     float2 *Y0 = c.A.y0 + d.y0_off + (int64_t)r * D * B;
     for (int p = 0; p < P; p++) {
-      gather_delays(lds, x, Bs, lgs, (uint64_t)L, (uint64_t)P, (uint64_t)p, d.shift[r],
+      gather_delays(lds, src, Bs, lgs, (uint64_t)L, (uint64_t)P, (uint64_t)p, d.shift[r],
                     (uint64_t)(N - 1), D);
       __syncthreads();
       for (int dl = 0; dl < D; dl++) fft_lds(lds + (int64_t)dl * Bs, lgs, c.A.tw);
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_stats(LaunchCtx c) {
 // Classification of the B0 level-0 classes (Sect. 3.2, Subproblems 1-2):
 // item = (signal, 256 classes); single-tons and multi-tons are compacted by
 // wave ballot + prefix, one atomic per wave and list.
-template <int NMAX, bool F32>
+template <int NMAX, bool F32, bool WAVE>
 __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
   for (int item = blockIdx.x; item < c.l0c_items; item += gridDim.x) {
     const int li = find_owner(c.l0c_pre, c.ntree, item);
@@ -131,8 +131,9 @@ __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
 #pragma unroll
       for (int i = 0; i < NMAX; i++)
         if (i < n) Y[i] = to_d(Y0[(int64_t)i * B + cc]);
-      v = classify<NMAX, true, F32>(Y, d, n, d.R, cc, B, sref2, nv);
     }
+    // every lane of the work-group takes part (the noisy enumeration is shared by the wave)
+    v = classify<NMAX, true, F32, WAVE>(Y, d, n, d.R, cc, B, sref2, nv, valid);
     const int nf = !valid ? 0 : (v.cls == kSingle ? 1 : (v.cls == kDouble ? 2 : 0));
     const int fs = wave_append_n(&c.st[s].found, nf);
     if (nf >= 1) push_found(c, s, d, fs, v.f, v.a);
@@ -227,7 +228,6 @@ hipError_t launch_reset(const LaunchCtx &c, hipStream_t s) {
 }
 
 hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
-  const int nm = nmax_bucket(c.nmax);
   if (c.ntree > 0) {
     const size_t lds = 64 * 1024;
     hipLaunchKernelGGL(k_level0_fft, dim3(c.l0_items < 8192 ? c.l0_items : 8192), dim3(kThreads),
@@ -237,15 +237,7 @@ hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
     hipLaunchKernelGGL(k_level0_stats, dim3(c.ntree < 4096 ? c.ntree : 4096), dim3(kThreads), 0, s, c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int g = c.l0c_items < 8192 ? c.l0c_items : 8192;
-    if (c.any_fp32) {
-      if (nm == 8) hipLaunchKernelGGL((k_level0_classify<8, true>), dim3(g), dim3(kThreads), 0, s, c);
-      else if (nm == 16) hipLaunchKernelGGL((k_level0_classify<16, true>), dim3(g), dim3(kThreads), 0, s, c);
-      else hipLaunchKernelGGL((k_level0_classify<64, true>), dim3(g), dim3(kThreads), 0, s, c);
-    } else {
-      if (nm == 8) hipLaunchKernelGGL((k_level0_classify<8, false>), dim3(g), dim3(kThreads), 0, s, c);
-      else if (nm == 16) hipLaunchKernelGGL((k_level0_classify<16, false>), dim3(g), dim3(kThreads), 0, s, c);
-      else hipLaunchKernelGGL((k_level0_classify<64, false>), dim3(g), dim3(kThreads), 0, s, c);
-    }
+    SFFT_LAUNCH_CLASSIFIER(k_level0_classify, c, dim3(g), dim3(kThreads), 0, s, c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (c.nffast > 0) return launch_ffast(c, s);

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_fft(LaunchCtx c, int level)
     const int s = find_owner(pf, c.nsig, item);
     const int rem = item - pf[s];
     const SigDesc &d = c.desc[s];
-    const float2 *__restrict__ x = io_of(c, s).x;
+    const SigSrc src = sig_src(io_of(c, s).x, d);
     const int64_t N = d.N;
     const int lb = d.log2B0 + level - 1;
     const int64_t Bp = (int64_t)1 << lb;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_fft(LaunchCtx c, int level)
     int m_s = c.st[s].multi[par];
     if (m_s > d.multi_cap) m_s = d.multi_cap;
     const uint64_t tau0 = (d.shift[r] + (uint64_t)(Lp >> 1)) & (uint64_t)(N - 1);
-    gather_delays(lds, x, Bs, lgs, (uint64_t)Lp, (uint64_t)P, (uint64_t)p, tau0, (uint64_t)(N - 1), D);
+    gather_delays(lds, src, Bs, lgs, (uint64_t)Lp, (uint64_t)P, (uint64_t)p, tau0, (uint64_t)(N - 1), D);
     __syncthreads();
     for (int dl = 0; dl < D; dl++) fft_lds(lds + (int64_t)dl * Bs, lgs, c.A.tw);
     for (int j = threadIdx.x; j < m_s; j += blockDim.x) {
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_direct(LaunchCtx c, int lev
     const int s = find_owner(pd, c.nsig, item);
     const int rem = item - pd[s];
     const SigDesc &d = c.desc[s];
-    const float2 *__restrict__ x = io_of(c, s).x;
+    const SigSrc src = sig_src(io_of(c, s).x, d);
     const int64_t N = d.N;
     const int lb = d.log2B0 + level - 1;
     const int64_t Bp = (int64_t)1 << lb;
@@ -149,7 +149,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_direct(LaunchCtx c, int lev
 #pragma unroll
       for (int dl = 0; dl < kMaxD; dl++) {
         z[q][dl] = make_float2(0.f, 0.f);
-        if (dl < D && m < Bp) z[q][dl] = ldg(x + ((p0 + (uint64_t)dl) & (uint64_t)(N - 1)));
+        if (dl < D && m < Bp) z[q][dl] = load_sample(src, (p0 + (uint64_t)dl) & (uint64_t)(N - 1));
       }
     }
     for (int j = 0; j < m_s; j++) {
@@ -197,12 +197,15 @@ __global__ __launch_bounds__(kThreads) void k_expand_direct(LaunchCtx c, int lev
 
 // Children of every multi-ton of level-1: Y_child = 1/2 (Y_parent +- w Z/B'),
 // w = e^{-pi i c / B'} (radix-2 split of the level's transform); classify.
-template <int NMAX, bool F32>
+template <int NMAX, bool F32, bool WAVE>
 __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
   const int par = (level - 1) & 1, cur = level & 1;
   const int32_t *pc = c.A.pre + 2 * (c.nsig + 1);
   const int total = pc[c.nsig];
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+  // whole work-groups step together (the noisy enumeration is shared by the wave)
+  for (int g0 = blockIdx.x * blockDim.x; g0 < total; g0 += gridDim.x * blockDim.x) {
+    const bool act = g0 + (int)threadIdx.x < total;
+    const int g = act ? g0 + (int)threadIdx.x : g0;
     const int s = find_owner(pc, c.nsig, g);
     const int q = g - pc[s];
     const int j = q >> 1, side = q & 1;
@@ -233,7 +236,8 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
     }
     const int64_t cc = cpar + (side ? Bp : 0);
     const SigState &ss = c.st[s];
-    const Decision v = classify<NMAX, true, F32>(Y, d, n, d.R, cc, B, ss.sref2, ss.noise_var);
+    const Decision v = classify<NMAX, true, F32, WAVE>(Y, d, n, d.R, cc, B, ss.sref2, ss.noise_var, act);
+    if (!act) continue;
     if (v.cls == kSingle) {
       const int fs = atomicAdd(&c.st[s].found, 1);
       push_found(c, s, d, fs, v.f, v.a);
@@ -284,16 +288,7 @@ hipError_t launch_expand_direct(const LaunchCtx &c, int level, int grid, hipStre
 }
 
 hipError_t launch_children(const LaunchCtx &c, int level, int grid, hipStream_t s) {
-  const int nm = nmax_bucket(c.nmax);
-  if (c.any_fp32) {
-    if (nm == 8) hipLaunchKernelGGL((k_children<8, true>), dim3(grid), dim3(kThreads), 0, s, c, level);
-    else if (nm == 16) hipLaunchKernelGGL((k_children<16, true>), dim3(grid), dim3(kThreads), 0, s, c, level);
-    else hipLaunchKernelGGL((k_children<64, true>), dim3(grid), dim3(kThreads), 0, s, c, level);
-  } else {
-    if (nm == 8) hipLaunchKernelGGL((k_children<8, false>), dim3(grid), dim3(kThreads), 0, s, c, level);
-    else if (nm == 16) hipLaunchKernelGGL((k_children<16, false>), dim3(grid), dim3(kThreads), 0, s, c, level);
-    else hipLaunchKernelGGL((k_children<64, false>), dim3(grid), dim3(kThreads), 0, s, c, level);
-  }
+  SFFT_LAUNCH_CLASSIFIER(k_children, c, dim3(grid), dim3(kThreads), 0, s, c, level);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ HDR = os.path.join(ROOT, "include", "sfft.h")
 def header_functions():
     txt = open(HDR).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(sfft_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(sfft_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -158,7 +158,7 @@ def test_noisy_plan_allows_one_delay_and_window():
 
 
 def test_column_pass_shapes():
-    """The level-1 column pass is taken for B0 = 1024, 2048, 4096, 8192 with at
+    """The level-1 column pass is taken for B0 = 512 ... 8192 with at
     least 32768 / B0 columns and one tree level, never for FFAST plans."""
     assert sfft.Plan(2 ** 22, 1024, 4, 2, B0=2048).info.l1_resolve == 1
     assert sfft.Plan(2 ** 15, 300, 2, 2, B0=2048).info.l1_resolve == 1
@@ -166,7 +166,9 @@ def test_column_pass_shapes():
     assert sfft.Plan(2 ** 15, 300, 2, 2, B0=1024).info.l1_resolve == 1
     assert sfft.Plan(2 ** 14, 300, 2, 2, B0=1024).info.l1_resolve == 0
     assert sfft.Plan(2 ** 15, 300, 2, 2, B0=4096).info.l1_resolve == 1
-    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 14, 300, 2, 2, B0=512).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=256).info.l1_resolve == 0
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=8192).info.l1_resolve == 1
     assert sfft.Plan(2 ** 14, 300, 2, 2, B0=8192).info.l1_resolve == 0
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, l1_resolve=0).info.l1_resolve == 0

@@ -27,7 +27,7 @@ def check(sfft, x, N, K, R, D, seed=0, okw=None, **kw):
     plan = sfft.Plan(N, K, R, D, seed=seed, **kw)
     hi, hv, hc, hs = plan.exec_host(x)
     # device-resident path of the same plan without the dense pass
-    dplan = sfft.Plan(N, K, R, D, seed=seed, **dict(kw, jump_L=0) if plan.info.kind == 0 else kw)
+    dplan = sfft.Plan(N, K, R, D, seed=seed, **dict(kw, jump_L=0, l1_resolve=0) if plan.info.kind == 0 else kw)
     di, dv, dc = dplan.exec(to_dev(x))
     ds = dplan.stats()
     np.testing.assert_array_equal(hi, di.cpu().numpy())

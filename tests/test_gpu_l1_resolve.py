@@ -38,6 +38,8 @@ EXACT_CASES = [
     (2 ** 17, 500, 2, 3, 1024, 5),
     (2 ** 20, 2000, 3, 2, 4096, 6),
     (2 ** 16, 3000, 2, 2, 8192, 7),   # L = 8, 2 columns per item
+    (2 ** 15, 150, 4, 2, 512, 9),     # L = 64, 32 columns per item
+    (2 ** 20, 256, 4, 2, 512, 10),
     (2 ** 18, 4000, 4, 2, 8192, 8),
 ]
 
@@ -115,7 +117,8 @@ def test_no_multiton_reads_nothing_more(sfft):
 
 
 def test_unsupported_widths_fall_back(sfft):
-    assert sfft.Plan(2 ** 16, 100, 2, 2, B0=512).info.l1_resolve == 0
+    assert sfft.Plan(2 ** 16, 100, 2, 2, B0=512).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 16, 100, 2, 2, B0=256).info.l1_resolve == 0
     assert sfft.Plan(2 ** 16, 100, 2, 2, B0=8192).info.l1_resolve == 1
     assert sfft.Plan(2 ** 14, 100, 2, 2, B0=8192).info.l1_resolve == 0   # L = 2 < 4
     assert sfft.Plan(2 ** 14, 100, 2, 2, B0=2048).info.l1_resolve == 0   # L = 8 < 16

@@ -32,7 +32,7 @@ def test_mpp_tree_exact(sfft, N, K, R, D, B0, seed, ident, jump):
     sp = siggen.make_spec(N, K, seed)
     x = siggen.synth(sp)
     g, o = solve_both(sfft, x, N, K, R, D, seed=seed, B0=B0, identity_round0=ident, jump_L=jump,
-                      mpp=2)
+                      mpp=2, l1_resolve=0)
     assert_parity(g, o)
     assert g[3]["levels"] == o[3].levels
     if jump == 0:

@@ -147,11 +147,13 @@ def test_ffast_n20_example(sfft, D):
     (2 ** 16, 100, 4, 256, 3, 0), (2 ** 10, 1, 1, 1, 5, 1), (2 ** 13, 7, 3, 16, 6, 0),
     (2 ** 18, 200, 1, 256, 7, 1), (2 ** 20, 256, 4, 512, 8, 0), (2 ** 17, 37, 2, 64, 9, 0)])
 def test_tree_exact(sfft, N, K, R, B0, seed, ident, jump):
-    """jump = 0: level-by-level gathers to the end; jump > 0: subtree
-    resolution once the stride is <= jump (same decisions, fewer passes)."""
+    """The gathering path (column pass off): jump = 0: level-by-level gathers
+    to the end; jump > 0: subtree resolution once the stride is <= jump (same
+    decisions, fewer passes)."""
     sp = siggen.make_spec(N, K, seed)
     x = siggen.synth(sp)
-    g, o = solve_both(sfft, x, N, K, R, 2, seed=seed, B0=B0, identity_round0=ident, jump_L=jump)
+    g, o = solve_both(sfft, x, N, K, R, 2, seed=seed, B0=B0, identity_round0=ident, jump_L=jump,
+                      l1_resolve=0)
     assert_parity(g, o)
     assert g[3]["levels"] == o[3].levels
     if jump == 0:
@@ -237,6 +239,20 @@ def test_noisy_tree(sfft, window, seed, jump):
     g, o = solve_both(sfft, x, N, K, 4, 2, seed=8, mode=1, window=window, jump_L=jump)
     assert_parity(g, o)
     assert abs(g[3]["noise_var"] / o[3].noise_var - 1) < 1e-4
+
+
+@pytest.mark.parametrize("N,K,B0,seed,l1", [(2 ** 20, 16, 32, 41, 0), (2 ** 22, 24, 64, 42, 0),
+                                           (2 ** 20, 300, 1024, 43, 1)])
+def test_noisy_long_candidate_ranges(sfft, N, K, B0, seed, l1):
+    """Classes with up to L = 2^16 candidates (Sect. 3.1, Method 2): ranges
+    longer than 64 blocks of 32 are enumerated by the whole wave, shorter ones
+    (the deeper levels, and the last case throughout) by their own lane;
+    decisions and values equal the oracle's."""
+    sp = siggen.make_spec(N, K, seed, snr_db=25.0)
+    x = siggen.synth(sp)
+    g, o = solve_both(sfft, x, N, K, 4, 2, seed=seed, B0=B0, mode=1, l1_resolve=l1)
+    assert_parity(g, o)
+    np.testing.assert_array_equal(g[0], siggen.truth(sp)[0])
 
 
 # ------------------------------------------------------------- batched form (a9)
@@ -412,18 +428,23 @@ def test_config3_uneven_2048_batch(sfft):
 def test_config4_precision_shape(sfft):
     """N = 2^24, K = 4096, magnitudes 10^U[0,2], SNR 30 dB, B0 = 8192, 4 rounds
     x 2 delays, noisy mode: FP32 buckets with FP64 locate / value / residual
-    (precision 0) and all-FP32 (precision 1), each against the FP64 oracle:
-    index agreement and value error reported per variant; the FP64 variant is
-    held to bit-exact indices and 1e-5, the FP32 variant to its measured
-    agreement."""
+    (precision 0), all-FP32 (precision 1), and FP16-stored samples with FP32
+    sums (sample_format 1), each against the FP64 oracle on the complex64
+    signal: index agreement and value error reported per variant; the FP64
+    variant is held to bit-exact indices and 1e-5, the others to their
+    measured agreement."""
     N, K = 2 ** 24, 4096
     sp = siggen.make_spec(N, K, 5000, mag="loguniform", mag_lo=0.0, mag_hi=2.0, snr_db=30.0)
     x = siggen.synth(sp)
     oi, ov, oc, tr = oracle.solve(oracle_cfg(N, K, 4, 2, seed=5000, mode=1, B0=8192), x)
     xd = to_dev(x)
-    for prec in (0, 1):
-        plan = sfft.Plan(N, K, 4, 2, seed=5000, B0=8192, mode="noisy", precision=prec)
-        gi, gv, gc = plan.exec(xd)
+    from tests.test_gpu_fp16 import np_pack
+    xh = to_dev(np_pack(x)[0])
+    for prec in (0, 1, 2):
+        # 2: FP16-stored samples (per-signal scale), FP32 sums, FP64 decisions
+        plan = sfft.Plan(N, K, 4, 2, seed=5000, B0=8192, mode="noisy", precision=min(prec, 1) if prec < 2 else 0,
+                         sample_format=1 if prec == 2 else 0)
+        gi, gv, gc = plan.exec(xh if prec == 2 else xd)
         gi, gv = gi.cpu().numpy(), gv.cpu().numpy().astype(np.complex128)
         go, oo = set(gi[gi >= 0].tolist()), set(oi[oi >= 0].tolist())
         common = sorted(go & oo)
@@ -438,9 +459,14 @@ def test_config4_precision_shape(sfft):
             assert gc == oc
             np.testing.assert_array_equal(gi, oi)
             assert rel_l2(gv[oi >= 0], ov[oi >= 0]) <= VAL_TOL
-        else:
+        elif prec == 1:
             assert len(go ^ oo) <= 4
             assert rel_l2(a, o) <= 1e-5
+        else:
+            # binary16 rounding of the samples (relative 2^-12) against the oracle on the
+            # complex64 signal: measured agreement, not bit-exactness
+            assert len(go ^ oo) <= 8
+            assert rel_l2(a, o) <= 1e-3
         assert l2 < 0.05
         plan.close()
 

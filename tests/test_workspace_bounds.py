@@ -61,7 +61,7 @@ def audit(plans):
                     need_jacc = max(need_jacc, (s["multi_off"] + s["multi_cap"]) * KJUMPMAX)
             if s["l1"]:
                 L = N // B0
-                assert B0 in (1024, 2048, 4096, 8192) and L >= 32768 // B0
+                assert B0 in (512, 1024, 2048, 4096, 8192) and L >= 32768 // B0
                 # column-pass items of 512 / P adjacent columns: an even count
                 tc = 512 // (B0 // 32)
                 assert L % tc == 0 and (L // tc) % 2 == 0

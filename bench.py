@@ -255,6 +255,36 @@ def run_serving(sfft, torch, np, dev, n_req=3000, per_n=16, seed=7000):
     return out
 
 
+def run_tuned(sfft, torch, np, steps, warmup, dev):
+    """Autotuner (paper_2011_05749_amd.tune) on two shapes, with a throw-away
+    cache: the noisy N = 2^20, K = 256 batch of 64 (B0 = 512, 20 dB) and the
+    exactly sparse N = 2^22, K = 1024 batch of 64 (B0 = 2048); each batch timed
+    with the default knobs and with the tuned ones."""
+    import tempfile
+
+    import siggen
+    from paper_2011_05749_amd import tune
+    out = {}
+    path = os.path.join(tempfile.mkdtemp(), "tune.json")
+    for name, N, K, B0, mode, snr, seed0 in (("noisy_n2p20_k256_20db_batch64", 2 ** 20, 256, 512, 1, 20.0, 1000),
+                                              ("exact_n2p22_k1024_batch64", 2 ** 22, 1024, 2048, 0, None, 9000)):
+        t0 = time.perf_counter()
+        e = tune.tune(N, K, 4, 2, B0=B0, mode=mode, batch=16, reps=3, path=path)
+        t_tune = time.perf_counter() - t0
+        seeds = list(range(seed0, seed0 + 64))
+        specs = [siggen.make_spec(N, K, s, snr_db=snr) for s in seeds]
+        xs = [siggen.synth_torch(sp, dev) for sp in specs]
+        res = {"tuned_knobs": e["best"], "candidates": e["tried"], "tune_s": round(t_tune, 2)}
+        for label, kw in (("default", {}), ("tuned", e["best"])):
+            plans = [sfft.Plan(N, K, 4, 2, seed=s, B0=B0, mode=mode, **kw) for s in seeds]
+            r = _time_plans(sfft, torch, np, plans, xs, specs, K, steps, warmup)
+            res[label] = {"value": r["value"], "verified": r["verified"]}
+        out[name] = res
+        del xs
+        sfft.release_batches()
+    return out
+
+
 def ilog2(v):
     return int(v).bit_length() - 1
 
@@ -709,6 +739,8 @@ def main():
         variants.update(run_configs(sfft, torch, np, args.steps, args.warmup, dev))
         variants["precision_n2p24_k4096_30db_batch8"] = run_precision_study(sfft, torch, np, args.steps,
                                                                             args.warmup, dev)
+        print("bench: autotuner", file=sys.stderr, flush=True)
+        variants["autotuned"] = run_tuned(sfft, torch, np, args.steps, args.warmup, dev)
         print("bench: serving loop", file=sys.stderr, flush=True)
         variants["serving"] = run_serving(sfft, torch, np, dev, n_req=args.serving_requests)
 

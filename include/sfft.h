@@ -164,6 +164,17 @@ typedef struct {
                               binary16, sample n = s (re + i im)): half the bytes of
                               the signal; every sum stays FP32.  FFAST plans and
                               sfft_exec_host: SFFT_EUNSUPPORTED */
+  int32_t fft_tile_lg;     /* tree: log2 of the sub-FFT size of the level-0 transform
+                              (the B0-point DFT of Eq. 6 taken as B0 / 2^fft_tile_lg
+                              LDS-resident sub-FFTs combined by twiddles); 0 = the
+                              largest that fits (2^13 / D rounded down to a power of
+                              two, at most B0); else 5 .. that size's log2
+                              (SFFT_EINVAL outside).  A launch-shape knob: results are
+                              the same up to FP32 rounding */
+  int32_t gather_unroll;   /* tree: strided sample loads each thread keeps in flight in
+                              the level-0 and level gathers: 2, 4 (0 = default) or 8;
+                              a batch takes the value of its first tree plan.  Results
+                              are unchanged */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -192,6 +203,8 @@ typedef struct {
   int32_t precision;       /* 0: FP64 decisions, 1: FP32 */
   int32_t l1_resolve;      /* 1 when the level-1 column pass is taken */
   int32_t sample_format;   /* SFFT_SAMPLES_C64 or SFFT_SAMPLES_F16 */
+  int32_t fft_tile_lg;     /* level-0 sub-FFT size in use (log2) */
+  int32_t gather_unroll;   /* gather loads in flight per thread */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */

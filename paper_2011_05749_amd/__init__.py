@@ -61,6 +61,7 @@ class Params(ctypes.Structure):
         ("peel_start_f", ctypes.c_int64 * MAX_PEEL_STARTS),
         ("l1_resolve", ctypes.c_int32),
         ("sample_format", ctypes.c_int32),
+        ("fft_tile_lg", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
     ]
 
 
@@ -87,6 +88,7 @@ class PlanInfo(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("l1_resolve", ctypes.c_int32),
         ("sample_format", ctypes.c_int32),
+        ("fft_tile_lg", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
     ]
 
 

@@ -172,13 +172,16 @@ __device__ void fft_lds(float2 *X, int lg, const float2 *__restrict__ tw) {
 // All D delays of a sample are read in the same batch of loads (adjacent
 // addresses, one cache-line fill): plane dl of lds receives, in bit-reversed
 // order, x[((m P + p) L + tau0 + dl) & mask] for m < Bs = 2^lg.
+// U: samples (each with its D delays) whose loads a thread issues before the
+// first of them is stored.
+template <int U>
 __device__ __forceinline__ void gather_delays(float2 *lds, const SigSrc &src, int64_t Bs,
                                               int lg, uint64_t L, uint64_t P, uint64_t p,
                                               uint64_t tau0, uint64_t mask, int D) {
-  for (int64_t m0 = threadIdx.x; m0 < Bs; m0 += 4 * (int64_t)blockDim.x) {
-    float2 v[4][kMaxD];
+  for (int64_t m0 = threadIdx.x; m0 < Bs; m0 += U * (int64_t)blockDim.x) {
+    float2 v[U][kMaxD];
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
+    for (int u = 0; u < U; u++) {
       const int64_t m = m0 + (int64_t)u * blockDim.x;
       const uint64_t mc = (uint64_t)(m < Bs ? m : Bs - 1);   // in-bounds; stored only if m < Bs
       const uint64_t base = (mc * P + p) * L + tau0;
@@ -187,7 +190,7 @@ __device__ __forceinline__ void gather_delays(float2 *lds, const SigSrc &src, in
         v[u][dl] = dl < D ? load_sample(src, (base + (uint64_t)dl) & mask) : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
+    for (int u = 0; u < U; u++) {
       const int64_t m = m0 + (int64_t)u * blockDim.x;
       if (m < Bs) {
         const uint32_t br = bitrev((uint32_t)m, lg);

@@ -177,6 +177,7 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     d.precision = in.precision;
     d.fp16 = in.kind == SFFT_KIND_TREE && in.sample_format == SFFT_SAMPLES_F16 ? 1 : 0;
     d.col_key = -1;
+    d.l0_tile_lg = in.fft_tile_lg;
     d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
     d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
     d.rf_m = in.rf_m;
@@ -217,6 +218,11 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
   }
   for (int s = 0; s < nsig; s++)
     if (Y.desc[s].kind == SFFT_KIND_TREE && jump_level(Y.desc[s]) <= Y.desc[s].max_levels) Y.any_jump = true;
+  for (int s = 0; s < nsig; s++)
+    if (ps[s]->info.kind == SFFT_KIND_TREE) {
+      Y.gather_u = ps[s]->info.gather_unroll;
+      break;
+    }
   // longest solves first (LPT order) for the persistent level-0 launches
   std::stable_sort(tree.begin(), tree.end(), [](auto &a, auto &b) { return a.first > b.first; });
   std::stable_sort(ffast.begin(), ffast.end(), [](auto &a, auto &b) { return a.first > b.first; });
@@ -261,6 +267,8 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
       const int64_t cnt = (d.window > 0 && d.D >= 2 && 2 * (int64_t)d.window + 1 < L0) ? 2 * (int64_t)d.window + 1 : L0;
       if (((cnt + 31) >> 5) > kEnumLaneBlocks) Y.any_noisy = 1;
     }
+    if (d.kind == SFFT_KIND_TREE)
+      Y.l0_lds = std::max<int32_t>(Y.l0_lds, (int32_t)(sizeof(float2) * (size_t)d.D << d.l0_tile_lg));
     if (d.kind == SFFT_KIND_TREE && d.jump_L >= (1 << kJumpMfmaMinLg)) Y.any_wide_jump = 1;
   }
   // arenas
@@ -385,6 +393,8 @@ void bind_layout(const Layout &Y, char *base, const float2 *tw, LaunchCtx &c) {
   c.col_lp_mask = Y.col_lp_mask;
   c.col_f16_mask = Y.col_f16_mask;
   c.any_noisy = Y.any_noisy;
+  c.gather_u = Y.gather_u;
+  c.l0_lds = Y.l0_lds;
   c.any_wide_jump = Y.any_wide_jump;
   c.nsig = (int32_t)Y.desc.size();
   c.ntree = Y.ntree;
@@ -566,6 +576,9 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
   if (p.l1_resolve != 0 && p.l1_resolve != 1) return SFFT_EINVAL;
   if (p.sample_format != SFFT_SAMPLES_C64 && p.sample_format != SFFT_SAMPLES_F16) return SFFT_EINVAL;
   in.sample_format = p.sample_format;
+  if (p.gather_unroll != 0 && p.gather_unroll != 2 && p.gather_unroll != 4 && p.gather_unroll != 8)
+    return SFFT_EINVAL;
+  in.gather_unroll = p.gather_unroll ? p.gather_unroll : 4;
   in.found_cap = (int32_t)std::max<int64_t>(64, npow2(2 * p.K));
   in.multi_cap = (int32_t)std::max<int64_t>(64, p.K);
   memset(pl->stage_off, 0, sizeof(pl->stage_off));
@@ -580,6 +593,11 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     if (B0 <= 0) B0 = std::min<int64_t>(npow2(2 * p.K), p.N);
     if (!pow2(B0) || B0 > p.N) return SFFT_EINVAL;
     if (B0 > kFftMax) return SFFT_EUNSUPPORTED;
+    {
+      const int top = std::min(ilog2(B0), split_lg(delays));
+      if (p.fft_tile_lg != 0 && (p.fft_tile_lg < 5 || p.fft_tile_lg > top)) return SFFT_EINVAL;
+      in.fft_tile_lg = p.fft_tile_lg ? p.fft_tile_lg : top;
+    }
     if (p.peel_starts != 0) return SFFT_EUNSUPPORTED;
     if (p.mpp == 2 && p.mode != SFFT_EXACT) return SFFT_EUNSUPPORTED;
     if (p.mpp == 2 && (int64_t)p.stages * (delays - 2) < 2) return SFFT_EINVAL;

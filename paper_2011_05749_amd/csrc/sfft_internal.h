@@ -57,6 +57,7 @@ struct SigDesc {
   int32_t precision;      // 0: locate / value / residual in FP64; 1: in FP32
   int32_t fp16;           // 1: x is the packed FP16 form (header with the scale, binary16 pairs)
   int32_t col_key;        // column-pass signals: log2 B0 + 32 fp16 (the instance that takes it)
+  int32_t l0_tile_lg;     // log2 of the level-0 sub-FFT size
   int32_t rf_iters, rf_m; // FFAST R-FFAST delay set r_c + 2^c t (rf_iters = 0: delays 0..D-1)
   uint64_t rf_off[SFFT_MAX_ROUNDS];
   int32_t n_starts;       // FFAST packet-erasure schedule: start frequencies (0: method 1)
@@ -141,6 +142,8 @@ struct LaunchCtx {
   int32_t col_f16_mask;    // ... for signals stored in the packed FP16 form
   int32_t any_noisy;       // some noisy tree signal has candidate ranges longer than
                            // kEnumLaneBlocks blocks (wave-shared enumeration compiled in)
+  int32_t gather_u;        // gather loads in flight per thread (2, 4 or 8)
+  int32_t l0_lds;          // dynamic LDS bytes of the level-0 transform (largest tile x D)
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
   int32_t max_B0;

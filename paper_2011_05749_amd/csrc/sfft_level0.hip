@@ -32,6 +32,7 @@ __global__ void k_reset(LaunchCtx c) {
 //   Yhat[c] = (1/B0) sum_p e^{-2 pi i c p / B0} FFT_Bs(y[m' P0 + p])[c mod Bs],
 // accumulated in the level-0 planes Y0[(r D + d) B0 + c] by this work-group
 // alone (fixed order, no atomics).
+template <int U>
 __global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
   extern __shared__ float2 lds[];
   for (int item = blockIdx.x; item < c.l0_items; item += gridDim.x) {
@@ -45,13 +46,13 @@ __global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
     const int64_t B = d.B0;
     const int64_t L = N >> lb;
     const int D = d.D;
-    const int lgs = lb < split_lg(D) ? lb : split_lg(D);
+    const int lgs = d.l0_tile_lg;
     const int64_t Bs = (int64_t)1 << lgs;
     const int P = (int)(B >> lgs);
     const float inv = 1.0f / (float)B;
     float2 *Y0 = c.A.y0 + d.y0_off + (int64_t)r * D * B;
     for (int p = 0; p < P; p++) {
-      gather_delays(lds, src, Bs, lgs, (uint64_t)L, (uint64_t)P, (uint64_t)p, d.shift[r],
+      gather_delays<U>(lds, src, Bs, lgs, (uint64_t)L, (uint64_t)P, (uint64_t)p, d.shift[r],
                     (uint64_t)(N - 1), D);
       __syncthreads();
       for (int dl = 0; dl < D; dl++) fft_lds(lds + (int64_t)dl * Bs, lgs, c.A.tw);
@@ -229,9 +230,11 @@ hipError_t launch_reset(const LaunchCtx &c, hipStream_t s) {
 
 hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
   if (c.ntree > 0) {
-    const size_t lds = 64 * 1024;
-    hipLaunchKernelGGL(k_level0_fft, dim3(c.l0_items < 8192 ? c.l0_items : 8192), dim3(kThreads),
-                       lds, s, c);
+    const size_t lds = (size_t)c.l0_lds;
+    const dim3 g0(c.l0_items < 8192 ? c.l0_items : 8192), b0(kThreads);
+    if (c.gather_u == 2) hipLaunchKernelGGL(k_level0_fft<2>, g0, b0, lds, s, c);
+    else if (c.gather_u == 8) hipLaunchKernelGGL(k_level0_fft<8>, g0, b0, lds, s, c);
+    else hipLaunchKernelGGL(k_level0_fft<4>, g0, b0, lds, s, c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_level0_stats, dim3(c.ntree < 4096 ? c.ntree : 4096), dim3(kThreads), 0, s, c);

@@ -70,6 +70,7 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
 // B'/Bs sub-FFTs of size Bs = min(B', kFftMax) in LDS: with m = m' P + p,
 //   Z[c] = sum_p e^{-2 pi i c p / B'} FFT_Bs(z[m' P + p])[c mod Bs].
 // Item = (signal, round, p); the P partial bins meet in FP64 atomics.
+template <int U>
 __global__ __launch_bounds__(kThreads) void k_expand_fft(LaunchCtx c, int level) {
   extern __shared__ float2 lds[];
   const int par = (level - 1) & 1;
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_expand_fft(LaunchCtx c, int level)
     int m_s = c.st[s].multi[par];
     if (m_s > d.multi_cap) m_s = d.multi_cap;
     const uint64_t tau0 = (d.shift[r] + (uint64_t)(Lp >> 1)) & (uint64_t)(N - 1);
-    gather_delays(lds, src, Bs, lgs, (uint64_t)Lp, (uint64_t)P, (uint64_t)p, tau0, (uint64_t)(N - 1), D);
+    gather_delays<U>(lds, src, Bs, lgs, (uint64_t)Lp, (uint64_t)P, (uint64_t)p, tau0, (uint64_t)(N - 1), D);
     __syncthreads();
     for (int dl = 0; dl < D; dl++) fft_lds(lds + (int64_t)dl * Bs, lgs, c.A.tw);
     for (int j = threadIdx.x; j < m_s; j += blockDim.x) {
@@ -278,7 +279,9 @@ hipError_t launch_sched(const LaunchCtx &c, int level, hipStream_t s) {
 
 hipError_t launch_expand_fft(const LaunchCtx &c, int level, int grid, hipStream_t s) {
   const size_t lds = 64 * 1024;
-  hipLaunchKernelGGL(k_expand_fft, dim3(grid), dim3(kThreads), lds, s, c, level);
+  if (c.gather_u == 2) hipLaunchKernelGGL(k_expand_fft<2>, dim3(grid), dim3(kThreads), lds, s, c, level);
+  else if (c.gather_u == 8) hipLaunchKernelGGL(k_expand_fft<8>, dim3(grid), dim3(kThreads), lds, s, c, level);
+  else hipLaunchKernelGGL(k_expand_fft<4>, dim3(grid), dim3(kThreads), lds, s, c, level);
   return hipGetLastError();
 }
 

@@ -1,0 +1,53 @@
+"""Autotuner host logic (no GPU): cache keys carry the device and the library
+build, a cache of another version is ignored, lookups return the stored
+knobs, every candidate is a valid plan whose knobs round-trip through
+sfft_plan_info, and out-of-range knob values are rejected."""
+import json
+
+import pytest
+
+import paper_2011_05749_amd as sfft
+from paper_2011_05749_amd import tune
+
+
+def test_cache_roundtrip_and_version(tmp_path):
+    path = str(tmp_path / "c.json")
+    key = tune.shape_key(2 ** 20, 256, 4, 2, 512, 1, device="gfx950-256cu", lib="abc")
+    assert "gfx950-256cu" in key and "abc" in key and "N=1048576" in key and "mode=1" in key
+    json.dump({"version": tune.CACHE_VERSION, "entries": {key: {"best": {"l1_resolve": 0, "jump_L": 64}}}},
+              open(path, "w"))
+    got = tune.lookup(2 ** 20, 256, 4, 2, 512, "noisy", path=path, device="gfx950-256cu", lib="abc")
+    assert got == {"l1_resolve": 0, "jump_L": 64}
+    # default B0 (next pow2 >= 2K) resolves to the same key
+    assert tune.lookup(2 ** 20, 256, 4, 2, 0, 1, path=path, device="gfx950-256cu", lib="abc") == got
+    # another library build or device: not found
+    assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx950-256cu", lib="abd") == {}
+    assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx942-304cu", lib="abc") == {}
+    # a cache written by another format version is ignored
+    json.dump({"version": tune.CACHE_VERSION + 1, "entries": {key: {"best": {"jump_L": 0}}}}, open(path, "w"))
+    assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx950-256cu", lib="abc") == {}
+    assert tune.lookup(1, 1, 1, 2, path=str(tmp_path / "missing.json"), device="d", lib="l") == {}
+
+
+@pytest.mark.parametrize("N,K,R,D,B0", [(2 ** 20, 256, 4, 2, 512), (2 ** 22, 1024, 4, 2, 2048),
+                                        (2 ** 14, 40, 2, 3, 64), (2 ** 24, 4096, 4, 2, 8192)])
+def test_candidates_are_valid_plans(N, K, R, D, B0):
+    eligible = bool(sfft.Plan(N, K, R, D, B0=B0).info.l1_resolve)
+    cands = tune.candidates(N, B0, D, eligible)
+    assert cands[0] == tune.default_knobs(B0, D, eligible)
+    assert len({json.dumps(c, sort_keys=True) for c in cands}) == len(cands)
+    for c in cands:
+        p = sfft.Plan(N, K, R, D, B0=B0, **c)
+        assert p.info.fft_tile_lg == c["fft_tile_lg"] and p.info.gather_unroll == c["gather_unroll"]
+        assert p.info.l1_resolve == (c["l1_resolve"] if eligible else 0)
+    d = sfft.Plan(N, K, R, D, B0=B0).info
+    assert d.fft_tile_lg == cands[0]["fft_tile_lg"] and d.gather_unroll == 4
+
+
+def test_knob_validation():
+    top = sfft.Plan(2 ** 16, 64, 2, 2, B0=2048).info.fft_tile_lg
+    assert top == 11
+    assert sfft.Plan(2 ** 16, 64, 2, 3, B0=8192).info.fft_tile_lg == 11   # D = 3: 2^13 / 4
+    for bad in (dict(fft_tile_lg=4), dict(fft_tile_lg=12), dict(gather_unroll=3), dict(gather_unroll=16)):
+        with pytest.raises(sfft.SfftError):
+            sfft.Plan(2 ** 16, 64, 2, 2, B0=2048, **bad)

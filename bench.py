@@ -46,7 +46,7 @@ def pct(v, q):
 
 
 # translation unit of each kernel the roofline may name (with the shared headers)
-KERNEL_SOURCES = {"k_col_pass": "sfft_col.hip", "k_col_resolve": "sfft_colres.hip",
+KERNEL_SOURCES = {"k_col_pass": "sfft_col.hip", "k_col_resolve": "sfft_colres.hip", "k_col_deep": "sfft_colres.hip",
                   "k_level0": "sfft_level0.hip", "k_jump_pass": "sfft_jump.hip",
                   "k_expand_fft": "sfft_tree.hip", "k_expand_direct": "sfft_tree.hip"}
 
@@ -285,6 +285,54 @@ def run_tuned(sfft, torch, np, steps, warmup, dev):
     return out
 
 
+WORKLOADS = {
+    # name: (N, K, B0, rounds, delays, mode, SNR dB, magnitudes, batch, first seed)
+    "config2": (2 ** 20, 256, 512, 4, 2, "noisy", 20.0, "unit", 64, 1000),
+    "config4": (2 ** 24, 4096, 8192, 4, 2, "noisy", 30.0, "loguniform", 8, 5000),
+}
+
+
+def run_workload(name, sfft, torch, np, steps, warmup, dev):
+    """One configuration alone, as one captured batch: spectra/s, per-kernel
+    event timings and the roofline of its dominant kernel (algorithmic bytes
+    per launch / its average duration), for profiling runs of that shape."""
+    import siggen
+    N, K, B0, R, D, mode, snr, mag, nb, seed0 = WORKLOADS[name]
+    seeds = [seed0 + i for i in range(nb)]
+    specs = [siggen.make_spec(N, K, s, mag=mag, mag_lo=0.0, mag_hi=2.0, snr_db=snr) for s in seeds]
+    xs = [siggen.synth_torch(sp, dev) for sp in specs]
+    plans = [sfft.Plan(N, K, R, D, seed=s, B0=B0, mode=mode) for s in seeds]
+    b = sfft.Batch(plans, xs)
+    for _ in range(warmup):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    stats = [b.stats(i) for i in range(nb)]
+    per = {}
+    for kname, lvl, ms in b.profile():
+        e = per.setdefault(kname, {"ms": 0.0, "launches": 0, "bytes": 0})
+        e["ms"] += ms
+        e["launches"] += 1
+        e["bytes"] += kernel_bytes(kname, lvl, plans, stats)
+    dom = max(per, key=lambda k: per[k]["ms"])
+    d = per[dom]
+    avg = d["ms"] / d["launches"]
+    bpl = d["bytes"] / d["launches"]
+    ach = bpl / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+    ok = sum(int(np.array_equal(b.idxs[i].cpu().numpy(), siggen.truth(sp)[0])) for i, sp in enumerate(specs))
+    return {"workload": name, "N": N, "K": K, "B0": B0, "batch": nb, "mode": mode, "snr_db": snr,
+            "value": round(nb / dt, 2), "unit": "spectra/s", "ms_per_batch": round(dt * 1e3, 4),
+            "exact_support": f"{ok}/{nb}",
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "avg_launch_ms": round(avg, 5),
+                         "algorithmic_bytes_per_launch": int(bpl)},
+            "kernels": {k: {"total_ms": round(v["ms"], 4), "launches": v["launches"]} for k, v in per.items()}}
+
+
 def ilog2(v):
     return int(v).bit_length() - 1
 
@@ -366,10 +414,13 @@ def run_variant(sfft, torch, np, xs, specs, seeds, N, K, B0, R, D, steps, warmup
     ok = sum(int(counts[i] == K and np.array_equal(b.idxs[i].cpu().numpy(), siggen.truth(sp)[0]))
              for i, sp in enumerate(specs))
     st = [b.stats(i) for i in range(len(seeds))]
+    kms = {}
+    for kname, lvl, ms in b.profile():
+        kms[kname] = round(kms.get(kname, 0.0) + ms, 4)
     out = {"value": round(len(seeds) / dt, 2), "unit": "spectra/s", "ms_per_batch": round(dt * 1e3, 4),
            "rounds": R, "delays": D, **kw,
            "verified": f"{ok}/{len(seeds)} signals: exact support, count K",
-           "samples_per_solve": float(np.mean([s["samples"] for s in st]))}
+           "samples_per_solve": float(np.mean([s["samples"] for s in st])), "kernel_ms": kms}
     del b
     sfft.release_batches()
     return out
@@ -606,6 +657,8 @@ def main():
     ap.add_argument("--plain", type=int, default=256, help="signals in the plain pass")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-requests", type=int, default=3000)
+    ap.add_argument("--workload", default="headline", choices=["headline", *WORKLOADS],
+                    help="headline (the metric, default) or one other configuration alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--jump-L", type=int, default=None,
                     help="override the plans' subtree-resolution stride (0 = level by level)")
@@ -637,6 +690,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+        return
+    if args.workload != "headline":
+        print(json.dumps(run_workload(args.workload, sfft, torch, np, args.steps, args.warmup, dev)), flush=True)
         return
     N, K, R, D, B0 = 2 ** 22, 1024, 4, 2, 2048
     nb = args.batch
@@ -724,6 +780,10 @@ def main():
         print("bench: two-ton variant", file=sys.stderr, flush=True)
         variants = {"two_ton_r2_d4": run_variant(sfft, torch, np, xs, specs, seeds, N, K, B0, 2, 4,
                                                  args.steps, args.warmup, mpp=2, jump_L=0, l1_resolve=0)}
+        for form, vname in ((1, "col_form1_32_rows"), (2, "col_form2_16_rows")):
+            print(f"bench: column pass form {form}", file=sys.stderr, flush=True)
+            variants[vname] = run_variant(sfft, torch, np, xs, specs, seeds, N, K, B0, R, D,
+                                          args.steps, args.warmup, col_form=form)
         print("bench: level-by-level gathers (column pass off)", file=sys.stderr, flush=True)
         variants["gather_levels_l1_off"] = run_variant(sfft, torch, np, xs, specs, seeds, N, K, B0, R, D,
                                                        args.steps, args.warmup, l1_resolve=0)

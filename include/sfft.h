@@ -155,7 +155,7 @@ typedef struct {
                               measured with shift t, times B0), and each class vector
                               of any later level (Sect. 3.3) is a sum of 2^d of them,
                               d levels below; taken when B0 is 512, 1024, 2048, 4096 or 8192 and
-                              L >= 32768 / B0, in place of jump_L and the level-by-level
+                              L >= max(32768 / B0, 16), in place of jump_L and the level-by-level
                               gathers.  0 = off; other values: SFFT_EINVAL */
   int32_t sample_format;   /* tree: SFFT_SAMPLES_C64 (default) = x holds N complex64;
                               SFFT_SAMPLES_F16 = x holds the packed FP16 form that
@@ -175,6 +175,15 @@ typedef struct {
                               the level-0 and level gathers: 2, 4 (0 = default) or 8;
                               a batch takes the value of its first tree plan.  Results
                               are unchanged */
+  int32_t col_form;        /* tree, level-1 column pass at B0 = 2048: 0 = the library's
+                              choice (3 at B0 = 2048), 1 = 32 rows per thread (512-thread work-groups, a
+                              32-point and a 64-point transform per column, items of 8
+                              columns), 2 = 16 rows per thread (1024-thread work-groups,
+                              transforms of 16, 8 and 16 points), 3 = 64 rows per thread
+                              (512-thread work-groups, items of 16 columns read as
+                              128-byte row segments, a 64-point and a 32-point
+                              transform); other widths take form 1 (2 or 3 with another
+                              B0: SFFT_EINVAL).  Results equal up to FP32 rounding */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -205,6 +214,7 @@ typedef struct {
   int32_t sample_format;   /* SFFT_SAMPLES_C64 or SFFT_SAMPLES_F16 */
   int32_t fft_tile_lg;     /* level-0 sub-FFT size in use (log2) */
   int32_t gather_unroll;   /* gather loads in flight per thread */
+  int32_t col_form;        /* column-pass form in use (1, 2 or 3; 0 without the pass) */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */
@@ -314,6 +324,7 @@ int32_t sfft_exec_batch_ex(const sfft_plan_t *plans, const void *const *xs,
 #define SFFT_KERNEL_JUMP_RESOLVE 8  /* subtree classification from the coefficients */
 #define SFFT_KERNEL_COL_PASS 9      /* level-1 column DFTs: M_c(t) of every open class */
 #define SFFT_KERNEL_COL_RESOLVE 10  /* classification of every later level from M_c(t) */
+#define SFFT_KERNEL_COL_DEEP 11     /* classes open below half depth: an L-point FFT of the row */
 int32_t sfft_exec_batch_profile(const sfft_plan_t *plans, const void *const *xs,
                                 int64_t *const *idx, void *const *vals, int64_t *d_counts,
                                 int32_t *d_status, int32_t n, float *ms, int32_t *kernel,

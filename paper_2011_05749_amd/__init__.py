@@ -62,6 +62,7 @@ class Params(ctypes.Structure):
         ("l1_resolve", ctypes.c_int32),
         ("sample_format", ctypes.c_int32),
         ("fft_tile_lg", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
+        ("col_form", ctypes.c_int32),
     ]
 
 
@@ -89,6 +90,7 @@ class PlanInfo(ctypes.Structure):
         ("l1_resolve", ctypes.c_int32),
         ("sample_format", ctypes.c_int32),
         ("fft_tile_lg", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
+        ("col_form", ctypes.c_int32),
     ]
 
 
@@ -134,7 +136,8 @@ class Request(ctypes.Structure):
 
 KERNEL_NAMES = {0: "k_reset", 1: "k_level0", 2: "k_sched", 3: "k_expand_fft",
                 4: "k_expand_direct", 5: "k_children", 6: "k_finalize", 7: "k_jump_pass",
-                8: "k_jump_resolve", 9: "k_col_pass", 10: "k_col_resolve"}
+                8: "k_jump_resolve", 9: "k_col_pass", 10: "k_col_resolve",
+                11: "k_col_deep"}
 
 _vp = ctypes.c_void_p
 _lib.sfft_params_init.argtypes = [ctypes.POINTER(Params), ctypes.c_int64, ctypes.c_int64,

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
   __shared__ int n_nxt[CPW];
   __shared__ int deep[64];
   __shared__ int n_deep;
+  __shared__ unsigned long long dmask[CPW];  // open subclasses at depth col_dz + 1
   const int32_t *pr = c.A.pre + 6 * (c.nsig + 1);
   const int total = pr[c.nsig];
   const int lane = threadIdx.x, g = lane >> LGS, gl = lane & (GS - 1);
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
     int nopen = valid ? 2 : 0;
     __syncthreads();  // the previous classes are done with the lists
     if (gl < 2) open_cur[g][gl] = gl;
+    if (gl == 0) dmask[g] = 0;
     for (int dd = 1; __any(nopen > 0); dd++) {
       const int nq = 1 << dd;
       const int64_t Bd = d.B0 << dd;
@@ -151,7 +153,10 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
               push_found(c, s, d, fs, v.f, v.a);
               push_found(c, s, d, fs + 1, v.f2, v.a2);
             } else if (v.cls == kMulti) {
-              if (Ld >= 2 && dd + 1 <= d.max_levels) {
+              if (Ld >= 2 && dd + 1 <= d.max_levels && dd == d.col_dz) {
+                // the children go to the deep resolution
+                atomicOr(&dmask[g], (1ull << k) | (1ull << (k + nq)));
+              } else if (Ld >= 2 && dd + 1 <= d.max_levels) {
                 const int at = atomicAdd(&n_nxt[g], 2);
                 if (at + 2 <= CAP) {
                   open_nxt[g][at] = k;
@@ -171,14 +176,191 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
       for (int k = gl; k < nopen; k += GS) open_cur[g][k] = open_nxt[g][k];
       __syncthreads();
     }
+    if (valid && gl == 0 && dmask[g] != 0) {
+      c.A.deep_mask[d.multi_off + jslot] = dmask[g];
+      c.A.deep_list[atomicAdd(c.A.deep_count, 1)] = make_int2(s, jslot);
+    }
   }
 }
 
+// Deep subtree resolution from the column pass (Sect. 3.3): the level-0
+// classes that the resolution above leaves open below depth Dz = col_dz.
+// The class's spectrum values Z_k = X[c + k B0], k < L, come from one L-point
+// DFT of its pre-twiddled column row,
+//   Z_k = sum_{t < L} M_c(t) e^{-2 pi i (c + k B0) t / N},
+// and the class vector of subclass cs = c + kappa B0 at depth dd (kappa <
+// 2^dd, L_d = L / 2^dd) is the same bucket value as the column sums give,
+//   Y_i = 1/N e^{2 pi i cs tau_i / N} sum_{j < L_d} Z_{kappa + j 2^dd} e^{2 pi i j tau_i / L_d},
+// in L_d terms instead of 2^dd.  One work-group per deep class: the row into
+// LDS and its FFT; then, round by round, every node of the subtrees below the
+// open subclasses -- as many levels at once as kDeepNodes nodes allow -- has
+// its vector formed and is classified, all in parallel, and one thread per
+// subtree walks it from the root as the tree search does (children of
+// multi-tons only): the nodes the level-by-level search would reach are the
+// ones that count, with the same vectors and so the same decisions.
+// Multi-tons on the last level of a round open the next round.
+template <int NMAX, bool F32, bool WAVE>
+__global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
+  constexpr int CH = 2048 / NMAX;  // nodes whose vectors are staged at once (32 KiB)
+  extern __shared__ float2 Zs[];   // L values (the largest L of the batch's deep signals)
+  __shared__ double2 Ys[CH][NMAX];
+  __shared__ int8_t dcls[kDeepNodes], reached[kDeepNodes];
+  __shared__ int64_t df[kDeepNodes], df2[kDeepNodes];
+  __shared__ double2 da[kDeepNodes], da2[kDeepNodes];
+  __shared__ int open_cur[kColResolveCap], open_nxt[kColResolveCap];
+  __shared__ int n_cur, n_nxt;
+  __shared__ float2 twd[kDeepTw];  // e^{-2 pi i m / L_t}, L_t = L / 2^(Dz + 1): every sum's twiddles
+  const int ndeep = *c.A.deep_count;
+  const int tid = threadIdx.x;
+  for (int e = blockIdx.x; e < ndeep; e += gridDim.x) {
+    const int2 ent = c.A.deep_list[e];
+    const int s = ent.x, jslot = ent.y;
+    const SigDesc &d = c.desc[s];
+    const uint64_t N = (uint64_t)d.N;
+    const int lgL = d.log2N - d.log2B0;
+    const int L = 1 << lgL;
+    const int n = d.n;
+    const uint64_t cpar = (uint64_t)c.A.multi_c[0][d.multi_off + jslot];
+    const float2 *M = c.A.jcol + d.jc_off + (int64_t)jslot * L;
+    const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
+    const double invN = 1.0 / (double)N;
+    // deepest depth a node is classified at (a multi-ton opens children while
+    // its depth is below it)
+    const int dmax = d.max_levels < lgL ? d.max_levels : lgL;
+    __syncthreads();  // the previous class is done with Zs and the lists
+    for (int t = tid; t < L; t += blockDim.x)
+      Zs[bitrev((uint32_t)t, lgL)] = cmulf(ldg(M + t), unit_n((cpar * (uint64_t)t) & (N - 1), d));
+    const int lgLt = lgL - d.col_dz - 1;  // <= 7 (L <= 8192, Dz = 5)
+    for (int m = tid; m < (1 << lgLt); m += blockDim.x) twd[m] = c.A.tw[m << (kLog2FftMax - lgLt)];
+    if (tid == 0) {
+      const uint64_t mask = c.A.deep_mask[d.multi_off + jslot];
+      int m = 0;
+      for (int b = 0; b < 64; b++)
+        if ((mask >> b) & 1) open_cur[m++] = b;
+      n_cur = m;
+    }
+    __syncthreads();
+    fft_lds(Zs, lgL, c.A.tw);  // Zs[k] = Z_k
+    int dd = d.col_dz + 1;     // depth of the open subclasses
+    int nopen = n_cur;
+    while (nopen > 0) {
+      // levels dd .. dd + sl - 1 this round; node l of subtree o (l = 2^r - 1 + u,
+      // u < 2^r) is subclass open_cur[o] + u 2^dd at depth dd + r
+      int sl = 1;
+      while (dd + sl <= dmax && nopen * ((2 << sl) - 1) <= kDeepNodes) sl++;
+      const int per = (1 << sl) - 1;
+      const int nn = nopen * per;
+      for (int q0 = 0; q0 < nn; q0 += CH) {
+        const int nq = nn - q0 < CH ? nn - q0 : CH;
+        // the vectors: one thread per (node, measurement)
+        for (int pe = tid; pe < nq * NMAX; pe += blockDim.x) {
+          const int qi = pe / NMAX, i = pe - qi * NMAX;
+          if (i >= n) continue;
+          const int q = q0 + qi, o = q / per, l = q - o * per;
+          const int r = 31 - __clz(l + 1), u = l + 1 - (1 << r);
+          const int ddn = dd + r, lgLd = lgL - ddn, Ld = 1 << lgLd;
+          const int kap = open_cur[o] + (u << dd);
+          const uint64_t tau = tau_of(d, i);
+          const int rr = (int)(tau & (uint64_t)(Ld - 1));
+          double ax = 0.0, ay = 0.0;
+          for (int j = 0; j < Ld; j++) {
+            const float2 z = Zs[kap + (j << ddn)];
+            // e^{+2 pi i j rr / L_d}: the conjugate of e^{-2 pi i (j rr mod L_d) / L_d}
+            const float2 w = twd[((j * rr) & (Ld - 1)) << (lgLt - lgLd)];
+            ax += (double)z.x * w.x + (double)z.y * w.y;
+            ay += (double)z.y * w.x - (double)z.x * w.y;
+          }
+          const uint64_t cs = cpar + (uint64_t)kap * (uint64_t)d.B0;
+          const double2 w = unit_d((cs * tau) & (N - 1), N, +1);
+          Ys[qi][i] = make_double2((ax * w.x - ay * w.y) * invN, (ax * w.y + ay * w.x) * invN);
+        }
+        __syncthreads();
+        {
+          // every thread classifies (the noisy enumeration may be shared by the wave)
+          const int qi = tid < nq ? tid : 0;
+          const bool act = tid < nq;
+          const int q = q0 + qi, o = q / per, l = q - o * per;
+          const int r = 31 - __clz(l + 1), u = l + 1 - (1 << r);
+          const int ddn = dd + r;
+          const int64_t cs = (int64_t)cpar + (int64_t)(open_cur[o] + (u << dd)) * d.B0;
+          double2 Y[NMAX];
+#pragma unroll
+          for (int i = 0; i < NMAX; i++) Y[i] = act && i < n ? Ys[qi][i] : make_double2(0.0, 0.0);
+          const Decision v = classify<NMAX, true, F32, WAVE>(Y, d, n, d.R, cs, d.B0 << ddn, sref2, nv, act);
+          if (act) {
+            dcls[q] = (int8_t)v.cls;
+            df[q] = v.f;
+            da[q] = v.a;
+            df2[q] = v.f2;
+            da2[q] = v.a2;
+          }
+        }
+        __syncthreads();
+      }
+      // the walk: thread o takes subtree o, level by level from its root
+      if (tid == 0) n_nxt = 0;
+      __syncthreads();
+      for (int o = tid; o < nopen; o += blockDim.x) {
+        const int base = o * per;
+        // first the nodes reached, the entries they add and the deepest one; then
+        // one reservation in the found list for the whole subtree
+        int nf = 0, deepest = 0;
+        for (int l = 0; l < per; l++) {
+          const int r = 31 - __clz(l + 1), u = l + 1 - (1 << r);
+          bool reach = l == 0;
+          if (l > 0) {
+            const int pl = base + (1 << (r - 1)) - 1 + (u & ((1 << (r - 1)) - 1));
+            reach = reached[pl] && dcls[pl] == kMulti && dd + r - 1 < dmax;
+          }
+          reached[base + l] = reach ? 1 : 0;
+          if (!reach) continue;
+          const int ddn = dd + r, q = base + l;
+          deepest = ddn;
+          nf += dcls[q] == kSingle ? 1 : dcls[q] == kDouble ? 2 : 0;
+          if (dcls[q] == kMulti) {
+            if (ddn >= dmax) {
+              atomicOr(&c.st[s].flags, 1);
+            } else if (r == sl - 1) {
+              // children on the next round's first level
+              const int kap = open_cur[o] + (u << dd);
+              const int at = atomicAdd(&n_nxt, 2);
+              if (at + 2 <= kColResolveCap) {
+                open_nxt[at] = kap;
+                open_nxt[at + 1] = kap + (1 << ddn);
+              } else {
+                atomicOr(&c.st[s].flags, 1);
+              }
+            }
+          }
+        }
+        atomicMax(&c.st[s].levels, deepest);
+        if (nf > 0) {
+          int fs = atomicAdd(&c.st[s].found, nf);
+          for (int q = base; q < base + per; q++) {
+            if (!reached[q]) continue;
+            if (dcls[q] == kSingle || dcls[q] == kDouble) push_found(c, s, d, fs++, df[q], da[q]);
+            if (dcls[q] == kDouble) push_found(c, s, d, fs++, df2[q], da2[q]);
+          }
+        }
+      }
+      __syncthreads();
+      nopen = n_nxt < kColResolveCap ? n_nxt : kColResolveCap;
+      for (int k = tid; k < nopen; k += blockDim.x) open_cur[k] = open_nxt[k];
+      dd += sl;
+      __syncthreads();
+    }
+  }
+}
 
 }  // namespace
 
 hipError_t launch_col_resolve(const LaunchCtx &c, int grid, hipStream_t s) {
   SFFT_LAUNCH_CLASSIFIER(k_col_resolve, c, dim3(grid), dim3(64), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_deep(const LaunchCtx &c, int grid, hipStream_t s) {
+  SFFT_LAUNCH_CLASSIFIER(k_col_deep, c, dim3(grid), dim3(256), (size_t)c.deep_lds, s, c);
   return hipGetLastError();
 }
 

@@ -439,24 +439,32 @@ __device__ __forceinline__ void two_ton(const double2 (&Y)[NMAX], const SigDesc 
 // candidates k = lo + o0 + o (mod L), o < min(32, cnt - o0), in FP32 MACs
 // with the twiddles anchored exactly at the block's first candidate; folds
 // them into (best, bestk): the largest statistic, ties to the smaller k.
+// e^{-2 pi i t / N} for an exact integer t < N, in FP32: from the exact FP32
+// ratio 2t/N when N is a power of two up to 2^24, else through FP64
+__device__ __forceinline__ float2 unit_n(uint64_t t, const SigDesc &d) {
+  if (d.log2N >= 0 && d.log2N <= 24) return unit_f(t, (uint64_t)d.N);
+  const double2 u = unit_d(t, (uint64_t)d.N, -1);
+  return make_float2((float)u.x, (float)u.y);
+}
+
+// the step e^{-2 pi i B tau_i / N} between consecutive candidates c + kB
 template <int NMAX, bool TREE>
-__device__ __forceinline__ void enum_block(const float2 (&Yf)[NMAX], const SigDesc &d, int n, int64_t c,
-                                           int64_t B, int64_t L, int64_t lo, int64_t cnt, int64_t o0,
-                                           float &best, int64_t &bestk) {
-  const uint64_t N = (uint64_t)d.N;
-  float2 tw[NMAX], st[NMAX];
+__device__ __forceinline__ void enum_steps(const SigDesc &d, int n, int64_t B, float2 (&st)[NMAX]) {
+#pragma unroll
+  for (int i = 0; i < NMAX; i++)
+    st[i] = i < n ? unit_n(mod_n(mod_n((uint64_t)B * tau_of<TREE>(d, i), d), d), d) : make_float2(0.f, 0.f);
+}
+
+template <int NMAX, bool TREE>
+__device__ __forceinline__ void enum_block(const float2 (&Yf)[NMAX], const float2 (&st)[NMAX], const SigDesc &d,
+                                           int n, int64_t c, int64_t B, int64_t L, int64_t lo, int64_t cnt,
+                                           int64_t o0, float &best, int64_t &bestk) {
+  float2 tw[NMAX];
   const int64_t k0 = ((lo + o0) % L + L) % L;
   const uint64_t f0 = (uint64_t)(c + k0 * B);
 #pragma unroll
-  for (int i = 0; i < NMAX; i++) {
-    if (i < n) {
-      const uint64_t ti = tau_of<TREE>(d, i);
-      const double2 a = unit_d(mod_n(f0 * ti, d), N, -1);
-      const double2 b = unit_d(mod_n(mod_n((uint64_t)B * ti, d), d), N, -1);
-      tw[i] = make_float2((float)a.x, (float)a.y);
-      st[i] = make_float2((float)b.x, (float)b.y);
-    }
-  }
+  for (int i = 0; i < NMAX; i++)
+    if (i < n) tw[i] = unit_n(mod_n(f0 * tau_of<TREE>(d, i), d), d);
   const int64_t lim = (cnt - o0) < 32 ? (cnt - o0) : 32;
   for (int64_t o = 0; o < lim; o++) {
     float gx = 0.f, gy = 0.f;
@@ -507,7 +515,10 @@ __device__ int64_t enum_wave(bool need, const float2 (&Yf)[NMAX], const SigDesc 
     float best = -1.0f;
     int64_t bestk = 0;
     const int64_t nblk = (cntj + 31) >> 5;
-    for (int64_t b = rank; b < nblk; b += nact) enum_block<NMAX, TREE>(Yj, dj, nj, cj, Bj, L, loj, cntj, b << 5, best, bestk);
+    float2 st[NMAX];
+    enum_steps<NMAX, TREE>(dj, nj, Bj, st);
+    for (int64_t b = rank; b < nblk; b += nact)
+      enum_block<NMAX, TREE>(Yj, st, dj, nj, cj, Bj, L, loj, cntj, b << 5, best, bestk);
     // largest statistic, ties to the smaller k, over the active lanes
     unsigned long long rest = act;
     float wb = -1.0f;
@@ -648,7 +659,10 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
       if (go && enumerate && !coop) {
         float best = -1.0f;
         int64_t bestk = 0;
-        for (int64_t o0 = 0; o0 < cnt; o0 += 32) enum_block<NMAX, TREE>(Yf, d, n, c, B, L, lo, cnt, o0, best, bestk);
+        float2 st[NMAX];
+        enum_steps<NMAX, TREE>(d, n, B, st);
+        for (int64_t o0 = 0; o0 < cnt; o0 += 32)
+          enum_block<NMAX, TREE>(Yf, st, d, n, c, B, L, lo, cnt, o0, best, bestk);
         k = bestk;
       }
       const int64_t kw = enum_wave<NMAX, TREE>(coop, Yf, &d, n, c, B, lo, cnt);
@@ -656,7 +670,10 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
     } else {
       float best = -1.0f;
       int64_t bestk = 0;
-      for (int64_t o0 = 0; o0 < cnt; o0 += 32) enum_block<NMAX, TREE>(Yf, d, n, c, B, L, lo, cnt, o0, best, bestk);
+      float2 st[NMAX];
+      enum_steps<NMAX, TREE>(d, n, B, st);
+      for (int64_t o0 = 0; o0 < cnt; o0 += 32)
+        enum_block<NMAX, TREE>(Yf, st, d, n, c, B, L, lo, cnt, o0, best, bestk);
       k = bestk;
     }
   }

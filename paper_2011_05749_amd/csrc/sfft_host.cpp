@@ -177,6 +177,8 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     d.precision = in.precision;
     d.fp16 = in.kind == SFFT_KIND_TREE && in.sample_format == SFFT_SAMPLES_F16 ? 1 : 0;
     d.col_key = -1;
+    d.col_ltc = 0;
+    d.col_dz = 0;
     d.l0_tile_lg = in.fft_tile_lg;
     d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
     d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
@@ -198,7 +200,15 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     d.multi_off = mc;
     d.fst_off = fst;
     d.jc_off = jc;
-    if (d.l1) d.col_key = d.log2B0 + 32 * d.fp16;
+    if (d.l1) {
+      d.col_key = d.log2B0 + 32 * d.fp16 + (in.col_form == 2 ? 64 : in.col_form == 3 ? 128 : 0);
+      d.col_ltc = in.col_form == 3 ? 4 : 14 - d.log2B0;  // 16 columns; else 512 / (B0 / 32)
+      // classes open below depth col_dz go to the deep resolution (one L-point
+      // FFT of the row, then L / 2^dd terms per sum instead of 2^dd): from about
+      // half the depth of the tree, for rows an LDS transform holds
+      const int lgL = d.log2N - d.log2B0;
+      d.col_dz = lgL <= kLog2FftMax ? std::min(kColLaneDepth, (lgL + 1) / 2) : 0;
+    }
     if (in.kind == SFFT_KIND_TREE) {
       y0 += (int64_t)d.n * in.B0;
       mc += d.multi_cap;
@@ -259,7 +269,9 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
   for (int s = 0; s < nsig; s++) {
     const SigDesc &d = Y.desc[s];
     if (d.kind == SFFT_KIND_TREE && d.precision == 1) Y.any_fp32 = 1;
-    if (d.l1) (d.fp16 ? Y.col_f16_mask : Y.col_lp_mask) |= 1 << (d.log2B0 - 9);  // bit LP - 4, B0 = 2^(LP + 5)
+    if (d.l1 && ps[s]->info.col_form == 2) Y.col16_mask |= d.fp16 ? 2 : 1;
+    else if (d.l1 && ps[s]->info.col_form == 3) Y.col16_mask |= d.fp16 ? 8 : 4;
+    else if (d.l1) (d.fp16 ? Y.col_f16_mask : Y.col_lp_mask) |= 1 << (d.log2B0 - 9);  // bit LP - 4, B0 = 2^(LP + 5)
     // the wave-shared enumeration is compiled in only where some noisy class has
     // a candidate range longer than one lane keeps (level 0 has the longest)
     if (d.kind == SFFT_KIND_TREE && d.mode == SFFT_NOISY) {
@@ -270,6 +282,8 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     if (d.kind == SFFT_KIND_TREE)
       Y.l0_lds = std::max<int32_t>(Y.l0_lds, (int32_t)(sizeof(float2) * (size_t)d.D << d.l0_tile_lg));
     if (d.kind == SFFT_KIND_TREE && d.jump_L >= (1 << kJumpMfmaMinLg)) Y.any_wide_jump = 1;
+    if (d.l1 && d.col_dz > 0 && d.col_dz < d.max_levels)
+      Y.deep_lds = std::max<int32_t>(Y.deep_lds, (int32_t)(sizeof(float2) << (d.log2N - d.log2B0)));
   }
   // arenas
   Y.n_y0 = y0;
@@ -300,6 +314,8 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
   part(Y.o_mz, 2 * sizeof(double2) * (size_t)Y.n_mvec);
   part(Y.o_jacc, sizeof(double2) * (size_t)Y.n_jacc);
   part(Y.o_jcol, sizeof(float2) * (size_t)Y.n_jcol);
+  // deep-resolution hand-off: a counter, then a list entry and a mask per multi-ton slot
+  part(Y.o_deep, Y.deep_lds ? 256 + (sizeof(int2) + sizeof(uint64_t)) * (size_t)Y.n_multi : 0);
   Y.bytes = o;
   // static launch shape of every tree level: a signal gathers level by level
   // before its jump level, runs the dense pass and the subtree resolution at
@@ -318,7 +334,7 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
       if (d.kind != SFFT_KIND_TREE || l > d.max_levels) continue;
       if (d.l1) {
         if (l == 1) {
-          ncol += (d.N >> d.log2B0) / (kColThreads / (d.B0 / kColQ));
+          ncol += (((d.N >> d.log2B0) >> d.col_ltc) + kColItemAlign - 1) & ~(int64_t)(kColItemAlign - 1);
           ncr += d.multi_cap;
         }
         continue;
@@ -345,10 +361,11 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     L.children = nch > 0;
     L.jump = nj > 0;
     L.col = ncol > 0;
-    // column pass: one resident work-group per CU (a multiple of 16, for the
-    // XCD pairing of its items)
-    L.grid_col = (int)std::max<int64_t>(16, std::min<int64_t>((int64_t)ncu & ~15, ((ncol + 15) / 16) * 16));
+    // column pass: one resident work-group per CU (a multiple of 64, for the
+    // XCD grouping of its items: 8 XCDs x up to 8 work-groups per segment)
+    L.grid_col = (int)std::max<int64_t>(64, std::min<int64_t>((int64_t)ncu & ~63, ((ncol + 63) / 64) * 64));
     L.grid_col_resolve = (int)std::min<int64_t>(std::max<int64_t>((ncr + 64 / kColGroup - 1) / (64 / kColGroup), 1), 4096);
+    L.grid_col_deep = (int)std::min<int64_t>(std::max<int64_t>(ncr, 1), 2 * (int64_t)ncu);
     L.grid_fft = (int)std::min<int64_t>(std::max<int64_t>(nf, 1), 4096);
     L.grid_direct = (int)std::min<int64_t>(std::max<int64_t>(nd, 1), 8192);
     L.grid_children = (int)std::min<int64_t>(std::max<int64_t>((nch + kThreads - 1) / kThreads, 1), 2048);
@@ -379,6 +396,10 @@ void bind_layout(const Layout &Y, char *base, const float2 *tw, LaunchCtx &c) {
   c.A.pre = (int32_t *)(base + Y.o_pre);
   c.A.jacc = (double2 *)(base + Y.o_jacc);
   c.A.jcol = (float2 *)(base + Y.o_jcol);
+  c.A.deep_count = (int32_t *)(base + Y.o_deep);
+  c.A.deep_list = (int2 *)(base + Y.o_deep + 256);
+  c.A.deep_mask = (uint64_t *)(base + Y.o_deep + 256 + sizeof(int2) * (size_t)Y.n_multi);
+  c.deep_lds = Y.deep_lds;
   c.A.tw = tw;
   const int32_t *lists = (const int32_t *)(base + Y.o_lists);
   c.tree_list = lists;
@@ -392,6 +413,7 @@ void bind_layout(const Layout &Y, char *base, const float2 *tw, LaunchCtx &c) {
   c.any_fp32 = Y.any_fp32;
   c.col_lp_mask = Y.col_lp_mask;
   c.col_f16_mask = Y.col_f16_mask;
+  c.col16_mask = Y.col16_mask;
   c.any_noisy = Y.any_noisy;
   c.gather_u = Y.gather_u;
   c.l0_lds = Y.l0_lds;
@@ -452,6 +474,10 @@ hipError_t launch_pipeline(const Layout &lay, const LaunchCtx &c, hipStream_t s,
                   (e = mark(SFFT_KERNEL_COL_PASS | (l << 8))) != hipSuccess ||
                   (e = launch_col_resolve(c, L.grid_col_resolve, s)) != hipSuccess ||
                   (e = mark(SFFT_KERNEL_COL_RESOLVE | (l << 8))) != hipSuccess))
+      return e;
+    if (L.col && c.deep_lds &&
+        ((e = launch_col_deep(c, L.grid_col_deep, s)) != hipSuccess ||
+         (e = mark(SFFT_KERNEL_COL_DEEP | (l << 8))) != hipSuccess))
       return e;
   }
   if ((e = launch_finalize(c, s)) != hipSuccess) return e;
@@ -608,8 +634,13 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     in.max_levels = (p.max_levels < 0 || p.max_levels > full) ? full : p.max_levels;
     // level-1 column pass: B0 = P x 32 with P in {32, 64, 128}, and an even
     // number of column blocks of 512 / P columns
+    // items of 16384 / B0 columns, grouped by max(2, 16 / columns): at least
+    // 32768 / B0 and 16 columns
     in.l1_resolve = p.l1_resolve && (B0 == 512 || B0 == 1024 || B0 == 2048 || B0 == 4096 || B0 == 8192) &&
-                    p.N / B0 >= 32768 / B0 && in.max_levels >= 1;
+                    p.N / B0 >= std::max<int64_t>(32768 / B0, 16) && in.max_levels >= 1;
+    if (p.col_form < 0 || p.col_form > 3 || (p.col_form >= 2 && B0 != 2048)) return SFFT_EINVAL;
+    // the library's choice: the 16-column form at B0 = 2048, the 32-row form elsewhere
+    in.col_form = in.l1_resolve ? (p.col_form > 0 ? p.col_form : (B0 == 2048 ? 3 : 1)) : 0;
     SplitMix64 g{p.seed};
     for (int r = 0; r < p.stages; r++) {
       if (r == 0 && p.identity_round0) {

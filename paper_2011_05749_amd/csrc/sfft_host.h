@@ -11,7 +11,7 @@ namespace sfft {
 
 struct LevelLaunch {
   bool fft, direct, children, jump, col;
-  int grid_fft, grid_direct, grid_children, grid_jump, grid_resolve, grid_col, grid_col_resolve;
+  int grid_fft, grid_direct, grid_children, grid_jump, grid_resolve, grid_col, grid_col_resolve, grid_col_deep;
 };
 
 // Workspace of one batch, decided on the host from its plans alone: every
@@ -25,15 +25,16 @@ struct Layout {
   size_t l0_at = 0, l0c_at = 0;
   int32_t l0_items = 0, l0c_items = 0;
   int nmax = 1, max_B0 = 1, max_stage = 1, max_found_cap = 64;
-  int32_t jrows = kJumpItemRows, any_fp32 = 0, col_lp_mask = 0, col_f16_mask = 0, any_wide_jump = 0,
-          any_noisy = 0, gather_u = 4, l0_lds = 16;
+  int32_t jrows = kJumpItemRows, any_fp32 = 0, col_lp_mask = 0, col_f16_mask = 0, col16_mask = 0,
+          any_wide_jump = 0,
+          any_noisy = 0, gather_u = 4, l0_lds = 16, deep_lds = 0;
   bool any_jump = false;
   std::vector<LevelLaunch> levels;
   // arena sizes in elements
   int64_t n_y0 = 0, n_fst = 0, n_found = 0, n_multi = 0, n_mvec = 0, n_jacc = 0, n_jcol = 0;
   // byte offsets of the parts of the slab, and its size
   size_t o_desc = 0, o_io = 0, o_st = 0, o_lists = 0, o_pre = 0, o_out = 0, o_y0 = 0, o_fst = 0,
-         o_ff = 0, o_fa = 0, o_mc = 0, o_my = 0, o_mz = 0, o_jacc = 0, o_jcol = 0, bytes = 0;
+         o_ff = 0, o_fa = 0, o_mc = 0, o_my = 0, o_mz = 0, o_jacc = 0, o_jcol = 0, o_deep = 0, bytes = 0;
 };
 
 // Timing events of a profiled pipeline run: one after every launch, with the

@@ -28,10 +28,13 @@ constexpr int kJumpMfmaMinLg = 7;    // dense passes with L' = 128 run on the ma
 constexpr int kSplitMinBins = 4;     // parents from which B' > kFftMax uses split FFTs
 constexpr int kColThreads = 512;     // work-group of the level-1 column pass
 constexpr int kColQ = 32;            // column pass: B0 = P x 32, 32 rows per thread
+constexpr int kColItemAlign = 8;     // column pass: each signal's item range padded to a multiple of this
 constexpr int kColResolveCap = 128;  // open subclasses per depth of one class
 constexpr int kColGroupLg = 3;      // column resolve: 2^3 lanes per class
 constexpr int kColGroup = 1 << kColGroupLg;
 constexpr int kColLaneDepth = 5;    // ... one lane per class-vector sum down to this depth
+constexpr int kDeepNodes = 512;     // deep resolution: subtree nodes classified per round
+constexpr int kDeepTw = 128;        // ... its twiddle table: L / 2^(Dz + 1) <= 8192 / 64 entries
 constexpr int kEnumLaneBlocks = 64; // noisy enumeration: ranges of up to 64 x 32 candidates stay
                                     // with their lane; longer ones are shared by the wave
 constexpr size_t kNoAllocScratchBytes = (size_t)SFFT_NOALLOC_SCRATCH_MIB << 20;
@@ -56,7 +59,10 @@ struct SigDesc {
   int32_t mpp;            // 2: two-ton moment preserving solve of multi-tons
   int32_t precision;      // 0: locate / value / residual in FP64; 1: in FP32
   int32_t fp16;           // 1: x is the packed FP16 form (header with the scale, binary16 pairs)
-  int32_t col_key;        // column-pass signals: log2 B0 + 32 fp16 (the instance that takes it)
+  int32_t col_key;        // column-pass signals: log2 B0 + 32 fp16 + 64 (16-row) / 128 (16-column form)
+  int32_t col_ltc;        // column-pass signals: log2 of the columns of one item
+  int32_t col_dz;         // column-pass signals: depth below which open classes go to the
+                          // deep resolution (0: the column resolution goes all the way)
   int32_t l0_tile_lg;     // log2 of the level-0 sub-FFT size
   int32_t rf_iters, rf_m; // FFAST R-FFAST delay set r_c + 2^c t (rf_iters = 0: delays 0..D-1)
   uint64_t rf_off[SFFT_MAX_ROUNDS];
@@ -112,6 +118,9 @@ struct Arena {
                           // column-pass items, column-resolve items
   double2 *jacc;          // per multi-ton slot: jstride dense-pass coefficients
   float2 *jcol;           // per level-0 multi-ton slot: M_c(t), t < N/B0
+  int32_t *deep_count;    // classes handed to the deep resolution (reset per run)
+  int2 *deep_list;        // ... their (signal, multi-ton slot)
+  uint64_t *deep_mask;    // per multi-ton slot: its open subclasses at depth col_dz + 1
   const float2 *tw;       // e^{-2 pi i k / kFftMax}, k < kFftMax
 };
 
@@ -140,9 +149,12 @@ struct LaunchCtx {
   int32_t any_fp32;        // some tree signal classifies in single precision
   int32_t col_lp_mask;     // bit LP - 4 set when a signal with B0 = 2^(LP+5) takes the column pass
   int32_t col_f16_mask;    // ... for signals stored in the packed FP16 form
+  int32_t col16_mask;      // bit 0 / 1: a complex64 / packed FP16 signal takes the 16-row form;
+                           // bit 2 / 3: the 16-column form
   int32_t any_noisy;       // some noisy tree signal has candidate ranges longer than
                            // kEnumLaneBlocks blocks (wave-shared enumeration compiled in)
   int32_t gather_u;        // gather loads in flight per thread (2, 4 or 8)
+  int32_t deep_lds;        // dynamic LDS bytes of the deep resolution (largest L x 8), 0: none
   int32_t l0_lds;          // dynamic LDS bytes of the level-0 transform (largest tile x D)
   int32_t nsig, ntree, nffast;
   int32_t nmax;           // largest n = R*D of the batch (selects the template)
@@ -162,6 +174,7 @@ hipError_t launch_jump_pass(const LaunchCtx &c, int level, int grid, hipStream_t
 hipError_t launch_jump_resolve(const LaunchCtx &c, int level, int grid, hipStream_t s);
 hipError_t launch_col_pass(const LaunchCtx &c, int grid, hipStream_t s);
 hipError_t launch_col_resolve(const LaunchCtx &c, int grid, hipStream_t s);
+hipError_t launch_col_deep(const LaunchCtx &c, int grid, hipStream_t s);
 hipError_t launch_finalize(const LaunchCtx &c, hipStream_t s);
 // level-0 class vectors in class-major order (tree: out[c*n + i]; FFAST as stored)
 hipError_t launch_export_level0(const LaunchCtx &c, void *out, hipStream_t s);

@@ -11,6 +11,7 @@ namespace {
 
 __global__ void k_reset(LaunchCtx c) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0 && c.deep_lds) *c.A.deep_count = 0;
   if (s >= c.nsig) return;
   SigState z;
   z.found = 0;

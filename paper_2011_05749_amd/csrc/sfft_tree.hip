@@ -34,7 +34,11 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
                             (m <= kJumpMfmaClasses || 2 * Lp <= d.jump_L);
           if (d.l1) {
             // level 1 of a column-pass signal: every level-0 multi-ton at once
-            cnt[5] = (int)(Lp / (kColThreads / (Bp / kColQ)));
+            // items of 2^col_ltc adjacent columns, the range padded to a
+            // multiple of kColItemAlign (the XCD grouping of the column pass
+            // takes items in aligned groups; the padding items are skipped)
+            const int nit = (int)(Lp >> d.col_ltc);
+            cnt[5] = (nit + kColItemAlign - 1) & ~(kColItemAlign - 1);
             cnt[6] = m;
             c.st[s].samples += d.N;
           } else if (jump) {

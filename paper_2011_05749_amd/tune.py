@@ -7,8 +7,9 @@ round costs B samples and a B log B transform) is laid out on the device,
 not what it computes:
 
 * the level-1 path: the column pass (every level-0 multi-ton's coefficients
-  from one read of x) or level-by-level gathers, and for the latter the
-  stride at which the dense subtree pass takes over (jump_L);
+  from one read of x; at B0 = 2048 in any of its three forms, col_form) or
+  level-by-level gathers, and for the latter the stride at which the dense
+  subtree pass takes over (jump_L);
 * fft_tile_lg: log2 of the sub-FFT size of the level-0 transform (the B0-point
   DFT is taken as B0 / 2^fft_tile_lg LDS-resident sub-FFTs; smaller tiles use
   less LDS per work-group, so more work-groups share a CU);
@@ -104,7 +105,8 @@ def candidates(N, B0, delays, l1_eligible):
     lgB = int(B0).bit_length() - 1
     top = min(lgB, 13 - (0 if delays <= 1 else (1 if delays <= 2 else 2)))
     tiles = sorted({t for t in (top, top - 1, top - 2) if t >= 5}, reverse=True) or [top]
-    paths = ([{"l1_resolve": 1}] if l1_eligible else []) + [
+    paths = ([{"l1_resolve": 1}] if l1_eligible else []) + (
+        [{"l1_resolve": 1, "col_form": f} for f in (1, 2)] if l1_eligible and int(B0) == 2048 else []) + [
         {"l1_resolve": 0, "jump_L": j} for j in (128, 64, 32, 0)]
     out = [default_knobs(B0, delays, l1_eligible)]
     for path, tile, u in itertools.product(paths, tiles, (4, 2, 8)):

@@ -165,7 +165,8 @@ def test_column_pass_shapes():
     assert sfft.Plan(2 ** 14, 300, 2, 2, B0=2048).info.l1_resolve == 0
     assert sfft.Plan(2 ** 15, 300, 2, 2, B0=1024).info.l1_resolve == 1
     assert sfft.Plan(2 ** 14, 300, 2, 2, B0=1024).info.l1_resolve == 0
-    assert sfft.Plan(2 ** 15, 300, 2, 2, B0=4096).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 16, 300, 2, 2, B0=4096).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 15, 300, 2, 2, B0=4096).info.l1_resolve == 0   # L = 8 < 16
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512).info.l1_resolve == 1
     assert sfft.Plan(2 ** 14, 300, 2, 2, B0=512).info.l1_resolve == 0
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=256).info.l1_resolve == 0
@@ -174,6 +175,21 @@ def test_column_pass_shapes():
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, l1_resolve=0).info.l1_resolve == 0
     assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, max_levels=0).info.l1_resolve == 0
     assert sfft.Plan(10800, 10, 3, 2).info.l1_resolve == 0
+
+
+def test_column_pass_forms():
+    """Forms 2 (16 rows) and 3 (16 columns) of the column pass exist at
+    B0 = 2048 only; a plan without the pass reports form 0."""
+    for f in (1, 2, 3):
+        assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, col_form=f).info.col_form == f
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048).info.col_form == 3
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=4096).info.col_form == 1
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=1024, col_form=1).info.col_form == 1
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=2048, col_form=3, l1_resolve=0).info.col_form == 0
+    for bad in (dict(B0=1024, col_form=2), dict(B0=4096, col_form=3), dict(B0=2048, col_form=4),
+                dict(B0=2048, col_form=-1)):
+        with pytest.raises(sfft.SfftError):
+            sfft.Plan(2 ** 20, 300, 2, 2, **bad)
 
 
 def test_one_hip_runtime_per_process():

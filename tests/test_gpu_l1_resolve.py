@@ -6,7 +6,7 @@ The column pass measures every level-0 multi-ton's coefficients M_c(t) from
 one read of x and classifies each later level's class vectors from them; the
 oracle gathers those vectors level by level.  Bar: indices bit-exact (padding
 included), counts and status equal, values within relative L2 1e-5.
-Shapes cover the three widths B0 = 1024, 2048, 4096, the smallest stride each
+Shapes cover the five widths B0 = 512 ... 8192, the smallest stride each
 takes (L = 32768 / B0), both modes, the two-ton solve, the FP32 decisions, a
 depth cap, and a batch that mixes the widths with signals that gather.
 """
@@ -33,11 +33,11 @@ EXACT_CASES = [
     # N, K, rounds, delays, B0, seed
     (2 ** 15, 300, 2, 2, 2048, 1),    # L = 16: one item pair per signal
     (2 ** 15, 700, 4, 2, 1024, 2),    # L = 32, 16 columns per item
-    (2 ** 15, 1500, 3, 2, 4096, 3),   # L = 8, 4 columns per item
+    (2 ** 16, 1500, 3, 2, 4096, 3),   # L = 16, 4 columns per item, groups of 4
     (2 ** 18, 900, 4, 2, 2048, 4),
     (2 ** 17, 500, 2, 3, 1024, 5),
     (2 ** 20, 2000, 3, 2, 4096, 6),
-    (2 ** 16, 3000, 2, 2, 8192, 7),   # L = 8, 2 columns per item
+    (2 ** 17, 3000, 2, 2, 8192, 7),   # L = 16, 2 columns per item, groups of 8
     (2 ** 15, 150, 4, 2, 512, 9),     # L = 64, 32 columns per item
     (2 ** 20, 256, 4, 2, 512, 10),
     (2 ** 18, 4000, 4, 2, 8192, 8),
@@ -119,18 +119,20 @@ def test_no_multiton_reads_nothing_more(sfft):
 def test_unsupported_widths_fall_back(sfft):
     assert sfft.Plan(2 ** 16, 100, 2, 2, B0=512).info.l1_resolve == 1
     assert sfft.Plan(2 ** 16, 100, 2, 2, B0=256).info.l1_resolve == 0
-    assert sfft.Plan(2 ** 16, 100, 2, 2, B0=8192).info.l1_resolve == 1
-    assert sfft.Plan(2 ** 14, 100, 2, 2, B0=8192).info.l1_resolve == 0   # L = 2 < 4
+    assert sfft.Plan(2 ** 17, 100, 2, 2, B0=8192).info.l1_resolve == 1
+    assert sfft.Plan(2 ** 16, 100, 2, 2, B0=8192).info.l1_resolve == 0   # L = 8 < 16
+    assert sfft.Plan(2 ** 15, 100, 2, 2, B0=4096).info.l1_resolve == 0   # L = 8 < 16
     assert sfft.Plan(2 ** 14, 100, 2, 2, B0=2048).info.l1_resolve == 0   # L = 8 < 16
     assert sfft.Plan(2 ** 16, 100, 2, 2, B0=2048, max_levels=0).info.l1_resolve == 0
 
 
 def test_mixed_batch_matches_oracle(sfft):
-    """Widths 1024 / 2048 / 4096 beside signals that gather level by level, in
-    one batch, eager and graph-replayed."""
+    """All five widths beside signals that gather level by level, in one
+    batch, eager and graph-replayed."""
     shapes = [(2 ** 16, 500, 1024), (2 ** 17, 900, 2048), (2 ** 15, 1500, 4096),
               (2 ** 16, 120, 256), (2 ** 18, 700, 2048), (2 ** 14, 200, 512),
-              (2 ** 17, 1000, 1024), (2 ** 16, 800, 4096)]
+              (2 ** 17, 1000, 1024), (2 ** 16, 800, 4096), (2 ** 17, 2500, 8192),
+              (2 ** 16, 150, 512), (2 ** 18, 3000, 8192)]
     plans, xs, host, cfgs = [], [], [], []
     for i, (N, K, B0) in enumerate(shapes):
         seed = 700 + i
@@ -174,3 +176,63 @@ def test_deep_pairs_match_oracle(sfft, N, B0, gap):
     g, o = solve_both(sfft, x, N, len(sup), 4, 2, seed=51, B0=B0)
     assert_parity(g, o)
     assert g[2] == len(sup)
+
+
+@pytest.mark.parametrize("form", [2, 3])
+@pytest.mark.parametrize("N,K,R,D,seed,mode,snr", [
+    (2 ** 15, 300, 2, 2, 81, 0, None),      # L = 16: one item (form 3) or two (form 2) per signal
+    (2 ** 18, 900, 4, 2, 82, 0, None),
+    (2 ** 20, 1500, 3, 3, 83, 0, None),
+    (2 ** 18, 600, 4, 2, 84, 1, 25.0),
+])
+def test_col_form_matches_oracle(sfft, form, N, K, R, D, seed, mode, snr):
+    """The 16-row form (1024-thread work-groups, 16-, 8- and 16-point
+    transforms) and the 16-column form (128-byte row segments, 64- and
+    32-point transforms in two halves) of the B0 = 2048 column pass against
+    the oracle, and equal to the 32-row form up to FP32 rounding."""
+    x = siggen.synth(siggen.make_spec(N, K, seed, snr_db=snr))
+    g, o = solve_both(sfft, x, N, K, R, D, seed=seed, B0=2048, mode=mode, col_form=form)
+    assert_parity(g, o)
+    p = sfft.Plan(N, K, R, D, seed=seed, B0=2048, mode=mode, col_form=form)
+    assert p.info.col_form == form and p.info.l1_resolve == 1
+    q = sfft.Plan(N, K, R, D, seed=seed, B0=2048, mode=mode)
+    xd = to_dev(x)
+    ia, va, ca = p.exec(xd)
+    ib, vb, cb = q.exec(xd)
+    assert ca == cb
+    np.testing.assert_array_equal(ia.cpu().numpy(), ib.cpu().numpy())
+
+
+def test_col_forms_batch_mixed(sfft):
+    """All three forms, both sample formats and other widths in one captured batch."""
+    from tests.test_gpu_fp16 import EPS16, np_pack
+    shapes = [(2 ** 17, 900, 2048, 2, 0), (2 ** 17, 900, 2048, 1, 0), (2 ** 18, 700, 2048, 2, 1),
+              (2 ** 16, 500, 1024, 0, 0), (2 ** 15, 300, 2048, 2, 0), (2 ** 16, 120, 256, 0, 0),
+              (2 ** 17, 800, 2048, 3, 0), (2 ** 15, 250, 2048, 3, 0), (2 ** 18, 650, 2048, 3, 1),
+              (2 ** 17, 2000, 8192, 0, 0), (2 ** 16, 400, 2048, 3, 0)]
+    plans, xs, cfgs, decs = [], [], [], []
+    for i, (N, K, B0, form, f16) in enumerate(shapes):
+        x = siggen.synth(siggen.make_spec(N, K, 90 + i))
+        kw = dict(eps0=EPS16, eps1=EPS16) if f16 else {}
+        if f16:
+            buf, dec = np_pack(x)
+            xs.append(to_dev(buf))
+        else:
+            dec = x
+            xs.append(to_dev(x))
+        plans.append(sfft.Plan(N, K, 3, 2, seed=90 + i, B0=B0, col_form=form, sample_format=f16, **kw))
+        cfgs.append(oracle_cfg(N, K, 3, 2, seed=90 + i, B0=B0, **kw))
+        decs.append(dec)
+    b = sfft.Batch(plans, xs)
+    for graph in (False, True, True):
+        b.run(graph=graph)
+        torch.cuda.synchronize()
+        for i in range(len(plans)):
+            oi, ov, oc, tr = oracle.solve(cfgs[i], decs[i])
+            assert int(b.counts[i].item()) == oc, i
+            np.testing.assert_array_equal(b.idxs[i].cpu().numpy(), oi)
+            m = oi >= 0
+            if m.any():
+                assert rel_l2(b.vals[i].cpu().numpy()[m].astype(np.complex128), ov[m]) <= VAL_TOL
+    del b
+    sfft.release_batches()

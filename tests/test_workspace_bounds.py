@@ -61,10 +61,11 @@ def audit(plans):
                     need_jacc = max(need_jacc, (s["multi_off"] + s["multi_cap"]) * KJUMPMAX)
             if s["l1"]:
                 L = N // B0
-                assert B0 in (512, 1024, 2048, 4096, 8192) and L >= 32768 // B0
-                # column-pass items of 512 / P adjacent columns: an even count
+                assert B0 in (512, 1024, 2048, 4096, 8192) and L >= max(32768 // B0, 16)
+                # column-pass items of 512 / P adjacent columns, grouped by G = max(2, 16 / columns)
                 tc = 512 // (B0 // 32)
-                assert L % tc == 0 and (L // tc) % 2 == 0
+                G = max(2, 16 // tc)
+                assert L % tc == 0 and (L // tc) % G == 0
                 spans["jcol"].append((s["jcol_off"], s["jcol_off"] + s["multi_cap"] * L))
                 assert s["jump_L"] == 0
         else:

@@ -227,7 +227,12 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
     // deepest depth a node is classified at (a multi-ton opens children while
     // its depth is below it)
     const int dmax = d.max_levels < lgL ? d.max_levels : lgL;
-    __syncthreads();  // the previous class is done with Zs and the lists
+    __syncthreads();  // the previous class is done with Zs, the vectors' space and the lists
+    // the L-point FFT's twiddles e^{-2 pi i m / L}, m < L / 2, held in the space
+    // of the class vectors (not in use before the first round)
+    float2 *twf = reinterpret_cast<float2 *>(&Ys[0][0]);
+    static_assert(sizeof(Ys) >= sizeof(float2) * (kFftMax / 2), "FFT twiddles fit the vectors' space");
+    for (int m = tid; m < (L >> 1); m += blockDim.x) twf[m] = c.A.tw[m << (kLog2FftMax - lgL)];
     for (int t = tid; t < L; t += blockDim.x)
       Zs[bitrev((uint32_t)t, lgL)] = cmulf(ldg(M + t), unit_n((cpar * (uint64_t)t) & (N - 1), d));
     const int lgLt = lgL - d.col_dz - 1;  // <= 7 (L <= 8192, Dz = 5)
@@ -240,7 +245,8 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
       n_cur = m;
     }
     __syncthreads();
-    fft_lds(Zs, lgL, c.A.tw);  // Zs[k] = Z_k
+    fft_lds(Zs, lgL, twf, lgL);  // Zs[k] = Z_k
+    __syncthreads();             // the vectors' space is free again
     int dd = d.col_dz + 1;     // depth of the open subclasses
     int nopen = n_cur;
     while (nopen > 0) {

@@ -131,8 +131,9 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t m, int lg) {
 // radix-2 stages are fused per pass (radix-2^2): each thread owns four
 // points at distance h = 2^{s-1}, so a pass reads and writes LDS once for two
 // stages; an odd lg starts with one plain radix-2 stage.  Twiddles come from
-// the kFftMax-point table.
-__device__ void fft_lds(float2 *X, int lg, const float2 *__restrict__ tw) {
+// a table of e^{-2 pi i m / 2^lgtw} (the kFftMax-point table by default; any
+// lgtw >= lg works, and its first 2^(lg-1) entries are all that are read).
+__device__ void fft_lds(float2 *X, int lg, const float2 *__restrict__ tw, int lgtw = kLog2FftMax) {
   const int B = 1 << lg;
   int s = 1;
   if (lg & 1) {
@@ -149,8 +150,8 @@ __device__ void fft_lds(float2 *X, int lg, const float2 *__restrict__ tw) {
     for (int t = threadIdx.x; t < (B >> 2); t += blockDim.x) {
       const int j = t & (h - 1);
       const int i0 = ((t >> (s - 1)) << (s + 1)) + j;
-      const float2 w1 = tw[j << (kLog2FftMax - s)];       // w_{2h}^j
-      const float2 w2 = tw[j << (kLog2FftMax - s - 1)];   // w_{4h}^j; w_{4h}^{j+h} = -i w2
+      const float2 w1 = tw[j << (lgtw - s)];       // w_{2h}^j
+      const float2 w2 = tw[j << (lgtw - s - 1)];   // w_{4h}^j; w_{4h}^{j+h} = -i w2
       const float2 a0 = X[i0], a1 = cmulf(X[i0 + h], w1);
       const float2 a2 = X[i0 + 2 * h], a3 = cmulf(X[i0 + 3 * h], w1);
       const float2 b0 = make_float2(a0.x + a1.x, a0.y + a1.y);

@@ -595,6 +595,7 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
   __shared__ float2 E[16 * ST];
   __shared__ float2 tw1[B0];       // W2048^e
   __shared__ int16_t slot_of[B0];  // open class -> its row slot, -1 otherwise
+  __shared__ uint32_t omask[64];   // per k1: bit k2 set when class k1 + 64 k2 is open
   const __attribute__((address_space(4))) int32_t *pc = cst(c.A.pre + 5 * (c.nsig + 1));
   const int total = pc[c.nsig];
   const int per = (total + (int)gridDim.x - 1) / (int)gridDim.x;
@@ -709,14 +710,20 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
       const int kp = brev_c(i, 5);  // k1 = 2 kp
       E[t * ST + kp * SK + p] = i == 0 ? v[0] : cmulf(v[i], tw1[2 * kp * p_it]);
     }
-    if (s != s_open)
+    if (s != s_open) {
       for (int j = tid; j < B0; j += NT) slot_of[j] = -1;
+      if (tid < 64) omask[tid] = 0u;
+    }
     fetch_quarter(0);
     __syncthreads();
     if (s != s_open) {
       // first item of another signal: its open classes and their row slots
       s_open = s;
-      for (int j = tid; j < m_s; j += NT) slot_of[(int)c.A.multi_c[0][d.multi_off + j]] = (int16_t)j;
+      for (int j = tid; j < m_s; j += NT) {
+        const int cc = (int)c.A.multi_c[0][d.multi_off + j];
+        slot_of[cc] = (int16_t)j;
+        atomicOr(&omask[cc & 63], 1u << (cc >> 6));
+      }
       __syncthreads();
     }
     // the item's first column in the rows of the open classes: a uniform base
@@ -753,6 +760,9 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
 #pragma unroll
       for (int pp = 0; pp < 16; pp++) ev[pp] = row[2 * pp];
       dft_reg<4>(ev);  // ev[i] = Ev[bitrev4(i)]
+      // the open classes among this thread's 32 (about one in ten): a bit test
+      // each, and a slot lookup only for those
+      const uint32_t om = omask[2 * p + half];
 #pragma unroll
       for (int i = 0; i < 16; i++) {
         const int k2 = brev_c(i, 4);
@@ -760,9 +770,14 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
         const float2 x0 = make_float2(ev[i].x + od.x, ev[i].y + od.y);
         const float2 x1 = make_float2(ev[i].x - od.x, ev[i].y - od.y);
         const int cb = 2 * p + half + 64 * k2;
-        const int s0 = slot_of[cb], s1 = slot_of[cb + 1024];
-        if (s0 >= 0) out[(uint32_t)s0 * L + (uint32_t)t] = F16 ? make_float2(x0.x * sc_s, x0.y * sc_s) : x0;
-        if (s1 >= 0) out[(uint32_t)s1 * L + (uint32_t)t] = F16 ? make_float2(x1.x * sc_s, x1.y * sc_s) : x1;
+        if ((om >> k2) & 1u) {
+          const uint32_t s0 = (uint32_t)slot_of[cb];
+          out[s0 * L + (uint32_t)t] = F16 ? make_float2(x0.x * sc_s, x0.y * sc_s) : x0;
+        }
+        if ((om >> (k2 + 16)) & 1u) {
+          const uint32_t s1 = (uint32_t)slot_of[cb + 1024];
+          out[s1 * L + (uint32_t)t] = F16 ? make_float2(x1.x * sc_s, x1.y * sc_s) : x1;
+        }
         // a few pairs at a time (all lookups ahead would hold their registers)
         if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
       }

@@ -62,7 +62,7 @@ class Params(ctypes.Structure):
         ("l1_resolve", ctypes.c_int32),
         ("sample_format", ctypes.c_int32),
         ("fft_tile_lg", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
-        ("col_form", ctypes.c_int32),
+        ("col_form", ctypes.c_int32), ("enum_share", ctypes.c_int32),
     ]
 
 
@@ -90,7 +90,7 @@ class PlanInfo(ctypes.Structure):
         ("l1_resolve", ctypes.c_int32),
         ("sample_format", ctypes.c_int32),
         ("fft_tile_lg", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
-        ("col_form", ctypes.c_int32),
+        ("col_form", ctypes.c_int32), ("enum_share", ctypes.c_int32),
     ]
 
 

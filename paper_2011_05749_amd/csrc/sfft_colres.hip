@@ -366,7 +366,9 @@ hipError_t launch_col_resolve(const LaunchCtx &c, int grid, hipStream_t s) {
 }
 
 hipError_t launch_col_deep(const LaunchCtx &c, int grid, hipStream_t s) {
-  SFFT_LAUNCH_CLASSIFIER(k_col_deep, c, dim3(grid), dim3(256), (size_t)c.deep_lds, s, c);
+  // its subclasses' candidate ranges are short (at most L / 2^(Dz + 1)): each
+  // stays with its lane, and the form without the wave-shared enumeration serves
+  SFFT_LAUNCH_CLASSIFIER_W(k_col_deep, c, false, dim3(grid), dim3(256), (size_t)c.deep_lds, s, c);
   return hipGetLastError();
 }
 

@@ -654,9 +654,13 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
 #pragma unroll
     for (int i = 0; i < NMAX; i++) Yf[i] = make_float2((float)Y[i].x, (float)Y[i].y);
     if (WAVE) {
-      // ranges of up to kEnumLaneBlocks blocks stay with their lane (those lanes
+      // ranges of up to enum_lane_blocks blocks stay with their lane (those lanes
       // run side by side); longer ones are shared by the whole wave, one by one
-      const bool coop = go && enumerate && ((cnt + 31) >> 5) > kEnumLaneBlocks;
+      // (level 0, where every non-empty class enumerates its whole range side
+      // by side, shares only ranges longer than kEnumLaneBlocks; the subtree
+      // levels, with few open classes per wave, from the plan's enum_share on)
+      const int share = B == d.B0 ? kEnumLaneBlocks : d.enum_lane_blocks;
+      const bool coop = go && enumerate && ((cnt + 31) >> 5) > share;
       if (go && enumerate && !coop) {
         float best = -1.0f;
         int64_t bestk = 0;
@@ -766,10 +770,12 @@ __host__ __device__ inline int nmax_bucket(int n) { return n <= 8 ? 8 : (n <= 16
     else if (w_) hipLaunchKernelGGL((KERNEL<NM, false, true>), __VA_ARGS__);      \
     else hipLaunchKernelGGL((KERNEL<NM, false, false>), __VA_ARGS__);             \
   } while (0)
-#define SFFT_LAUNCH_CLASSIFIER(KERNEL, c, ...)                                    \
+#define SFFT_LAUNCH_CLASSIFIER(KERNEL, c, ...) SFFT_LAUNCH_CLASSIFIER_W(KERNEL, c, (c).any_noisy != 0, __VA_ARGS__)
+// ... with the wave-shared enumeration compiled in when `wave` holds
+#define SFFT_LAUNCH_CLASSIFIER_W(KERNEL, c, wave, ...)                            \
   do {                                                                            \
     const int nm_ = nmax_bucket((c).nmax);                                        \
-    const bool f_ = (c).any_fp32 != 0, w_ = (c).any_noisy != 0;                   \
+    const bool f_ = (c).any_fp32 != 0, w_ = (wave);                               \
     if (nm_ == 8) SFFT_LAUNCH_FW_(KERNEL, 8, f_, w_, __VA_ARGS__);                \
     else if (nm_ == 16) SFFT_LAUNCH_FW_(KERNEL, 16, f_, w_, __VA_ARGS__);         \
     else SFFT_LAUNCH_FW_(KERNEL, 64, f_, w_, __VA_ARGS__);                        \

@@ -180,6 +180,7 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     d.col_ltc = 0;
     d.col_dz = 0;
     d.l0_tile_lg = in.fft_tile_lg;
+    d.enum_lane_blocks = in.kind == SFFT_KIND_TREE && in.enum_share > 0 ? in.enum_share : kEnumLaneBlocks;
     d.n_starts = in.kind == SFFT_KIND_FFAST ? in.peel_starts : 0;
     d.rf_iters = in.kind == SFFT_KIND_FFAST ? in.rf_iters : 0;
     d.rf_m = in.rf_m;
@@ -273,11 +274,16 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     else if (d.l1 && ps[s]->info.col_form == 3) Y.col16_mask |= d.fp16 ? 8 : 4;
     else if (d.l1) (d.fp16 ? Y.col_f16_mask : Y.col_lp_mask) |= 1 << (d.log2B0 - 9);  // bit LP - 4, B0 = 2^(LP + 5)
     // the wave-shared enumeration is compiled in only where some noisy class has
-    // a candidate range longer than one lane keeps (level 0 has the longest)
+    // a candidate range longer than one lane keeps: at level 0 (the longest
+    // ranges) past kEnumLaneBlocks blocks, below it past the plan's enum_share
     if (d.kind == SFFT_KIND_TREE && d.mode == SFFT_NOISY) {
       const int64_t L0 = d.N >> d.log2B0;
       const int64_t cnt = (d.window > 0 && d.D >= 2 && 2 * (int64_t)d.window + 1 < L0) ? 2 * (int64_t)d.window + 1 : L0;
-      if (((cnt + 31) >> 5) > kEnumLaneBlocks) Y.any_noisy = 1;
+      if (((cnt + 31) >> 5) > kEnumLaneBlocks) Y.any_noisy0 = 1;
+      // the subtree levels' ranges: L0 / 2 candidates at level 1 (a window, if
+      // any, is the same at every level)
+      const int64_t cnt1 = (d.window > 0 && d.D >= 2 && 2 * (int64_t)d.window + 1 < L0 / 2) ? 2 * (int64_t)d.window + 1 : L0 / 2;
+      if (d.max_levels >= 1 && ((cnt1 + 31) >> 5) > d.enum_lane_blocks) Y.any_noisy = 1;
     }
     if (d.kind == SFFT_KIND_TREE)
       Y.l0_lds = std::max<int32_t>(Y.l0_lds, (int32_t)(sizeof(float2) * (size_t)d.D << d.l0_tile_lg));
@@ -414,6 +420,7 @@ void bind_layout(const Layout &Y, char *base, const float2 *tw, LaunchCtx &c) {
   c.col_lp_mask = Y.col_lp_mask;
   c.col_f16_mask = Y.col_f16_mask;
   c.col16_mask = Y.col16_mask;
+  c.any_noisy0 = Y.any_noisy0;
   c.any_noisy = Y.any_noisy;
   c.gather_u = Y.gather_u;
   c.l0_lds = Y.l0_lds;
@@ -632,13 +639,13 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     in.B0 = B0;
     const int full = ilog2(p.N / B0);
     in.max_levels = (p.max_levels < 0 || p.max_levels > full) ? full : p.max_levels;
-    // level-1 column pass: B0 = P x 32 with P in {32, 64, 128}, and an even
-    // number of column blocks of 512 / P columns
-    // items of 16384 / B0 columns, grouped by max(2, 16 / columns): at least
-    // 32768 / B0 and 16 columns
+    // level-1 column pass: B0 = 32 P with P = 16 ... 256, at least 32768 / B0
+    // and 16 columns
     in.l1_resolve = p.l1_resolve && (B0 == 512 || B0 == 1024 || B0 == 2048 || B0 == 4096 || B0 == 8192) &&
                     p.N / B0 >= std::max<int64_t>(32768 / B0, 16) && in.max_levels >= 1;
     if (p.col_form < 0 || p.col_form > 3 || (p.col_form >= 2 && B0 != 2048)) return SFFT_EINVAL;
+    if (p.enum_share < 0 || p.enum_share > kEnumLaneBlocks) return SFFT_EINVAL;
+    in.enum_share = p.enum_share ? p.enum_share : kEnumShareDefault;
     // the library's choice: the 16-column form at B0 = 2048, the 32-row form elsewhere
     in.col_form = in.l1_resolve ? (p.col_form > 0 ? p.col_form : (B0 == 2048 ? 3 : 1)) : 0;
     SplitMix64 g{p.seed};

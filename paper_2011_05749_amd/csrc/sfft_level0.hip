@@ -241,7 +241,7 @@ hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
     hipLaunchKernelGGL(k_level0_stats, dim3(c.ntree < 4096 ? c.ntree : 4096), dim3(kThreads), 0, s, c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     const int g = c.l0c_items < 8192 ? c.l0c_items : 8192;
-    SFFT_LAUNCH_CLASSIFIER(k_level0_classify, c, dim3(g), dim3(kThreads), 0, s, c);
+    SFFT_LAUNCH_CLASSIFIER_W(k_level0_classify, c, c.any_noisy0 != 0, dim3(g), dim3(kThreads), 0, s, c);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (c.nffast > 0) return launch_ffast(c, s);

@@ -14,7 +14,10 @@ not what it computes:
   DFT is taken as B0 / 2^fft_tile_lg LDS-resident sub-FFTs; smaller tiles use
   less LDS per work-group, so more work-groups share a CU);
 * gather_unroll: samples each thread has in flight in the strided gathers
-  (2, 4 or 8 load batches per thread).
+  (2, 4 or 8 load batches per thread);
+* enum_share (noisy mode): from how many blocks of 32 candidates on a class's
+  enumeration (Sect. 3.1, Method 2) is shared by the 64 lanes of its wave
+  instead of walked by its own lane.
 
 Each candidate runs a captured batch of synthetic signals of the shape
 (random K-sparse spectra, unit magnitudes, generated on the device) and the
@@ -99,9 +102,10 @@ def default_knobs(B0, delays, l1_eligible) -> dict:
     return {**path, "fft_tile_lg": top, "gather_unroll": 4}
 
 
-def candidates(N, B0, delays, l1_eligible):
+def candidates(N, B0, delays, l1_eligible, mode=0):
     """Knob settings tried for a shape (each a dict of Plan keywords), the
-    default first."""
+    default first; noisy shapes also try the wave-shared enumeration from
+    fewer candidate blocks on (enum_share)."""
     lgB = int(B0).bit_length() - 1
     top = min(lgB, 13 - (0 if delays <= 1 else (1 if delays <= 2 else 2)))
     tiles = sorted({t for t in (top, top - 1, top - 2) if t >= 5}, reverse=True) or [top]
@@ -113,6 +117,8 @@ def candidates(N, B0, delays, l1_eligible):
         c = {**path, "fft_tile_lg": tile, "gather_unroll": u}
         if c not in out:
             out.append(c)
+    if mode in (1, "noisy"):
+        out += [{**out[0], "enum_share": e} for e in (64, 16, 1)]
     return out
 
 
@@ -145,7 +151,7 @@ def tune(N, K, rounds, delays, B0=0, mode=0, batch=32, reps=5, seed=1, path=None
     eligible = bool(base.info.l1_resolve)
     xs = _signals(N, K, batch, seed, dev)
     results = []
-    cands = candidates(N, B0, delays, eligible)
+    cands = candidates(N, B0, delays, eligible, mode)
     if limit is not None:
         cands = cands[:limit]
     for cand in cands:

@@ -192,6 +192,16 @@ def test_column_pass_forms():
             sfft.Plan(2 ** 20, 300, 2, 2, **bad)
 
 
+def test_enum_share_bounds():
+    """The wave-sharing threshold of the noisy enumeration below level 0:
+    1 .. 64 blocks, 0 = 4; FFAST plans ignore it."""
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512, mode="noisy").info.enum_share == 4
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512, mode="noisy", enum_share=4).info.enum_share == 4
+    for bad in (-1, 65):
+        with pytest.raises(sfft.SfftError):
+            sfft.Plan(2 ** 20, 300, 2, 2, B0=512, mode="noisy", enum_share=bad)
+
+
 def test_one_hip_runtime_per_process():
     """Importing the binding maps exactly one HIP and one HSA runtime: the
     library's runtime dependency binds to the copy torch already loaded (two

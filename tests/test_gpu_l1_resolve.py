@@ -236,3 +236,24 @@ def test_col_forms_batch_mixed(sfft):
                 assert rel_l2(b.vals[i].cpu().numpy()[m].astype(np.complex128), ov[m]) <= VAL_TOL
     del b
     sfft.release_batches()
+
+
+def test_enum_share_changes_nothing(sfft):
+    """Noisy solves with the enumeration shared by the wave from 1, 2, 16 or
+    64 blocks of 32 candidates on: every candidate's statistic is the same
+    number, so indices and values are identical, and equal to the oracle."""
+    N, K, B0 = 2 ** 18, 160, 512
+    x = siggen.synth(siggen.make_spec(N, K, 77, snr_db=20.0))
+    xd = to_dev(x)
+    outs = []
+    for es in (64, 16, 2, 1):
+        p = sfft.Plan(N, K, 4, 2, seed=77, B0=B0, mode=1, enum_share=es)
+        assert p.info.enum_share == es
+        idx, val, cnt = p.exec(xd)
+        outs.append((idx.cpu().numpy(), val.cpu().numpy(), cnt))
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o[0], outs[0][0])
+        np.testing.assert_array_equal(o[1], outs[0][1])
+        assert o[2] == outs[0][2]
+    g, o = solve_both(sfft, x, N, K, 4, 2, seed=77, B0=B0, mode=1, enum_share=1)
+    assert_parity(g, o)

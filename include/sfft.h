@@ -184,13 +184,15 @@ typedef struct {
                               128-byte row segments, a 64-point and a 32-point
                               transform); other widths take form 1 (2 or 3 with another
                               B0: SFFT_EINVAL).  Results equal up to FP32 rounding */
-  int32_t enum_share;      /* tree, noisy mode, levels below 0: a class whose candidate
-                              range is longer than this many blocks of 32 candidates is
-                              enumerated by the 64 lanes of its wave together, shorter
-                              ones each by its own lane (level 0 shares ranges over 64
-                              blocks); 1 .. 64 (0 = 4, SFFT_EINVAL outside).  A
-                              launch-shape knob: every candidate's statistic is the same
-                              number either way, so results are unchanged */
+  int32_t enum_share;      /* tree, noisy mode, levels below 0: where some class of a
+                              batch has a candidate range longer than this many blocks
+                              of 32 candidates, the classes of a wave that enumerate are
+                              dealt to teams of lanes (a lone class gets the whole wave),
+                              else each enumerates on its own lane (level 0 uses teams
+                              for ranges over 64 blocks); 1 .. 64 (0 = 4, SFFT_EINVAL
+                              outside).  A launch-shape knob: every candidate's
+                              statistic is the same number either way, so results are
+                              unchanged */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -222,7 +224,7 @@ typedef struct {
   int32_t fft_tile_lg;     /* level-0 sub-FFT size in use (log2) */
   int32_t gather_unroll;   /* gather loads in flight per thread */
   int32_t col_form;        /* column-pass form in use (1, 2 or 3; 0 without the pass) */
-  int32_t enum_share;      /* wave-shared enumeration above this many 32-candidate blocks */
+  int32_t enum_share;      /* team enumeration above this many 32-candidate blocks */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */

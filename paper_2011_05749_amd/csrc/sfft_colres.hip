@@ -135,7 +135,7 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
         }
         __syncthreads();
         {
-          // every lane takes part (the noisy enumeration is shared by the wave)
+          // every lane takes part (the noisy enumeration may run in teams of the wave's lanes)
           const bool act = gl < no;
           const int k = act ? open_cur[g][ch * GS + gl] : 0;
           const int64_t cs = (int64_t)cpar + (int64_t)k * d.B0;
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
         }
         __syncthreads();
         {
-          // every thread classifies (the noisy enumeration may be shared by the wave)
+          // every thread classifies (the noisy enumeration may run in teams of the wave's lanes)
           const int qi = tid < nq ? tid : 0;
           const bool act = tid < nq;
           const int q = q0 + qi, o = q / per, l = q - o * per;
@@ -367,7 +367,7 @@ hipError_t launch_col_resolve(const LaunchCtx &c, int grid, hipStream_t s) {
 
 hipError_t launch_col_deep(const LaunchCtx &c, int grid, hipStream_t s) {
   // its subclasses' candidate ranges are short (at most L / 2^(Dz + 1)): each
-  // stays with its lane, and the form without the wave-shared enumeration serves
+  // stays with its lane, and the form without the team enumeration serves
   SFFT_LAUNCH_CLASSIFIER_W(k_col_deep, c, false, dim3(grid), dim3(256), (size_t)c.deep_lds, s, c);
   return hipGetLastError();
 }

@@ -487,56 +487,88 @@ __device__ __forceinline__ void enum_block(const float2 (&Yf)[NMAX], const float
   }
 }
 
-// The enumeration of every lane whose `need` is set, by all the lanes that
-// execute the call: lane j's class vector and candidate range are broadcast,
-// the active lanes take its 32-candidate blocks in turn (the blocks and
-// anchors of the one-lane loop, so every statistic is the same number), and
-// the best candidate is reduced over the lanes.  Each needing lane gets its
-// own k; every lane of the wave must reach the call together with the others
-// of its group (all lanes of the wave in the tree kernels).
-template <int NMAX, bool TREE>
-__device__ int64_t enum_wave(bool need, const float2 (&Yf)[NMAX], const SigDesc *dp, int n, int64_t c,
-                             int64_t B, int64_t lo, int64_t cnt) {
-  const unsigned long long act = __ballot(1);
-  unsigned long long mask = __ballot(need);
-  const int lane = __lane_id();
-  const int rank = (int)__popcll(act & ((1ull << lane) - 1ull)), nact = (int)__popcll(act);
-  int64_t result = 0;
-  while (mask) {
-    const int j = __ffsll((long long)mask) - 1;
-    mask &= mask - 1ull;
-    const SigDesc &dj = *(const SigDesc *)__shfl((unsigned long long)dp, j);
-    const int nj = __shfl(n, j);
-    const int64_t cj = __shfl((long long)c, j), Bj = __shfl((long long)B, j);
-    const int64_t loj = __shfl((long long)lo, j), cntj = __shfl((long long)cnt, j);
-    float2 Yj[NMAX];
+// position of the r-th set bit of m (r < popcount(m))
+__device__ __forceinline__ int nth_set_bit(unsigned long long m, int r) {
+  int pos = 0;
 #pragma unroll
-    for (int i = 0; i < NMAX; i++) Yj[i] = make_float2(__shfl(Yf[i].x, j), __shfl(Yf[i].y, j));
-    const int64_t L = dj.N / Bj;
+  for (int w = 32; w >= 1; w >>= 1) {
+    const int low = (int)__popcll(m & ((1ull << w) - 1ull));
+    if (r >= low) {
+      r -= low;
+      m >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// The enumeration of every lane whose `need` is set, by teams: the A needing
+// lanes' classes are dealt, in lane order, to teams of T = 2^t adjacent lanes
+// (the largest T with A T <= 64, and no larger than the longest range's block
+// count); member m of a team takes its class's blocks m, m + T, ... -- the
+// blocks and anchors of the one-lane loop, so every statistic is the same
+// number -- and the team reduces its best candidate by a butterfly (largest
+// statistic, ties to the smaller k).  T = 1 is the one-lane form, T = 64 the
+// whole wave on one class.  Every lane of the wave must make the call.
+template <int NMAX, bool TREE>
+__device__ int64_t enum_team(bool need, const float2 (&Yf)[NMAX], const SigDesc *dp, int n, int64_t c,
+                             int64_t B, int64_t lo, int64_t cnt) {
+  const unsigned long long mask = __ballot(need);
+  const int A = (int)__popcll(mask);
+  if (A == 0) return 0;
+  const int lane = __lane_id();
+  if (__ballot(1) != ~0ull) {
+    // not every lane present: each needing lane takes its own class
     float best = -1.0f;
     int64_t bestk = 0;
+    if (need) {
+      const int64_t L = dp->N / B;
+      float2 st[NMAX];
+      enum_steps<NMAX, TREE>(*dp, n, B, st);
+      for (int64_t o0 = 0; o0 < cnt; o0 += 32)
+        enum_block<NMAX, TREE>(Yf, st, *dp, n, c, B, L, lo, cnt, o0, best, bestk);
+    }
+    return bestk;
+  }
+  // the longest range (in blocks) among the needing lanes
+  int nb = need ? (int)((cnt + 31) >> 5) : 0;
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) nb = max(nb, __shfl_xor(nb, m));
+  int lgT = 0;
+  while ((A << (lgT + 1)) <= 64 && (1 << (lgT + 1)) <= nb) lgT++;
+  const int T = 1 << lgT;
+  const int r = lane >> lgT, mem = lane & (T - 1);
+  const bool worker = r < A;
+  const int src = worker ? nth_set_bit(mask, r) : lane;
+  const SigDesc &dj = *(const SigDesc *)__shfl((unsigned long long)dp, src);
+  const int nj = __shfl(n, src);
+  const int64_t cj = __shfl((long long)c, src), Bj = __shfl((long long)B, src);
+  const int64_t loj = __shfl((long long)lo, src), cntj = __shfl((long long)cnt, src);
+  float2 Yj[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; i++) Yj[i] = make_float2(__shfl(Yf[i].x, src), __shfl(Yf[i].y, src));
+  float best = -1.0f;
+  int64_t bestk = 0;
+  if (worker) {
+    const int64_t L = dj.N / Bj;
     const int64_t nblk = (cntj + 31) >> 5;
     float2 st[NMAX];
     enum_steps<NMAX, TREE>(dj, nj, Bj, st);
-    for (int64_t b = rank; b < nblk; b += nact)
+    for (int64_t b = mem; b < nblk; b += T)
       enum_block<NMAX, TREE>(Yj, st, dj, nj, cj, Bj, L, loj, cntj, b << 5, best, bestk);
-    // largest statistic, ties to the smaller k, over the active lanes
-    unsigned long long rest = act;
-    float wb = -1.0f;
-    int64_t wk = 0;
-    while (rest) {
-      const int l = __ffsll((long long)rest) - 1;
-      rest &= rest - 1ull;
-      const float ob = __shfl(best, l);
-      const int64_t ok = __shfl((long long)bestk, l);
-      if (ob > wb || (ob == wb && ok < wk)) {
-        wb = ob;
-        wk = ok;
-      }
-    }
-    if (lane == j) result = wk;
   }
-  return result;
+  for (int m = 1; m < T; m <<= 1) {
+    const float ob = __shfl_xor(best, m);
+    const int64_t ok = __shfl_xor((long long)bestk, m);
+    if (ob > best || (ob == best && ok < bestk)) {
+      best = ob;
+      bestk = ok;
+    }
+  }
+  // the needing lane of rank q reads its team's first lane
+  const int q = (int)__popcll(mask & ((1ull << lane) - 1ull));
+  const int64_t res = __shfl((long long)bestk, (need ? q : 0) << lgT);
+  return need ? res : 0;
 }
 
 // Singleton test (Sect. 3.2, Subproblems 1-2) of one class vector Y (n values,
@@ -654,24 +686,10 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
 #pragma unroll
     for (int i = 0; i < NMAX; i++) Yf[i] = make_float2((float)Y[i].x, (float)Y[i].y);
     if (WAVE) {
-      // ranges of up to enum_lane_blocks blocks stay with their lane (those lanes
-      // run side by side); longer ones are shared by the whole wave, one by one
-      // (level 0, where every non-empty class enumerates its whole range side
-      // by side, shares only ranges longer than kEnumLaneBlocks; the subtree
-      // levels, with few open classes per wave, from the plan's enum_share on)
-      const int share = B == d.B0 ? kEnumLaneBlocks : d.enum_lane_blocks;
-      const bool coop = go && enumerate && ((cnt + 31) >> 5) > share;
-      if (go && enumerate && !coop) {
-        float best = -1.0f;
-        int64_t bestk = 0;
-        float2 st[NMAX];
-        enum_steps<NMAX, TREE>(d, n, B, st);
-        for (int64_t o0 = 0; o0 < cnt; o0 += 32)
-          enum_block<NMAX, TREE>(Yf, st, d, n, c, B, L, lo, cnt, o0, best, bestk);
-        k = bestk;
-      }
-      const int64_t kw = enum_wave<NMAX, TREE>(coop, Yf, &d, n, c, B, lo, cnt);
-      if (coop) k = kw;
+      // the wave's enumerating classes by teams of lanes (one lane each when
+      // they fill the wave, the whole wave for a lone class)
+      const int64_t kt = enum_team<NMAX, TREE>(go && enumerate, Yf, &d, n, c, B, lo, cnt);
+      if (go && enumerate) k = kt;
     } else {
       float best = -1.0f;
       int64_t bestk = 0;
@@ -762,7 +780,7 @@ __host__ __device__ inline int nmax_bucket(int n) { return n <= 8 ? 8 : (n <= 16
 
 // Launch a classifying kernel KERNEL<NMAX, F32, WAVE> for the batch in c: its
 // class-vector size, whether a signal decides in FP32, whether a signal is in
-// noisy mode (the wave-shared enumeration is compiled into those instances only).
+// noisy mode (the team enumeration is compiled into those instances only).
 #define SFFT_LAUNCH_FW_(KERNEL, NM, f_, w_, ...)                                  \
   do {                                                                            \
     if (f_ && w_) hipLaunchKernelGGL((KERNEL<NM, true, true>), __VA_ARGS__);      \
@@ -771,7 +789,7 @@ __host__ __device__ inline int nmax_bucket(int n) { return n <= 8 ? 8 : (n <= 16
     else hipLaunchKernelGGL((KERNEL<NM, false, false>), __VA_ARGS__);             \
   } while (0)
 #define SFFT_LAUNCH_CLASSIFIER(KERNEL, c, ...) SFFT_LAUNCH_CLASSIFIER_W(KERNEL, c, (c).any_noisy != 0, __VA_ARGS__)
-// ... with the wave-shared enumeration compiled in when `wave` holds
+// ... with the team enumeration compiled in when `wave` holds
 #define SFFT_LAUNCH_CLASSIFIER_W(KERNEL, c, wave, ...)                            \
   do {                                                                            \
     const int nm_ = nmax_bucket((c).nmax);                                        \

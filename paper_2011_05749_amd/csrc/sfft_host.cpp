@@ -273,9 +273,10 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     if (d.l1 && ps[s]->info.col_form == 2) Y.col16_mask |= d.fp16 ? 2 : 1;
     else if (d.l1 && ps[s]->info.col_form == 3) Y.col16_mask |= d.fp16 ? 8 : 4;
     else if (d.l1) (d.fp16 ? Y.col_f16_mask : Y.col_lp_mask) |= 1 << (d.log2B0 - 9);  // bit LP - 4, B0 = 2^(LP + 5)
-    // the wave-shared enumeration is compiled in only where some noisy class has
-    // a candidate range longer than one lane keeps: at level 0 (the longest
-    // ranges) past kEnumLaneBlocks blocks, below it past the plan's enum_share
+    // the team enumeration is compiled in only where some noisy class has a
+    // candidate range longer than one lane keeps: at level 0 (the longest
+    // ranges, every non-empty class of a wave enumerating side by side) past
+    // kEnumLaneBlocks blocks, below it past the plan's enum_share
     if (d.kind == SFFT_KIND_TREE && d.mode == SFFT_NOISY) {
       const int64_t L0 = d.N >> d.log2B0;
       const int64_t cnt = (d.window > 0 && d.D >= 2 && 2 * (int64_t)d.window + 1 < L0) ? 2 * (int64_t)d.window + 1 : L0;

@@ -35,9 +35,9 @@ constexpr int kColGroup = 1 << kColGroupLg;
 constexpr int kColLaneDepth = 5;    // ... one lane per class-vector sum down to this depth
 constexpr int kDeepNodes = 512;     // deep resolution: subtree nodes classified per round
 constexpr int kDeepTw = 128;        // ... its twiddle table: L / 2^(Dz + 1) <= 8192 / 64 entries
-constexpr int kEnumLaneBlocks = 64; // noisy enumeration at level 0: ranges of up to this many blocks of 32
-                                    // candidates stay with their lane, longer ones are shared by the
-                                    // wave (also the largest value of a plan's enum_share)
+constexpr int kEnumLaneBlocks = 64; // noisy enumeration at level 0: a batch whose ranges are at most this many
+                                    // blocks of 32 candidates enumerates one lane a class, else in
+                                    // teams of lanes (also the largest value of a plan's enum_share)
 constexpr int kEnumShareDefault = 4; // ... at the subtree levels, unless the plan says otherwise
 constexpr size_t kNoAllocScratchBytes = (size_t)SFFT_NOALLOC_SCRATCH_MIB << 20;
 constexpr size_t kNoAllocTwBytes = 64 * 1024;  // twiddle table at the scratch's start
@@ -66,7 +66,7 @@ struct SigDesc {
   int32_t col_dz;         // column-pass signals: depth below which open classes go to the
                           // deep resolution (0: the column resolution goes all the way)
   int32_t l0_tile_lg;     // log2 of the level-0 sub-FFT size
-  int32_t enum_lane_blocks;  // noisy enumeration: longer candidate ranges (in 32-blocks) shared by the wave
+  int32_t enum_lane_blocks;  // noisy enumeration below level 0: teams where ranges exceed this many 32-blocks
   int32_t rf_iters, rf_m; // FFAST R-FFAST delay set r_c + 2^c t (rf_iters = 0: delays 0..D-1)
   uint64_t rf_off[SFFT_MAX_ROUNDS];
   int32_t n_starts;       // FFAST packet-erasure schedule: start frequencies (0: method 1)
@@ -154,9 +154,9 @@ struct LaunchCtx {
   int32_t col_f16_mask;    // ... for signals stored in the packed FP16 form
   int32_t col16_mask;      // bit 0 / 1: a complex64 / packed FP16 signal takes the 16-row form;
                            // bit 2 / 3: the 16-column form
-  int32_t any_noisy0;      // some noisy tree signal's level-0 range exceeds kEnumLaneBlocks blocks
+  int32_t any_noisy0;      // some noisy tree signal's level-0 range exceeds kEnumLaneBlocks blocks (teams)
   int32_t any_noisy;       // some noisy tree signal has subtree candidate ranges longer than
-                           // its enum_share blocks (wave-shared enumeration compiled in)
+                           // its enum_share blocks (team enumeration compiled in)
   int32_t gather_u;        // gather loads in flight per thread (2, 4 or 8)
   int32_t deep_lds;        // dynamic LDS bytes of the deep resolution (largest L x 8), 0: none
   int32_t l0_lds;          // dynamic LDS bytes of the level-0 transform (largest tile x D)

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(kJumpMax) void k_jump_resolve(LaunchCtx c, int leve
       if (k == 0) any_open = 0;
       __syncthreads();
       {
-        // every thread takes part (the noisy enumeration is shared by the wave)
+        // every thread takes part (the noisy enumeration may run in teams of the wave's lanes)
         const bool act = k < nq && open_cur[k];
         double2 Y[NMAX];
 #pragma unroll

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
       for (int i = 0; i < NMAX; i++)
         if (i < n) Y[i] = to_d(Y0[(int64_t)i * B + cc]);
     }
-    // every lane of the work-group takes part (the noisy enumeration is shared by the wave)
+    // every lane of the work-group takes part (the noisy enumeration may run in teams of the wave's lanes)
     v = classify<NMAX, true, F32, WAVE>(Y, d, n, d.R, cc, B, sref2, nv, valid);
     const int nf = !valid ? 0 : (v.cls == kSingle ? 1 : (v.cls == kDouble ? 2 : 0));
     const int fs = wave_append_n(&c.st[s].found, nf);

@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void k_children(LaunchCtx c, int level) {
   const int par = (level - 1) & 1, cur = level & 1;
   const int32_t *pc = c.A.pre + 2 * (c.nsig + 1);
   const int total = pc[c.nsig];
-  // whole work-groups step together (the noisy enumeration is shared by the wave)
+  // whole work-groups step together (the noisy enumeration may run in teams of the wave's lanes)
   for (int g0 = blockIdx.x * blockDim.x; g0 < total; g0 += gridDim.x * blockDim.x) {
     const bool act = g0 + (int)threadIdx.x < total;
     const int g = act ? g0 + (int)threadIdx.x : g0;

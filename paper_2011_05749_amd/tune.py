@@ -15,9 +15,9 @@ not what it computes:
   less LDS per work-group, so more work-groups share a CU);
 * gather_unroll: samples each thread has in flight in the strided gathers
   (2, 4 or 8 load batches per thread);
-* enum_share (noisy mode): from how many blocks of 32 candidates on a class's
-  enumeration (Sect. 3.1, Method 2) is shared by the 64 lanes of its wave
-  instead of walked by its own lane.
+* enum_share (noisy mode): from how many blocks of 32 candidates on the
+  subtree levels' enumerations (Sect. 3.1, Method 2) run in teams of a wave's
+  lanes instead of one lane a class.
 
 Each candidate runs a captured batch of synthetic signals of the shape
 (random K-sparse spectra, unit magnitudes, generated on the device) and the
@@ -104,8 +104,8 @@ def default_knobs(B0, delays, l1_eligible) -> dict:
 
 def candidates(N, B0, delays, l1_eligible, mode=0):
     """Knob settings tried for a shape (each a dict of Plan keywords), the
-    default first; noisy shapes also try the wave-shared enumeration from
-    fewer candidate blocks on (enum_share)."""
+    default first; noisy shapes also try the team enumeration from other
+    range lengths on (enum_share)."""
     lgB = int(B0).bit_length() - 1
     top = min(lgB, 13 - (0 if delays <= 1 else (1 if delays <= 2 else 2)))
     tiles = sorted({t for t in (top, top - 1, top - 2) if t >= 5}, reverse=True) or [top]

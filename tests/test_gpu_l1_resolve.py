@@ -239,7 +239,7 @@ def test_col_forms_batch_mixed(sfft):
 
 
 def test_enum_share_changes_nothing(sfft):
-    """Noisy solves with the enumeration shared by the wave from 1, 2, 16 or
+    """Noisy solves with the enumeration in teams of lanes from 1, 2, 16 or
     64 blocks of 32 candidates on: every candidate's statistic is the same
     number, so indices and values are identical, and equal to the oracle."""
     N, K, B0 = 2 ** 18, 160, 512
@@ -257,3 +257,32 @@ def test_enum_share_changes_nothing(sfft):
         assert o[2] == outs[0][2]
     g, o = solve_both(sfft, x, N, K, 4, 2, seed=77, B0=B0, mode=1, enum_share=1)
     assert_parity(g, o)
+
+
+def test_open_list_overflow_reports_partial(sfft):
+    """200 tones in one level-0 class (N = 2^20, B0 = 512, L = 2048), in 100
+    pairs 1024 positions apart whose members share their low 10 bits, the pairs
+    with distinct residues mod 128: from depth 7 to depth 10 each pair is a
+    multi-ton subclass of its own, so every depth there needs 200 open
+    subclasses next, more than the resolution's open list holds (128).  The
+    GPU reports PARTIAL and returns only planted tones, each with its value;
+    the oracle, which keeps no such list, resolves all."""
+    N, B0, c = 2 ** 20, 512, 37
+    rng = np.random.default_rng(5)
+    res = np.sort(rng.choice(128, size=100, replace=False))
+    r = res + 128 * rng.integers(0, 8, size=100)
+    ks = np.concatenate([r, r + 1024])
+    support = np.sort(c + B0 * ks)
+    assert len(np.unique(support)) == 200
+    sp = siggen.make_spec(N, 200, 3, support=support)
+    x = siggen.synth(sp)
+    g, o = solve_both(sfft, x, N, 200, 4, 2, seed=3, B0=B0)
+    gi, gv, gc, st = g
+    oi, ov, oc, tr = o
+    assert tr.status == 0 and oc == 200          # the oracle resolves every tone
+    assert st["status"] == sfft.STATUS_PARTIAL   # the GPU's open list overflowed
+    got = gi[gi >= 0]
+    assert 0 < len(got) < 200 and set(got.tolist()) <= set(support.tolist())
+    truth = dict(zip(sp.support.tolist(), sp.values.tolist()))
+    for f, v in zip(got.tolist(), gv[gi >= 0].tolist()):
+        assert abs(v - truth[f]) <= 1e-4 * abs(truth[f])

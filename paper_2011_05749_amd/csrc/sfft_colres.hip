@@ -67,10 +67,12 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
     const float2 *M = c.A.jcol + d.jc_off + (int64_t)jslot * (int64_t)L;
     const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
     int nopen = valid ? 2 : 0;
+    int deepest = 0;  // the class's deepest classified level (one atomic per class, at its end)
     __syncthreads();  // the previous classes are done with the lists
     if (gl < 2) open_cur[g][gl] = gl;
     if (gl == 0) dmask[g] = 0;
     for (int dd = 1; __any(nopen > 0); dd++) {
+      if (nopen > 0) deepest = dd;
       const int nq = 1 << dd;
       const int64_t Bd = d.B0 << dd;
       const uint64_t Ld = L >> dd;
@@ -143,16 +145,20 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
 #pragma unroll
           for (int i = 0; i < NMAX; i++) Y[i] = act && i < n ? Ys[g][gl][i] : make_double2(0.0, 0.0);
           const Decision v = classify<NMAX, true, F32, WAVE>(Y, d, n, d.R, cs, Bd, sref2, nv, act);
+          // found entries: one reservation for the wave when its classes belong
+          // to one signal (almost always), else one per lane
+          const int nf = !act ? 0 : (v.cls == kSingle ? 1 : (v.cls == kDouble ? 2 : 0));
+          const int s0 = __shfl(s, 0);
+          int fs;
+          if (__ballot(act && s != s0) == 0ull) {
+            fs = wave_append_n(&c.st[s0].found, nf);
+          } else {
+            fs = nf > 0 ? atomicAdd(&c.st[s].found, nf) : 0;
+          }
+          if (nf >= 1) push_found(c, s, d, fs, v.f, v.a);
+          if (nf == 2) push_found(c, s, d, fs + 1, v.f2, v.a2);
           if (act) {
-            atomicMax(&c.st[s].levels, dd);
-            if (v.cls == kSingle) {
-              const int fs = atomicAdd(&c.st[s].found, 1);
-              push_found(c, s, d, fs, v.f, v.a);
-            } else if (v.cls == kDouble) {
-              const int fs = atomicAdd(&c.st[s].found, 2);
-              push_found(c, s, d, fs, v.f, v.a);
-              push_found(c, s, d, fs + 1, v.f2, v.a2);
-            } else if (v.cls == kMulti) {
+            if (v.cls == kMulti) {
               if (Ld >= 2 && dd + 1 <= d.max_levels && dd == d.col_dz) {
                 // the children go to the deep resolution
                 atomicOr(&dmask[g], (1ull << k) | (1ull << (k + nq)));
@@ -176,6 +182,7 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
       for (int k = gl; k < nopen; k += GS) open_cur[g][k] = open_nxt[g][k];
       __syncthreads();
     }
+    if (valid && gl == 0 && deepest > 0) atomicMax(&c.st[s].levels, deepest);
     if (valid && gl == 0 && dmask[g] != 0) {
       c.A.deep_mask[d.multi_off + jslot] = dmask[g];
       c.A.deep_list[atomicAdd(c.A.deep_count, 1)] = make_int2(s, jslot);

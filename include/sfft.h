@@ -193,6 +193,13 @@ typedef struct {
                               outside).  A launch-shape knob: every candidate's
                               statistic is the same number either way, so results are
                               unchanged */
+  int32_t l0_spread;       /* tree, noisy mode, level 0: lanes each class of the level-0
+                              classification takes (1, 2, 4 or 8; 64 / it classes a wave),
+                              the extra lanes joining the team enumeration; 0 = the
+                              batch's choice: doubled from 1, up to 4, while the noisy
+                              classes with ranges over enum_share blocks would fill at
+                              most 8192 waves.  A batch takes the largest value its tree
+                              plans fix (SFFT_EINVAL outside).  Results are unchanged */
 } sfft_params_t;
 
 /* Read-only description of a plan (what the kernels will compute). */
@@ -225,6 +232,7 @@ typedef struct {
   int32_t gather_unroll;   /* gather loads in flight per thread */
   int32_t col_form;        /* column-pass form in use (1, 2 or 3; 0 without the pass) */
   int32_t enum_share;      /* team enumeration above this many 32-candidate blocks */
+  int32_t l0_spread;       /* level-0 lanes per class as set (0: the batch's choice) */
 } sfft_plan_info_t;
 
 /* Per-signal statistics of the last exec (host copy, see sfft_exec_stats). */

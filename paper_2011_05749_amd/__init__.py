@@ -63,6 +63,7 @@ class Params(ctypes.Structure):
         ("sample_format", ctypes.c_int32),
         ("fft_tile_lg", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
         ("col_form", ctypes.c_int32), ("enum_share", ctypes.c_int32),
+        ("l0_spread", ctypes.c_int32),
     ]
 
 
@@ -91,6 +92,7 @@ class PlanInfo(ctypes.Structure):
         ("sample_format", ctypes.c_int32),
         ("fft_tile_lg", ctypes.c_int32), ("gather_unroll", ctypes.c_int32),
         ("col_form", ctypes.c_int32), ("enum_share", ctypes.c_int32),
+        ("l0_spread", ctypes.c_int32),
     ]
 
 

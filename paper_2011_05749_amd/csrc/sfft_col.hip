@@ -583,7 +583,9 @@ __device__ __forceinline__ float2 rot64(float2 v, int k) {
 // values; thread (t, k') of a half (k1 = 2 k' + half) stores its open classes
 // from registers, 16 lanes writing one 128-byte run.  The registers a half
 // frees take the next item's rows: q < 16 after the even write, then a quarter
-// after the even stores, after the odd write and after the odd stores.  LDS slot of
+// after the even stores, after the odd write and after the odd stores; the odd
+// k1's 32-point DFT over q runs after the even stores, so that the rows of
+// two quarters are in flight meanwhile.  LDS slot of
 // (t, k', p): t ST + k' SK + p, ST = 2 mod 32 and SK = 33, so that the
 // 8-byte accesses of every 32 lanes fall on distinct bank pairs both ways.
 // Persistent work-groups, each walking a contiguous range of items.
@@ -700,10 +702,10 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
       v[j + 32] = rot64(make_float2(a.x - b.x, a.y - b.y), j);
     }
     __builtin_amdgcn_sched_barrier(0);
-    // ... then the 32-point DFTs of the even (v[0..31]) and odd (v[32..63]) k1:
-    // v[h 32 + i] = X[k1 = 2 bitrev5(i) + h]
+    // ... then the 32-point DFT of the even k1 (v[0..31]); the odd k1's
+    // (v[32..63]) waits until the even half is out, with the next item's
+    // first rows in flight: v[h 32 + i] = X[k1 = 2 bitrev5(i) + h]
     dft_reg<5>(v);
-    dft_reg<5>(v + 32);
     __syncthreads();  // the previous item is done with E and slot_of
 #pragma unroll
     for (int i = 0; i < 32; i++) {
@@ -733,6 +735,8 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
 #pragma unroll
     for (int half = 0; half < 2; half++) {
       if (half == 1) {
+        dft_reg<5>(v + 32);
+        __builtin_amdgcn_sched_barrier(0);
         __syncthreads();  // the even half's reads of E are done
 #pragma unroll
         for (int i = 0; i < 32; i++) {

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
     static_assert(sizeof(Ys) >= sizeof(float2) * (kFftMax / 2), "FFT twiddles fit the vectors' space");
     for (int m = tid; m < (L >> 1); m += blockDim.x) twf[m] = c.A.tw[m << (kLog2FftMax - lgL)];
     for (int t = tid; t < L; t += blockDim.x)
-      Zs[bitrev((uint32_t)t, lgL)] = cmulf(ldg(M + t), unit_n((cpar * (uint64_t)t) & (N - 1), d));
+      Zs[bitrev((uint32_t)t, lgL)] = cmulf(ldg(M + t), unit_nl((cpar * (uint64_t)t) & (N - 1), (uint64_t)N, d.log2N));
     const int lgLt = lgL - d.col_dz - 1;  // <= 7 (L <= 8192, Dz = 5)
     for (int m = tid; m < (1 << lgLt); m += blockDim.x) twd[m] = c.A.tw[m << (kLog2FftMax - lgLt)];
     if (tid == 0) {

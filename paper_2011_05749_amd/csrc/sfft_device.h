@@ -435,29 +435,49 @@ __device__ __forceinline__ void two_ton(const double2 (&Y)[NMAX], const SigDesc 
   v.a2 = a1;
 }
 
+// the enumeration's per-class constants: N, its log2 (-1 when N is not a
+// power of two) and the delays tau_i mod N (< N <= 2^30), read from the
+// descriptor once per class rather than at every block
+template <int NMAX>
+struct EnumSig {
+  uint64_t N;
+  int lgN;
+  uint32_t tau[NMAX];
+};
+
+__device__ __forceinline__ uint64_t mod_nl(uint64_t v, uint64_t N, int lgN) {
+  return lgN >= 0 ? (v & (N - 1)) : v % N;
+}
+
+// e^{-2 pi i t / N} for an exact integer t < N, in FP32: from the exact FP32
+// ratio 2t/N when N is a power of two up to 2^24, else through FP64
+__device__ __forceinline__ float2 unit_nl(uint64_t t, uint64_t N, int lgN) {
+  if (lgN >= 0 && lgN <= 24) return unit_f(t, N);
+  const double2 u = unit_d(t, N, -1);
+  return make_float2((float)u.x, (float)u.y);
+}
+
+// the class's constants and the step e^{-2 pi i B tau_i / N} between
+// consecutive candidates c + kB
+template <int NMAX, bool TREE>
+__device__ __forceinline__ void enum_prep(const SigDesc &d, int n, int64_t B, EnumSig<NMAX> &es,
+                                          float2 (&st)[NMAX]) {
+  es.N = (uint64_t)d.N;
+  es.lgN = d.log2N;
+#pragma unroll
+  for (int i = 0; i < NMAX; i++) es.tau[i] = i < n ? (uint32_t)tau_of<TREE>(d, i) : 0u;
+#pragma unroll
+  for (int i = 0; i < NMAX; i++)
+    st[i] = i < n ? unit_nl(mod_nl((uint64_t)B * es.tau[i], es.N, es.lgN), es.N, es.lgN) : make_float2(0.f, 0.f);
+}
+
 // One block of the noisy-mode enumeration (Sect. 3.1, Method 2): the
 // matched filter |sum_i Y_i e^{-2 pi i (c + kB) tau_i / N}| of the
 // candidates k = lo + o0 + o (mod L), o < min(32, cnt - o0), in FP32 MACs
 // with the twiddles anchored exactly at the block's first candidate; folds
 // them into (best, bestk): the largest statistic, ties to the smaller k.
-// e^{-2 pi i t / N} for an exact integer t < N, in FP32: from the exact FP32
-// ratio 2t/N when N is a power of two up to 2^24, else through FP64
-__device__ __forceinline__ float2 unit_n(uint64_t t, const SigDesc &d) {
-  if (d.log2N >= 0 && d.log2N <= 24) return unit_f(t, (uint64_t)d.N);
-  const double2 u = unit_d(t, (uint64_t)d.N, -1);
-  return make_float2((float)u.x, (float)u.y);
-}
-
-// the step e^{-2 pi i B tau_i / N} between consecutive candidates c + kB
-template <int NMAX, bool TREE>
-__device__ __forceinline__ void enum_steps(const SigDesc &d, int n, int64_t B, float2 (&st)[NMAX]) {
-#pragma unroll
-  for (int i = 0; i < NMAX; i++)
-    st[i] = i < n ? unit_n(mod_n(mod_n((uint64_t)B * tau_of<TREE>(d, i), d), d), d) : make_float2(0.f, 0.f);
-}
-
-template <int NMAX, bool TREE>
-__device__ __forceinline__ void enum_block(const float2 (&Yf)[NMAX], const float2 (&st)[NMAX], const SigDesc &d,
+template <int NMAX>
+__device__ __forceinline__ void enum_block(const float2 (&Yf)[NMAX], const float2 (&st)[NMAX], const EnumSig<NMAX> &es,
                                            int n, int64_t c, int64_t B, int64_t L, int64_t lo, int64_t cnt,
                                            int64_t o0, float &best, int64_t &bestk) {
   float2 tw[NMAX];
@@ -465,7 +485,7 @@ __device__ __forceinline__ void enum_block(const float2 (&Yf)[NMAX], const float
   const uint64_t f0 = (uint64_t)(c + k0 * B);
 #pragma unroll
   for (int i = 0; i < NMAX; i++)
-    if (i < n) tw[i] = unit_n(mod_n(f0 * tau_of<TREE>(d, i), d), d);
+    if (i < n) tw[i] = unit_nl(mod_nl(f0 * es.tau[i], es.N, es.lgN), es.N, es.lgN);
   const int64_t lim = (cnt - o0) < 32 ? (cnt - o0) : 32;
   for (int64_t o = 0; o < lim; o++) {
     float gx = 0.f, gy = 0.f;
@@ -524,9 +544,9 @@ __device__ int64_t enum_team(bool need, const float2 (&Yf)[NMAX], const SigDesc 
     if (need) {
       const int64_t L = dp->N / B;
       float2 st[NMAX];
-      enum_steps<NMAX, TREE>(*dp, n, B, st);
-      for (int64_t o0 = 0; o0 < cnt; o0 += 32)
-        enum_block<NMAX, TREE>(Yf, st, *dp, n, c, B, L, lo, cnt, o0, best, bestk);
+      EnumSig<NMAX> es;
+      enum_prep<NMAX, TREE>(*dp, n, B, es, st);
+      for (int64_t o0 = 0; o0 < cnt; o0 += 32) enum_block<NMAX>(Yf, st, es, n, c, B, L, lo, cnt, o0, best, bestk);
     }
     return bestk;
   }
@@ -553,9 +573,10 @@ __device__ int64_t enum_team(bool need, const float2 (&Yf)[NMAX], const SigDesc 
     const int64_t L = dj.N / Bj;
     const int64_t nblk = (cntj + 31) >> 5;
     float2 st[NMAX];
-    enum_steps<NMAX, TREE>(dj, nj, Bj, st);
+    EnumSig<NMAX> es;
+    enum_prep<NMAX, TREE>(dj, nj, Bj, es, st);
     for (int64_t b = mem; b < nblk; b += T)
-      enum_block<NMAX, TREE>(Yj, st, dj, nj, cj, Bj, L, loj, cntj, b << 5, best, bestk);
+      enum_block<NMAX>(Yj, st, es, nj, cj, Bj, L, loj, cntj, b << 5, best, bestk);
   }
   for (int m = 1; m < T; m <<= 1) {
     const float ob = __shfl_xor(best, m);
@@ -694,9 +715,9 @@ __device__ Decision classify(const double2 (&Y)[NMAX], const SigDesc &d, int n, 
       float best = -1.0f;
       int64_t bestk = 0;
       float2 st[NMAX];
-      enum_steps<NMAX, TREE>(d, n, B, st);
-      for (int64_t o0 = 0; o0 < cnt; o0 += 32)
-        enum_block<NMAX, TREE>(Yf, st, d, n, c, B, L, lo, cnt, o0, best, bestk);
+      EnumSig<NMAX> es;
+      enum_prep<NMAX, TREE>(d, n, B, es, st);
+      for (int64_t o0 = 0; o0 < cnt; o0 += 32) enum_block<NMAX>(Yf, st, es, n, c, B, L, lo, cnt, o0, best, bestk);
       k = bestk;
     }
   }

@@ -247,11 +247,40 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     acc0 += Y.desc[t.second].R;
   }
   Y.lists.push_back(acc0);
+  // level-0 classification: lanes per class.  The team enumeration is
+  // compiled in where some noisy class's candidate range is longer than its
+  // plan's enum_share blocks of 32; the classes are then spread over 2^lg
+  // lanes (64 >> lg classes a wave), doubled up to kL0SpreadAuto while such
+  // classes fill at most kL0SpreadWaves waves -- a small batch then
+  // enumerates on every SIMD, each class by a team -- unless a plan fixes it
+  {
+    int64_t nclass = 0;
+    int req = 0;
+    for (auto &t : tree) {
+      const SigDesc &d = Y.desc[t.second];
+      req = std::max(req, ps[t.second]->info.l0_spread);
+      if (d.mode != SFFT_NOISY) continue;
+      const int64_t L0 = d.N >> d.log2B0;
+      const int64_t cnt = (d.window > 0 && d.D >= 2 && 2 * (int64_t)d.window + 1 < L0) ? 2 * (int64_t)d.window + 1 : L0;
+      if (((cnt + 31) >> 5) > d.enum_lane_blocks) {
+        Y.any_noisy0 = 1;
+        nclass += d.B0;
+      }
+    }
+    int sp = req;
+    if (sp == 0) {
+      sp = 1;
+      while (nclass > 0 && sp < kL0SpreadAuto && nclass * 2 * sp <= (int64_t)kL0SpreadWaves * 64) sp *= 2;
+    }
+    Y.l0_spread_lg = ilog2(sp);
+    if (sp > 1) Y.any_noisy0 = 1;
+  }
   Y.l0c_at = Y.lists.size();
   int32_t acc1 = 0;
+  const int64_t per_item = kThreads >> Y.l0_spread_lg;
   for (auto &t : tree) {
     Y.lists.push_back(acc1);
-    acc1 += (int32_t)((Y.desc[t.second].B0 + kThreads - 1) / kThreads);
+    acc1 += (int32_t)((Y.desc[t.second].B0 + per_item - 1) / per_item);
   }
   Y.lists.push_back(acc1);
   Y.lists.push_back(0);
@@ -273,14 +302,10 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     if (d.l1 && ps[s]->info.col_form == 2) Y.col16_mask |= d.fp16 ? 2 : 1;
     else if (d.l1 && ps[s]->info.col_form == 3) Y.col16_mask |= d.fp16 ? 8 : 4;
     else if (d.l1) (d.fp16 ? Y.col_f16_mask : Y.col_lp_mask) |= 1 << (d.log2B0 - 9);  // bit LP - 4, B0 = 2^(LP + 5)
-    // the team enumeration is compiled in only where some noisy class has a
-    // candidate range longer than one lane keeps: at level 0 (the longest
-    // ranges, every non-empty class of a wave enumerating side by side) past
-    // kEnumLaneBlocks blocks, below it past the plan's enum_share
+    // the team enumeration below level 0 is compiled in only where some noisy
+    // class has a candidate range longer than its plan's enum_share blocks
     if (d.kind == SFFT_KIND_TREE && d.mode == SFFT_NOISY) {
       const int64_t L0 = d.N >> d.log2B0;
-      const int64_t cnt = (d.window > 0 && d.D >= 2 && 2 * (int64_t)d.window + 1 < L0) ? 2 * (int64_t)d.window + 1 : L0;
-      if (((cnt + 31) >> 5) > kEnumLaneBlocks) Y.any_noisy0 = 1;
       // the subtree levels' ranges: L0 / 2 candidates at level 1 (a window, if
       // any, is the same at every level)
       const int64_t cnt1 = (d.window > 0 && d.D >= 2 && 2 * (int64_t)d.window + 1 < L0 / 2) ? 2 * (int64_t)d.window + 1 : L0 / 2;
@@ -422,6 +447,7 @@ void bind_layout(const Layout &Y, char *base, const float2 *tw, LaunchCtx &c) {
   c.col_f16_mask = Y.col_f16_mask;
   c.col16_mask = Y.col16_mask;
   c.any_noisy0 = Y.any_noisy0;
+  c.l0_spread_lg = Y.l0_spread_lg;
   c.any_noisy = Y.any_noisy;
   c.gather_u = Y.gather_u;
   c.l0_lds = Y.l0_lds;
@@ -647,6 +673,8 @@ int32_t validate_and_fill(const sfft_params_t *pp, sfft_plan_s *pl) {
     if (p.col_form < 0 || p.col_form > 3 || (p.col_form >= 2 && B0 != 2048)) return SFFT_EINVAL;
     if (p.enum_share < 0 || p.enum_share > kEnumLaneBlocks) return SFFT_EINVAL;
     in.enum_share = p.enum_share ? p.enum_share : kEnumShareDefault;
+    if (p.l0_spread < 0 || p.l0_spread > kL0SpreadMax || (p.l0_spread & (p.l0_spread - 1))) return SFFT_EINVAL;
+    in.l0_spread = p.l0_spread;
     // the library's choice: the 16-column form at B0 = 2048, the 32-row form elsewhere
     in.col_form = in.l1_resolve ? (p.col_form > 0 ? p.col_form : (B0 == 2048 ? 3 : 1)) : 0;
     SplitMix64 g{p.seed};

@@ -35,10 +35,13 @@ constexpr int kColGroup = 1 << kColGroupLg;
 constexpr int kColLaneDepth = 5;    // ... one lane per class-vector sum down to this depth
 constexpr int kDeepNodes = 512;     // deep resolution: subtree nodes classified per round
 constexpr int kDeepTw = 128;        // ... its twiddle table: L / 2^(Dz + 1) <= 8192 / 64 entries
-constexpr int kEnumLaneBlocks = 64; // noisy enumeration at level 0: a batch whose ranges are at most this many
-                                    // blocks of 32 candidates enumerates one lane a class, else in
-                                    // teams of lanes (also the largest value of a plan's enum_share)
-constexpr int kEnumShareDefault = 4; // ... at the subtree levels, unless the plan says otherwise
+constexpr int kEnumLaneBlocks = 64; // largest value of a plan's enum_share: noisy classes whose candidate
+                                    // ranges are at most that many blocks of 32 enumerate one lane a
+                                    // class, longer ones in teams of lanes
+constexpr int kEnumShareDefault = 4; // ... unless the plan says otherwise
+constexpr int kL0SpreadMax = 8;      // level-0 classification: at most this many lanes per class
+constexpr int kL0SpreadAuto = 4;     // ... the batch's own choice: doubled up to this while the
+constexpr int kL0SpreadWaves = 8192; // noisy classes fill at most this many waves (eight per SIMD)
 constexpr size_t kNoAllocScratchBytes = (size_t)SFFT_NOALLOC_SCRATCH_MIB << 20;
 constexpr size_t kNoAllocTwBytes = 64 * 1024;  // twiddle table at the scratch's start
 
@@ -144,8 +147,9 @@ struct LaunchCtx {
   const int32_t *tree_list;
   const int32_t *ffast_list;
   const int32_t *l0_pre;   // prefix over tree_list of the rounds (level-0 FFT items)
-  const int32_t *l0c_pre;  // prefix over tree_list of ceil(B0 / 256) (classify items)
+  const int32_t *l0c_pre;  // prefix over tree_list of ceil(B0 / (256 >> l0_spread_lg)) (classify items)
   int32_t l0_items, l0c_items;
+  int32_t l0_spread_lg;    // level-0 classification: log2 of the lanes per class (64 >> it classes a wave)
   int32_t any_wide_jump;   // some signal may run the dense pass on the matrix cores (L' >= 32)
   int32_t jstride;         // dense-pass coefficients per multi-ton slot (kJumpMax)
   int32_t jrows;           // rows per dense-pass work item (power of two)
@@ -154,7 +158,8 @@ struct LaunchCtx {
   int32_t col_f16_mask;    // ... for signals stored in the packed FP16 form
   int32_t col16_mask;      // bit 0 / 1: a complex64 / packed FP16 signal takes the 16-row form;
                            // bit 2 / 3: the 16-column form
-  int32_t any_noisy0;      // some noisy tree signal's level-0 range exceeds kEnumLaneBlocks blocks (teams)
+  int32_t any_noisy0;      // some noisy tree signal's level-0 range exceeds its enum_share blocks, or
+                           // the classes are spread over several lanes (team enumeration compiled in)
   int32_t any_noisy;       // some noisy tree signal has subtree candidate ranges longer than
                            // its enum_share blocks (team enumeration compiled in)
   int32_t gather_u;        // gather loads in flight per thread (2, 4 or 8)

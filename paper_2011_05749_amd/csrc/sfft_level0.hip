@@ -109,10 +109,13 @@ __global__ __launch_bounds__(kThreads) void k_level0_stats(LaunchCtx c) {
 }
 
 // Classification of the B0 level-0 classes (Sect. 3.2, Subproblems 1-2):
-// item = (signal, 256 classes); single-tons and multi-tons are compacted by
-// wave ballot + prefix, one atomic per wave and list.
+// item = (signal, 256 >> lg classes), 64 >> lg a wave on its first lanes (lg
+// = l0_spread_lg: the other lanes only join the team enumeration); single-tons
+// and multi-tons are compacted by wave ballot + prefix, one atomic per wave
+// and list.  Registers are capped for two waves a SIMD (the instance with the
+// team enumeration would otherwise take more and run one).
 template <int NMAX, bool F32, bool WAVE>
-__global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
+__global__ __launch_bounds__(kThreads, 2) void k_level0_classify(LaunchCtx c) {
   for (int item = blockIdx.x; item < c.l0c_items; item += gridDim.x) {
     const int li = find_owner(c.l0c_pre, c.ntree, item);
     const int s = c.tree_list[li];
@@ -122,8 +125,12 @@ __global__ __launch_bounds__(kThreads) void k_level0_classify(LaunchCtx c) {
     const int n = d.n;
     const float2 *Y0 = c.A.y0 + d.y0_off;
     const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
-    const int64_t cc = (int64_t)(item - c.l0c_pre[li]) * kThreads + threadIdx.x;
-    const bool valid = cc < B;
+    // 64 >> lg classes a wave, on its first lanes; the rest of the wave joins
+    // the team enumeration only
+    const int lg = c.l0_spread_lg;
+    const int lane = threadIdx.x & 63, cpw = 64 >> lg;
+    const int64_t cc = (int64_t)(item - c.l0c_pre[li]) * (kThreads >> lg) + (threadIdx.x >> 6) * cpw + lane;
+    const bool valid = lane < cpw && cc < B;
     Decision v;
     v.cls = kZero;
     double2 Y[NMAX];

@@ -17,7 +17,9 @@ not what it computes:
   (2, 4 or 8 load batches per thread);
 * enum_share (noisy mode): from how many blocks of 32 candidates on the
   subtree levels' enumerations (Sect. 3.1, Method 2) run in teams of a wave's
-  lanes instead of one lane a class.
+  lanes instead of one lane a class; l0_spread (noisy mode): lanes per
+  class of the level-0 classification (1 .. 8; the extra lanes join the
+  teams).
 
 Each candidate runs a captured batch of synthetic signals of the shape
 (random K-sparse spectra, unit magnitudes, generated on the device) and the
@@ -105,7 +107,7 @@ def default_knobs(B0, delays, l1_eligible) -> dict:
 def candidates(N, B0, delays, l1_eligible, mode=0):
     """Knob settings tried for a shape (each a dict of Plan keywords), the
     default first; noisy shapes also try the team enumeration from other
-    range lengths on (enum_share)."""
+    range lengths on (enum_share) and other level-0 spreads (l0_spread)."""
     lgB = int(B0).bit_length() - 1
     top = min(lgB, 13 - (0 if delays <= 1 else (1 if delays <= 2 else 2)))
     tiles = sorted({t for t in (top, top - 1, top - 2) if t >= 5}, reverse=True) or [top]
@@ -119,6 +121,7 @@ def candidates(N, B0, delays, l1_eligible, mode=0):
             out.append(c)
     if mode in (1, "noisy"):
         out += [{**out[0], "enum_share": e} for e in (64, 16, 1)]
+        out += [{**out[0], "l0_spread": sp} for sp in (1, 2, 4, 8)]
     return out
 
 

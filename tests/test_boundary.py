@@ -202,6 +202,16 @@ def test_enum_share_bounds():
             sfft.Plan(2 ** 20, 300, 2, 2, B0=512, mode="noisy", enum_share=bad)
 
 
+def test_l0_spread_bounds():
+    """Level-0 lanes per class: 1, 2, 4 or 8, 0 = the batch's choice."""
+    assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512, mode="noisy").info.l0_spread == 0
+    for ok in (1, 2, 4, 8):
+        assert sfft.Plan(2 ** 20, 300, 2, 2, B0=512, mode="noisy", l0_spread=ok).info.l0_spread == ok
+    for bad in (-1, 3, 6, 16):
+        with pytest.raises(sfft.SfftError):
+            sfft.Plan(2 ** 20, 300, 2, 2, B0=512, mode="noisy", l0_spread=bad)
+
+
 def test_one_hip_runtime_per_process():
     """Importing the binding maps exactly one HIP and one HSA runtime: the
     library's runtime dependency binds to the copy torch already loaded (two

@@ -259,6 +259,28 @@ def test_enum_share_changes_nothing(sfft):
     assert_parity(g, o)
 
 
+def test_l0_spread_changes_nothing(sfft):
+    """Noisy solves with the level-0 classes spread over 1, 2, 4 or 8 lanes
+    each (64, 32, 16 or 8 classes a wave; the extra lanes join the team
+    enumeration): indices and values are identical at every spread and under
+    the batch's own choice, and equal to the oracle."""
+    N, K, B0 = 2 ** 18, 160, 512
+    x = siggen.synth(siggen.make_spec(N, K, 78, snr_db=20.0))
+    xd = to_dev(x)
+    outs = []
+    for sp in (1, 2, 4, 8, 0):
+        p = sfft.Plan(N, K, 4, 2, seed=78, B0=B0, mode=1, enum_share=2, l0_spread=sp)
+        assert p.info.l0_spread == sp
+        idx, val, cnt = p.exec(xd)
+        outs.append((idx.cpu().numpy(), val.cpu().numpy(), cnt))
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o[0], outs[0][0])
+        np.testing.assert_array_equal(o[1], outs[0][1])
+        assert o[2] == outs[0][2]
+    g, o = solve_both(sfft, x, N, K, 4, 2, seed=78, B0=B0, mode=1, enum_share=2, l0_spread=8)
+    assert_parity(g, o)
+
+
 def test_open_list_overflow_reports_partial(sfft):
     """200 tones in one level-0 class (N = 2^20, B0 = 512, L = 2048), in 100
     pairs 1024 positions apart whose members share their low 10 bits, the pairs

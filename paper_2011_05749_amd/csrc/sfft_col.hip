@@ -87,14 +87,6 @@ __device__ __forceinline__ void rows_in() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// Uniform values that no kernel writes while the reader runs, read through
-// the constant address space so that they come in by scalar loads (which do
-// not wait behind the vector loads in flight).
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const T *p) {
-  return (const __attribute__((address_space(4))) T *)p;
-}
-
 // Level-1 column pass (power-of-two N, B0 = 32 P, P = 2^LP in {16, 32, 64, 128, 256}):
 // viewing x as B0 rows m of L = N/B0 samples, class c's coefficients
 //   M_c(t) = sum_{m < B0} x[m L + t] e^{-2 pi i c m / B0},   t < L

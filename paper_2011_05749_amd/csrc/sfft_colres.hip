@@ -51,21 +51,24 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
   __shared__ int deep[64];
   __shared__ int n_deep;
   __shared__ unsigned long long dmask[CPW];  // open subclasses at depth col_dz + 1
-  const int32_t *pr = c.A.pre + 6 * (c.nsig + 1);
+  static_assert(CPW == kColResolveAlign, "a wave's classes are one aligned group");
+  const __attribute__((address_space(4))) int32_t *pr = cst(c.A.pre + 6 * (c.nsig + 1));
   const int total = pr[c.nsig];
   const int lane = threadIdx.x, g = lane >> LGS, gl = lane & (GS - 1);
   for (int base = blockIdx.x * CPW; base < total; base += gridDim.x * CPW) {
-    const int item = base + g;
-    const bool valid = item < total;
-    const int s = valid ? find_owner(pr, c.nsig, item) : 0;
-    const int jslot = valid ? item - pr[s] : 0;
-    const SigDesc &d = c.desc[s];
+    // each signal's classes are padded to whole groups of CPW, so that the
+    // wave's all belong to one signal, its descriptor read by scalar loads
+    const int s = find_owner(pr, c.nsig, base);
+    const SigDesc &d = *(const SigDesc *)&cst(c.desc)[s];
+    const int jslot = base + g - pr[s];
+    const int mcnt = cst(c.st)[s].multi[0];
+    const bool valid = jslot < (mcnt < d.multi_cap ? mcnt : d.multi_cap);
     const uint64_t N = (uint64_t)d.N;
     const int n = valid ? d.n : 0;
     const uint64_t L = N >> d.log2B0;
     const uint64_t cpar = valid ? (uint64_t)c.A.multi_c[0][d.multi_off + jslot] : 0;
     const float2 *M = c.A.jcol + d.jc_off + (int64_t)jslot * (int64_t)L;
-    const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
+    const double sref2 = cst(c.st)[s].sref2, nv = cst(c.st)[s].noise_var;
     int nopen = valid ? 2 : 0;
     int deepest = 0;  // the class's deepest classified level (one atomic per class, at its end)
     __syncthreads();  // the previous classes are done with the lists
@@ -145,16 +148,9 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
 #pragma unroll
           for (int i = 0; i < NMAX; i++) Y[i] = act && i < n ? Ys[g][gl][i] : make_double2(0.0, 0.0);
           const Decision v = classify<NMAX, true, F32, WAVE>(Y, d, n, d.R, cs, Bd, sref2, nv, act);
-          // found entries: one reservation for the wave when its classes belong
-          // to one signal (almost always), else one per lane
+          // found entries: one reservation for the wave (its classes share a signal)
           const int nf = !act ? 0 : (v.cls == kSingle ? 1 : (v.cls == kDouble ? 2 : 0));
-          const int s0 = __shfl(s, 0);
-          int fs;
-          if (__ballot(act && s != s0) == 0ull) {
-            fs = wave_append_n(&c.st[s0].found, nf);
-          } else {
-            fs = nf > 0 ? atomicAdd(&c.st[s].found, nf) : 0;
-          }
+          const int fs = wave_append_n(&c.st[s].found, nf);
           if (nf >= 1) push_found(c, s, d, fs, v.f, v.a);
           if (nf == 2) push_found(c, s, d, fs + 1, v.f2, v.a2);
           if (act) {
@@ -217,19 +213,21 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
   __shared__ int open_cur[kColResolveCap], open_nxt[kColResolveCap];
   __shared__ int n_cur, n_nxt;
   __shared__ float2 twd[kDeepTw];  // e^{-2 pi i m / L_t}, L_t = L / 2^(Dz + 1): every sum's twiddles
-  const int ndeep = *c.A.deep_count;
+  // the deep list, the descriptors and the level-0 results are written by
+  // earlier kernels: scalar loads
+  const int ndeep = *cst(c.A.deep_count);
   const int tid = threadIdx.x;
   for (int e = blockIdx.x; e < ndeep; e += gridDim.x) {
-    const int2 ent = c.A.deep_list[e];
-    const int s = ent.x, jslot = ent.y;
-    const SigDesc &d = c.desc[s];
+    const uint64_t ent = cst((const uint64_t *)c.A.deep_list)[e];  // the int2 (signal, slot)
+    const int s = (int)(uint32_t)ent, jslot = (int)(uint32_t)(ent >> 32);
+    const SigDesc &d = *(const SigDesc *)&cst(c.desc)[s];
     const uint64_t N = (uint64_t)d.N;
     const int lgL = d.log2N - d.log2B0;
     const int L = 1 << lgL;
     const int n = d.n;
-    const uint64_t cpar = (uint64_t)c.A.multi_c[0][d.multi_off + jslot];
+    const uint64_t cpar = (uint64_t)cst(c.A.multi_c[0])[d.multi_off + jslot];
     const float2 *M = c.A.jcol + d.jc_off + (int64_t)jslot * L;
-    const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
+    const double sref2 = cst(c.st)[s].sref2, nv = cst(c.st)[s].noise_var;
     const double invN = 1.0 / (double)N;
     // deepest depth a node is classified at (a multi-ton opens children while
     // its depth is below it)
@@ -245,7 +243,7 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
     const int lgLt = lgL - d.col_dz - 1;  // <= 7 (L <= 8192, Dz = 5)
     for (int m = tid; m < (1 << lgLt); m += blockDim.x) twd[m] = c.A.tw[m << (kLog2FftMax - lgLt)];
     if (tid == 0) {
-      const uint64_t mask = c.A.deep_mask[d.multi_off + jslot];
+      const uint64_t mask = cst(c.A.deep_mask)[d.multi_off + jslot];
       int m = 0;
       for (int b = 0; b < 64; b++)
         if ((mask >> b) & 1) open_cur[m++] = b;

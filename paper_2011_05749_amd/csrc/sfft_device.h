@@ -276,7 +276,17 @@ __device__ int block_scan_excl(int v, int *red, int *total) {
 }
 
 // index s with pre[s] <= item < pre[s+1] (pre non-decreasing, n+1 entries)
-__device__ __forceinline__ int find_owner(const int32_t *pre, int n, int item) {
+// Uniform values that no kernel writes while the reader runs, read through
+// the constant address space so that they come in by scalar loads (which do
+// not wait behind the vector loads in flight, and which later stores cannot
+// make stale, so nothing is loaded twice).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const T *p) {
+  return (const __attribute__((address_space(4))) T *)p;
+}
+
+template <typename P>
+__device__ __forceinline__ int find_owner(P pre, int n, int item) {
   int lo = 0, hi = n;  // pre[lo] <= item < pre[hi]
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;

@@ -32,6 +32,7 @@ constexpr int kColItemAlign = 8;     // column pass: each signal's item range pa
 constexpr int kColResolveCap = 128;  // open subclasses per depth of one class
 constexpr int kColGroupLg = 3;      // column resolve: 2^3 lanes per class
 constexpr int kColGroup = 1 << kColGroupLg;
+constexpr int kColResolveAlign = 64 / kColGroup;  // ... classes a wave: each signal's range padded to it
 constexpr int kColLaneDepth = 5;    // ... one lane per class-vector sum down to this depth
 constexpr int kDeepNodes = 512;     // deep resolution: subtree nodes classified per round
 constexpr int kDeepTw = 128;        // ... its twiddle table: L / 2^(Dz + 1) <= 8192 / 64 entries

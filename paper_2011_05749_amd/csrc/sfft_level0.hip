@@ -117,19 +117,21 @@ __global__ __launch_bounds__(kThreads) void k_level0_stats(LaunchCtx c) {
 template <int NMAX, bool F32, bool WAVE>
 __global__ __launch_bounds__(kThreads, 2) void k_level0_classify(LaunchCtx c) {
   for (int item = blockIdx.x; item < c.l0c_items; item += gridDim.x) {
-    const int li = find_owner(c.l0c_pre, c.ntree, item);
-    const int s = c.tree_list[li];
-    const SigDesc &d = c.desc[s];
+    // the lists, the descriptors and the level-0 statistics are written
+    // before this kernel runs: scalar loads
+    const int li = find_owner(cst(c.l0c_pre), c.ntree, item);
+    const int s = cst(c.tree_list)[li];
+    const SigDesc &d = *(const SigDesc *)&cst(c.desc)[s];
     const int64_t B = d.B0;
     const int64_t L = d.N >> d.log2B0;
     const int n = d.n;
     const float2 *Y0 = c.A.y0 + d.y0_off;
-    const double sref2 = c.st[s].sref2, nv = c.st[s].noise_var;
+    const double sref2 = cst(c.st)[s].sref2, nv = cst(c.st)[s].noise_var;
     // 64 >> lg classes a wave, on its first lanes; the rest of the wave joins
     // the team enumeration only
     const int lg = c.l0_spread_lg;
     const int lane = threadIdx.x & 63, cpw = 64 >> lg;
-    const int64_t cc = (int64_t)(item - c.l0c_pre[li]) * (kThreads >> lg) + (threadIdx.x >> 6) * cpw + lane;
+    const int64_t cc = (int64_t)(item - cst(c.l0c_pre)[li]) * (kThreads >> lg) + (threadIdx.x >> 6) * cpw + lane;
     const bool valid = lane < cpw && cc < B;
     Decision v;
     v.cls = kZero;

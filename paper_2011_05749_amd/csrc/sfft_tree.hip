@@ -39,7 +39,9 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
             // takes items in aligned groups; the padding items are skipped)
             const int nit = (int)(Lp >> d.col_ltc);
             cnt[5] = (nit + kColItemAlign - 1) & ~(kColItemAlign - 1);
-            cnt[6] = m;
+            // the column resolution's classes, padded to whole waves of
+            // 64 / kColGroup (a wave's classes then share one signal)
+            cnt[6] = (m + kColResolveAlign - 1) & ~(kColResolveAlign - 1);
             c.st[s].samples += d.N;
           } else if (jump) {
             cnt[3] = (int)((Bp + c.jrows - 1) / c.jrows);

@@ -27,6 +27,33 @@ __device__ __forceinline__ void col_sum(const float2 *M, uint64_t Ld, int u0, in
   }
 }
 
+// The depth-dd sums of one measurement (delay tau, tr = tau mod L_d) for the
+// chunk's `no` open subclasses: its NQ = 2^dd coefficients M[tr + u L_d] are
+// loaded once (all in flight together), then each subclass's sum runs over
+// them in registers with the twiddle advancing term by term, in the order and
+// arithmetic of col_sum; the result, over B_d, goes to Y[oi * stride].
+template <int NQ>
+__device__ __forceinline__ void lane_sums(const float2 *Mt, uint64_t Ld, const SigDesc &d, uint64_t N, uint64_t cpar,
+                                          const int *open, int no, uint64_t tau, uint64_t tr, double sc, double2 *Y,
+                                          int stride) {
+  float2 mv[NQ];
+#pragma unroll
+  for (int u = 0; u < NQ; u++) mv[u] = Mt[(uint64_t)u * Ld];
+  for (int oi = 0; oi < no; oi++) {
+    const uint64_t cs = cpar + (uint64_t)open[oi] * (uint64_t)d.B0;
+    double2 w = unit_d((cs * ((tr - tau) & (N - 1))) & (N - 1), N, -1);
+    const double2 st = unit_d((cs * Ld) & (N - 1), N, -1);
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < NQ; u++) {
+      acc.x += (double)mv[u].x * w.x - (double)mv[u].y * w.y;
+      acc.y += (double)mv[u].x * w.y + (double)mv[u].y * w.x;
+      w = cmul(w, st);
+    }
+    Y[oi * stride] = make_double2(acc.x * sc, acc.y * sc);
+  }
+}
+
 // Subtree resolution from the column pass.  Each open level-0 class c is
 // served by a group of kColGroup lanes (a wave serves 64 / kColGroup classes
 // side by side, so that their classifications run together).  Its subclass
@@ -85,17 +112,21 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
         const int left = nopen - ch * GS;
         const int no = left < 0 ? 0 : (left < GS ? left : GS);
         if (dd <= kColLaneDepth) {
-          for (int e = gl; e < no * n; e += GS) {
-            const int oi = e / n, i = e - oi * n;
-            const uint64_t cs = cpar + (uint64_t)open_cur[g][ch * GS + oi] * (uint64_t)d.B0;
+          // lane gl takes measurements gl, gl + GS, ... for every open subclass
+          static_assert(kColLaneDepth == 5, "lane sums are instantiated for 2 .. 32 terms");
+          const double sc = 1.0 / (double)Bd;
+          for (int i = gl; no > 0 && i < n; i += GS) {
             const uint64_t tau = tau_of(d, i);
             const uint64_t tr = tau & (Ld - 1);
-            double2 w = unit_d((cs * ((tr - tau) & (N - 1))) & (N - 1), N, -1);
-            const double2 st = unit_d((cs * Ld) & (N - 1), N, -1);
-            double2 acc = make_double2(0.0, 0.0);
-            col_sum<8>(M + tr, Ld, 0, 1, nq, w, st, acc);
-            const double sc = 1.0 / (double)Bd;
-            Ys[g][oi][i] = make_double2(acc.x * sc, acc.y * sc);
+            const int *op = &open_cur[g][ch * GS];
+            double2 *yo = &Ys[g][0][i];
+            switch (dd) {
+              case 1: lane_sums<2>(M + tr, Ld, d, N, cpar, op, no, tau, tr, sc, yo, NMAX); break;
+              case 2: lane_sums<4>(M + tr, Ld, d, N, cpar, op, no, tau, tr, sc, yo, NMAX); break;
+              case 3: lane_sums<8>(M + tr, Ld, d, N, cpar, op, no, tau, tr, sc, yo, NMAX); break;
+              case 4: lane_sums<16>(M + tr, Ld, d, N, cpar, op, no, tau, tr, sc, yo, NMAX); break;
+              default: lane_sums<32>(M + tr, Ld, d, N, cpar, op, no, tau, tr, sc, yo, NMAX); break;
+            }
           }
         } else {
           // the wave's open subclasses of this chunk, one after the other;
@@ -238,8 +269,20 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
     float2 *twf = reinterpret_cast<float2 *>(&Ys[0][0]);
     static_assert(sizeof(Ys) >= sizeof(float2) * (kFftMax / 2), "FFT twiddles fit the vectors' space");
     for (int m = tid; m < (L >> 1); m += blockDim.x) twf[m] = c.A.tw[m << (kLog2FftMax - lgL)];
-    for (int t = tid; t < L; t += blockDim.x)
-      Zs[bitrev((uint32_t)t, lgL)] = cmulf(ldg(M + t), unit_nl((cpar * (uint64_t)t) & (N - 1), (uint64_t)N, d.log2N));
+    // the row, 8 values a thread in flight at once (256 threads)
+    for (int t0 = 0; t0 < L; t0 += 8 * 256) {
+      float2 mv[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int t = t0 + j * 256 + tid;
+        mv[j] = t < L ? ldg(M + t) : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int t = t0 + j * 256 + tid;
+        if (t < L) Zs[bitrev((uint32_t)t, lgL)] = cmulf(mv[j], unit_nl((cpar * (uint64_t)t) & (N - 1), (uint64_t)N, d.log2N));
+      }
+    }
     const int lgLt = lgL - d.col_dz - 1;  // <= 7 (L <= 8192, Dz = 5)
     for (int m = tid; m < (1 << lgLt); m += blockDim.x) twd[m] = c.A.tw[m << (kLog2FftMax - lgLt)];
     if (tid == 0) {

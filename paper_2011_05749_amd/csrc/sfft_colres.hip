@@ -228,11 +228,13 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
 // in L_d terms instead of 2^dd.  One work-group per deep class: the row into
 // LDS and its FFT; then, round by round, every node of the subtrees below the
 // open subclasses -- as many levels at once as kDeepNodes nodes allow -- has
-// its vector formed and is classified, all in parallel, and one thread per
-// subtree walks it from the root as the tree search does (children of
-// multi-tons only): the nodes the level-by-level search would reach are the
-// ones that count, with the same vectors and so the same decisions.
-// Multi-tons on the last level of a round open the next round.
+// its vector formed and is classified, all in parallel; then the round's
+// levels are walked from the subtrees' roots as the tree search does
+// (children of multi-tons only), a level at a time with one thread per node:
+// the nodes the level-by-level search would reach are the ones that count,
+// with the same vectors and so the same decisions.  Their entries take one
+// reservation in the found list per round.  Multi-tons on the last level of a
+// round open the next round.
 template <int NMAX, bool F32, bool WAVE>
 __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
   constexpr int CH = 2048 / NMAX;  // nodes whose vectors are staged at once (32 KiB)
@@ -243,6 +245,8 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
   __shared__ double2 da[kDeepNodes], da2[kDeepNodes];
   __shared__ int open_cur[kColResolveCap], open_nxt[kColResolveCap];
   __shared__ int n_cur, n_nxt;
+  __shared__ int nf_round, fs_round, deepest_round;  // the walk's entries, their first slot, its deepest level
+  __shared__ int16_t fslot[kDeepNodes];               // a reached node's first entry in the round's reservation
   __shared__ float2 twd[kDeepTw];  // e^{-2 pi i m / L_t}, L_t = L / 2^(Dz + 1): every sum's twiddles
   // the deep list, the descriptors and the level-0 results are written by
   // earlier kernels: scalar loads
@@ -268,14 +272,27 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
     // of the class vectors (not in use before the first round)
     float2 *twf = reinterpret_cast<float2 *>(&Ys[0][0]);
     static_assert(sizeof(Ys) >= sizeof(float2) * (kFftMax / 2), "FFT twiddles fit the vectors' space");
-    for (int m = tid; m < (L >> 1); m += blockDim.x) twf[m] = c.A.tw[m << (kLog2FftMax - lgL)];
-    // the row, 8 values a thread in flight at once (256 threads)
+    const int lgLt = lgL - d.col_dz - 1;  // <= 7 (L <= 8192, Dz = 5)
+    static_assert(kDeepTw <= 256, "one sum twiddle a thread");
+    const float2 tdv = tid < (1 << lgLt) ? c.A.tw[tid << (kLog2FftMax - lgLt)] : make_float2(0.f, 0.f);
+    // the row and the FFT's twiddles, 8 + 4 values a thread in flight at once
+    // (256 threads)
     for (int t0 = 0; t0 < L; t0 += 8 * 256) {
-      float2 mv[8];
+      float2 mv[8], tv[4];
 #pragma unroll
       for (int j = 0; j < 8; j++) {
         const int t = t0 + j * 256 + tid;
         mv[j] = t < L ? ldg(M + t) : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int m = (t0 >> 1) + j * 256 + tid;
+        tv[j] = m < (L >> 1) ? c.A.tw[m << (kLog2FftMax - lgL)] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int m = (t0 >> 1) + j * 256 + tid;
+        if (m < (L >> 1)) twf[m] = tv[j];
       }
 #pragma unroll
       for (int j = 0; j < 8; j++) {
@@ -283,8 +300,7 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
         if (t < L) Zs[bitrev((uint32_t)t, lgL)] = cmulf(mv[j], unit_nl((cpar * (uint64_t)t) & (N - 1), (uint64_t)N, d.log2N));
       }
     }
-    const int lgLt = lgL - d.col_dz - 1;  // <= 7 (L <= 8192, Dz = 5)
-    for (int m = tid; m < (1 << lgLt); m += blockDim.x) twd[m] = c.A.tw[m << (kLog2FftMax - lgLt)];
+    if (tid < (1 << lgLt)) twd[tid] = tdv;
     if (tid == 0) {
       const uint64_t mask = cst(c.A.deep_mask)[d.multi_off + jslot];
       int m = 0;
@@ -351,26 +367,31 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
         }
         __syncthreads();
       }
-      // the walk: thread o takes subtree o, level by level from its root
-      if (tid == 0) n_nxt = 0;
+      // the walk, a level at a time: node l = 2^r - 1 + u of subtree o is
+      // reached when it is a root or its parent was reached as a multi-ton
+      // above the deepest level
+      if (tid == 0) {
+        n_nxt = 0;
+        nf_round = 0;
+        deepest_round = 0;
+      }
       __syncthreads();
-      for (int o = tid; o < nopen; o += blockDim.x) {
-        const int base = o * per;
-        // first the nodes reached, the entries they add and the deepest one; then
-        // one reservation in the found list for the whole subtree
-        int nf = 0, deepest = 0;
-        for (int l = 0; l < per; l++) {
-          const int r = 31 - __clz(l + 1), u = l + 1 - (1 << r);
-          bool reach = l == 0;
-          if (l > 0) {
-            const int pl = base + (1 << (r - 1)) - 1 + (u & ((1 << (r - 1)) - 1));
+      for (int r = 0; r < sl; r++) {
+        const int w = 1 << r, nl = nopen << r;
+        for (int e = tid; e < nl; e += blockDim.x) {
+          const int o = e >> r, u = e & (w - 1);
+          const int q = o * per + w - 1 + u;
+          bool reach = r == 0;
+          if (r > 0) {
+            const int pl = o * per + (w >> 1) - 1 + (u & ((w >> 1) - 1));
             reach = reached[pl] && dcls[pl] == kMulti && dd + r - 1 < dmax;
           }
-          reached[base + l] = reach ? 1 : 0;
+          reached[q] = reach ? 1 : 0;
           if (!reach) continue;
-          const int ddn = dd + r, q = base + l;
-          deepest = ddn;
-          nf += dcls[q] == kSingle ? 1 : dcls[q] == kDouble ? 2 : 0;
+          const int ddn = dd + r;
+          atomicMax(&deepest_round, ddn);
+          const int nfq = dcls[q] == kSingle ? 1 : dcls[q] == kDouble ? 2 : 0;
+          if (nfq > 0) fslot[q] = (int16_t)atomicAdd(&nf_round, nfq);
           if (dcls[q] == kMulti) {
             if (ddn >= dmax) {
               atomicOr(&c.st[s].flags, 1);
@@ -387,15 +408,19 @@ __global__ __launch_bounds__(256) void k_col_deep(LaunchCtx c) {
             }
           }
         }
-        atomicMax(&c.st[s].levels, deepest);
-        if (nf > 0) {
-          int fs = atomicAdd(&c.st[s].found, nf);
-          for (int q = base; q < base + per; q++) {
-            if (!reached[q]) continue;
-            if (dcls[q] == kSingle || dcls[q] == kDouble) push_found(c, s, d, fs++, df[q], da[q]);
-            if (dcls[q] == kDouble) push_found(c, s, d, fs++, df2[q], da2[q]);
-          }
-        }
+        __syncthreads();
+      }
+      // one reservation for the round's entries, then every reached node's
+      if (tid == 0) {
+        if (deepest_round > 0) atomicMax(&c.st[s].levels, deepest_round);
+        fs_round = nf_round > 0 ? atomicAdd(&c.st[s].found, nf_round) : 0;
+      }
+      __syncthreads();
+      for (int q = tid; q < nn; q += blockDim.x) {
+        if (!reached[q]) continue;
+        const int fq = fs_round + fslot[q];
+        if (dcls[q] == kSingle || dcls[q] == kDouble) push_found(c, s, d, fq, df[q], da[q]);
+        if (dcls[q] == kDouble) push_found(c, s, d, fq + 1, df2[q], da2[q]);
       }
       __syncthreads();
       nopen = n_nxt < kColResolveCap ? n_nxt : kColResolveCap;

@@ -3,10 +3,12 @@
 The deep resolution classifies, in one round, every node of the subtrees
 below its open subclasses down to as many levels as its node budget allows
 (node l = 2^r - 1 + u of subtree o is subclass kappa_o + u 2^dd at depth
-dd + r), then walks each subtree from its root so that only children of
-multi-tons count.  This model of that indexing and walk must visit exactly the
-nodes the depth-by-depth tree search visits, with the same decisions, flags
-and deepest level, whatever the decisions are.
+dd + r), then walks the round's levels from the subtrees' roots, a level at a
+time with one thread per node (a node is reached when it is a root or its
+parent was reached as a multi-ton), so that only children of multi-tons count.
+This model of that indexing and walk must visit exactly the nodes the
+depth-by-depth tree search visits, with the same decisions, flags and deepest
+level, whatever the decisions are.
 """
 import random
 
@@ -51,22 +53,24 @@ def rounds(open0, dd0, dmax, decide):
         dec = [decide(*nd) for nd in nodes]
         reached = [False] * len(nodes)
         nxt = []
-        for o in range(len(open_)):
-            base = o * per
-            for l in range(per):
-                r = (l + 1).bit_length() - 1
-                u = l + 1 - (1 << r)
-                if l == 0:
+        # level-major, as the kernel's threads take them: level r holds the
+        # nopen 2^r nodes e = (o, u) of every subtree, and reads level r - 1
+        for r in range(sl):
+            for e in range(len(open_) << r):
+                o, u = e >> r, e & ((1 << r) - 1)
+                base = o * per
+                q = base + (1 << r) - 1 + u
+                if r == 0:
                     reach = True
                 else:
                     pl = base + (1 << (r - 1)) - 1 + (u & ((1 << (r - 1)) - 1))
                     reach = reached[pl] and dec[pl] == MULTI and dd + r - 1 < dmax
-                reached[base + l] = reach
+                reached[q] = reach
                 if not reach:
                     continue
-                ddn, k = nodes[base + l]
+                ddn, k = nodes[q]
                 assert ddn == dd + r
-                v = dec[base + l]
+                v = dec[q]
                 seen.append((ddn, k, v))
                 levels = max(levels, ddn)
                 if v == MULTI:

@@ -275,7 +275,6 @@ __device__ int block_scan_excl(int v, int *red, int *total) {
   return before + inc - v;
 }
 
-// index s with pre[s] <= item < pre[s+1] (pre non-decreasing, n+1 entries)
 // Uniform values that no kernel writes while the reader runs, read through
 // the constant address space so that they come in by scalar loads (which do
 // not wait behind the vector loads in flight, and which later stores cannot
@@ -285,6 +284,7 @@ __device__ __forceinline__ const __attribute__((address_space(4))) T *cst(const 
   return (const __attribute__((address_space(4))) T *)p;
 }
 
+// index s with pre[s] <= item < pre[s+1] (pre non-decreasing, n+1 entries)
 template <typename P>
 __device__ __forceinline__ int find_owner(P pre, int n, int item) {
   int lo = 0, hi = n;  // pre[lo] <= item < pre[hi]
@@ -296,30 +296,41 @@ __device__ __forceinline__ int find_owner(P pre, int n, int item) {
 }
 
 // k-th smallest (0-based) of scale*|v|^2 over cnt complex64 values, by a
-// four-pass radix select on the float bit patterns (all values >= 0)
+// four-pass radix select on the float bit patterns (all values >= 0).  For
+// work-groups of 256 threads: each thread keeps 8 loads in flight, and the
+// pass's digit is found by a scan with one histogram bin a thread.
 __device__ float select_kth_power(const float2 *v, int64_t cnt, float scale, int64_t k,
                                   uint32_t *hist, uint32_t *sel) {
+  static_assert(kThreads == 256, "one bin a thread");
+  __shared__ int scan_red[kThreads / 64];
+  const int tid = threadIdx.x;
   uint32_t prefix = 0, mask = 0;
   for (int pass = 0; pass < 4; pass++) {
     const int sh = 24 - 8 * pass;
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) hist[i] = 0;
+    hist[tid] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-      const float2 y = v[i];
-      const float p = scale * (y.x * y.x + y.y * y.y);
-      const uint32_t key = __float_as_uint(p);
-      if ((key & mask) == prefix) atomicAdd(&hist[(key >> sh) & 255u], 1u);
+    for (int64_t i0 = 0; i0 < cnt; i0 += 8 * kThreads) {
+      float2 y[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int64_t i = i0 + j * kThreads + tid;
+        y[j] = i < cnt ? v[i] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int64_t i = i0 + j * kThreads + tid;
+        const uint32_t key = __float_as_uint(scale * (y[j].x * y[j].x + y[j].y * y[j].y));
+        if (i < cnt && (key & mask) == prefix) atomicAdd(&hist[(key >> sh) & 255u], 1u);
+      }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t acc = 0;
-      uint32_t dsel = 255;
-      for (uint32_t dg = 0; dg < 256; dg++) {
-        if (acc + (int64_t)hist[dg] > k) { dsel = dg; break; }
-        acc += hist[dg];
-      }
-      sel[0] = dsel;
-      sel[1] = (uint32_t)(k - acc);
+    // the digit: the bin in which the running count passes k
+    const int h = (int)hist[tid];
+    int tot;
+    const int before = block_scan_excl(h, scan_red, &tot);
+    if ((int64_t)before <= k && k < (int64_t)before + h) {
+      sel[0] = (uint32_t)tid;
+      sel[1] = (uint32_t)(k - before);
     }
     __syncthreads();
     prefix |= sel[0] << sh;

@@ -6,7 +6,7 @@ namespace sfft {
 namespace {
 
 // Top-K by magnitude (ties: lower index), then ascending index; padding.
-__global__ __launch_bounds__(kThreads) void k_finalize(LaunchCtx c) {
+__global__ __launch_bounds__(1024) void k_finalize(LaunchCtx c) {
   extern __shared__ uint64_t keys[];
   int32_t *ix = (int32_t *)(keys + c.max_found_cap);
   for (int s = blockIdx.x; s < c.nsig; s += gridDim.x) {
@@ -110,7 +110,10 @@ hipError_t launch_finalize(const LaunchCtx &c, hipStream_t s) {
   }
   const int grid = c.nsig < 4096 ? c.nsig : 4096;
   const size_t lds = (sizeof(uint64_t) + sizeof(int32_t)) * (size_t)c.max_found_cap;
-  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(kThreads), lds, s, c);
+  // a signal a work-group; batches too small to fill the CUs sort with 1024
+  // threads a signal (every loop strides by the work-group size)
+  const int nt = c.nsig < 256 ? 1024 : kThreads;
+  hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(nt), lds, s, c);
   return hipGetLastError();
 }
 

@@ -87,9 +87,16 @@ __global__ __launch_bounds__(kThreads) void k_level0_stats(LaunchCtx c) {
     const int64_t cnt = (int64_t)d.n * d.B0;
     const float2 *Y0 = c.A.y0 + d.y0_off;
     double psum = 0.0;
-    for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-      const float2 v = Y0[i];
-      psum += (double)v.x * v.x + (double)v.y * v.y;
+    for (int64_t i0 = 0; i0 < cnt; i0 += 8 * kThreads) {
+      // 8 loads a thread in flight at once
+      float2 y[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int64_t i = i0 + j * kThreads + threadIdx.x;
+        y[j] = i < cnt ? Y0[i] : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j++) psum += (double)y[j].x * y[j].x + (double)y[j].y * y[j].y;
     }
     const double sref2 = block_sum_d(psum, red) / (double)cnt;
     double nv = d.noise_var;

@@ -400,7 +400,9 @@ typedef struct {
   int32_t n;           /* measurements per class vector */
   int32_t l1;          /* 1: takes the level-1 column pass */
   int32_t jump_L;      /* dense-pass stride in effect (0: off) */
-  int32_t pad;
+  int32_t col_rows;    /* column-pass rows reserved (l1 only): the expected level-0
+                          multi-tons x 1.5 + 64, at most multi_cap; open classes
+                          beyond them leave the signal PARTIAL */
 } sfft_workspace_signal_t;
 
 int32_t sfft_workspace(const sfft_plan_t *plans, int32_t n, sfft_workspace_t *out,

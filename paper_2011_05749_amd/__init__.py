@@ -121,7 +121,7 @@ class WorkspaceSignal(ctypes.Structure):
         ("y0_off", ctypes.c_int64), ("fst_off", ctypes.c_int64), ("found_off", ctypes.c_int64),
         ("multi_off", ctypes.c_int64), ("jcol_off", ctypes.c_int64),
         ("found_cap", ctypes.c_int32), ("multi_cap", ctypes.c_int32), ("n", ctypes.c_int32),
-        ("l1", ctypes.c_int32), ("jump_L", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("l1", ctypes.c_int32), ("jump_L", ctypes.c_int32), ("col_rows", ctypes.c_int32),
     ]
 
 

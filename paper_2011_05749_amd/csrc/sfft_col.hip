@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
   auto fetch = [&](int item, int sg) {
     const __attribute__((address_space(4))) SigDesc &ds = cst(c.desc)[sg];
     const int m = cst(c.st)[sg].multi[0];
-    m_n = m > ds.multi_cap ? ds.multi_cap : m;
+    m_n = m > ds.col_rows ? ds.col_rows : m;  // col_rows <= multi_cap
     const int64_t L = ds.N >> ds.log2B0;
     const float2 *xs = c.io ? cst(c.io)[sg].x : c.io1.x;
     const int64_t col0 = (int64_t)(item - pc[sg]) << LTC;
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(1024) void k_col_pass16(LaunchCtx c) {
   auto fetch = [&](int item, int sg) {
     const __attribute__((address_space(4))) SigDesc &ds = cst(c.desc)[sg];
     const int m = cst(c.st)[sg].multi[0];
-    m_n = m > ds.multi_cap ? ds.multi_cap : m;
+    m_n = m > ds.col_rows ? ds.col_rows : m;  // col_rows <= multi_cap
     const int64_t L = ds.N >> 11;
     const float2 *xs = c.io ? cst(c.io)[sg].x : c.io1.x;
     const int64_t col0 = (int64_t)(item - pc[sg]) << LTC;
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
   auto fetch = [&](int item, int sg) {
     const __attribute__((address_space(4))) SigDesc &ds = cst(c.desc)[sg];
     const int m = cst(c.st)[sg].multi[0];
-    m_n = m > ds.multi_cap ? ds.multi_cap : m;
+    m_n = m > ds.col_rows ? ds.col_rows : m;  // col_rows <= multi_cap
     const int64_t L = ds.N >> 11;
     const float2 *xs = c.io ? cst(c.io)[sg].x : c.io1.x;
     const int64_t col0 = (int64_t)(item - pc[sg]) << LTC;

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(64, 2) void k_col_resolve(LaunchCtx c) {
     const SigDesc &d = *(const SigDesc *)&cst(c.desc)[s];
     const int jslot = base + g - pr[s];
     const int mcnt = cst(c.st)[s].multi[0];
-    const bool valid = jslot < (mcnt < d.multi_cap ? mcnt : d.multi_cap);
+    const bool valid = jslot < (mcnt < d.col_rows ? mcnt : d.col_rows);
     const uint64_t N = (uint64_t)d.N;
     const int n = valid ? d.n : 0;
     const uint64_t L = N >> d.log2B0;

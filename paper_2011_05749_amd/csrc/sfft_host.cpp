@@ -171,6 +171,7 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     d.max_peel_rounds = in.max_peel_rounds;
     d.found_cap = in.found_cap;
     d.multi_cap = in.multi_cap;
+    d.col_rows = in.multi_cap;
     d.l1 = (in.kind == SFFT_KIND_TREE && !no_jump && in.l1_resolve) ? 1 : 0;
     d.jump_L = (in.kind == SFFT_KIND_TREE && !no_jump && !d.l1) ? in.jump_L : 0;
     d.mpp = in.mpp;
@@ -202,6 +203,15 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     d.fst_off = fst;
     d.jc_off = jc;
     if (d.l1) {
+      // rows of the column pass: the expected number of level-0 multi-tons
+      // (K tones in B0 classes, Poisson: B0 (1 - e^-l (1 + l)), l = K / B0)
+      // with half of it and 64 rows to spare; more open classes than that
+      // leave the signal PARTIAL
+      {
+        const double lam = (double)in.K / (double)in.B0;
+        const double ex = (double)in.B0 * (1.0 - std::exp(-lam) * (1.0 + lam));
+        d.col_rows = (int32_t)std::min<int64_t>(d.multi_cap, (int64_t)std::ceil(1.5 * ex) + 64);
+      }
       d.col_key = d.log2B0 + 32 * d.fp16 + (in.col_form == 2 ? 64 : in.col_form == 3 ? 128 : 0);
       d.col_ltc = in.col_form == 3 ? 4 : 14 - d.log2B0;  // 16 columns; else 512 / (B0 / 32)
       // classes open below depth col_dz go to the deep resolution (one L-point
@@ -213,7 +223,7 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
     if (in.kind == SFFT_KIND_TREE) {
       y0 += (int64_t)d.n * in.B0;
       mc += d.multi_cap;
-      if (d.l1) jc += (int64_t)d.multi_cap * (in.N / in.B0);
+      if (d.l1) jc += (int64_t)d.col_rows * (in.N / in.B0);
       tree.push_back({(int64_t)d.n * in.B0 * (in.max_levels + 1), s});
       maxB0 = std::max<int64_t>(maxB0, in.B0);
     } else {
@@ -1389,6 +1399,7 @@ int32_t sfft_workspace(const sfft_plan_t *plans, int32_t n, sfft_workspace_t *ou
       w.jcol_off = d.jc_off;
       w.found_cap = d.found_cap;
       w.multi_cap = d.multi_cap;
+      w.col_rows = d.l1 ? d.col_rows : 0;
       w.n = d.n;
       w.l1 = d.l1;
       w.jump_L = d.jump_L;

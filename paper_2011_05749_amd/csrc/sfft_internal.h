@@ -70,6 +70,7 @@ struct SigDesc {
   int32_t col_dz;         // column-pass signals: depth below which open classes go to the
                           // deep resolution (0: the column resolution goes all the way)
   int32_t l0_tile_lg;     // log2 of the level-0 sub-FFT size
+  int32_t col_rows;  // column pass: rows reserved for the open level-0 classes (<= multi_cap)
   int32_t enum_lane_blocks;  // noisy enumeration below level 0: teams where ranges exceed this many 32-blocks
   int32_t rf_iters, rf_m; // FFAST R-FFAST delay set r_c + 2^c t (rf_iters = 0: delays 0..D-1)
   uint64_t rf_off[SFFT_MAX_ROUNDS];

@@ -37,6 +37,11 @@ __global__ __launch_bounds__(1024) void k_sched(LaunchCtx c, int level) {
             // items of 2^col_ltc adjacent columns, the range padded to a
             // multiple of kColItemAlign (the XCD grouping of the column pass
             // takes items in aligned groups; the padding items are skipped)
+            // open classes beyond the rows reserved for them stay unresolved
+            if (m > d.col_rows) {
+              c.st[s].flags |= 1;
+              m = d.col_rows;
+            }
             const int nit = (int)(Lp >> d.col_ltc);
             cnt[5] = (nit + kColItemAlign - 1) & ~(kColItemAlign - 1);
             // the column resolution's classes, padded to whole waves of

@@ -281,6 +281,41 @@ def test_l0_spread_changes_nothing(sfft):
     assert_parity(g, o)
 
 
+@pytest.mark.parametrize("pairs", [128, 140])
+def test_column_rows_overflow_reports_partial(sfft, pairs):
+    """The column pass reserves rows for the expected level-0 multi-tons with a
+    margin: for K = 256 tones in B0 = 512 classes, 1.5 x 46.2 + 64 -> 134 rows
+    (of multi_cap = 256).  Tone pairs k B0 apart in `pairs` distinct classes
+    (N = 2^20) make that many level-0 multi-tons: 128 (the K tones) fit and
+    the solve equals the oracle's; with 140 the GPU leaves the classes past its
+    rows unresolved and reports PARTIAL, returning only planted tones with
+    their values, while the oracle, which reserves nothing, resolves every one
+    (280 tones of equal magnitude against K = 256: which 256 the top-K keeps
+    depends on rounding, so only the planted set is checked)."""
+    N, B0, K = 2 ** 20, 512, 256
+    ws, sig = sfft.workspace([sfft.Plan(N, K, 4, 2, seed=4, B0=B0)])
+    assert sig[0]["l1"] == 1 and sig[0]["col_rows"] == 134 and sig[0]["multi_cap"] == 256
+    rng = np.random.default_rng(11)
+    cls = rng.choice(B0, size=pairs, replace=False)
+    k = rng.integers(0, N // B0 - 1, size=pairs)
+    support = np.sort(np.concatenate([cls + B0 * k, cls + B0 * (k + 1)]))
+    sp = siggen.make_spec(N, 2 * pairs, 4, support=support)
+    x = siggen.synth(sp)
+    g, o = solve_both(sfft, x, N, K, 4, 2, seed=4, B0=B0)
+    gi, gv, gc, st = g
+    oi, ov, oc, tr = o
+    if pairs <= 134:
+        assert_parity(g, o)
+        return
+    assert tr.status == 0                          # the oracle resolves every tone
+    assert st["status"] == sfft.STATUS_PARTIAL     # the GPU ran out of rows
+    got = gi[gi >= 0]
+    assert 0 < len(got) <= K and set(got.tolist()) <= set(support.tolist())
+    truth = dict(zip(sp.support.tolist(), sp.values.tolist()))
+    for f, v in zip(got.tolist(), gv[gi >= 0].tolist()):
+        assert abs(v - truth[f]) <= 1e-4 * abs(truth[f])
+
+
 def test_open_list_overflow_reports_partial(sfft):
     """200 tones in one level-0 class (N = 2^20, B0 = 512, L = 2048), in 100
     pairs 1024 positions apart whose members share their low 10 bits, the pairs

@@ -61,7 +61,7 @@ def test_serving_results_equal_alone(sfft):
     vals = [torch.zeros(p.K, dtype=torch.complex64, device=dev) for p in plans]
     counts = torch.full((n,), -1, dtype=torch.int64, device=dev)
     status = torch.full((n,), -1, dtype=torch.int32, device=dev)
-    # 2 lanes of 64 MiB: a batch holds at most three of the 17 MiB requests
+    # 2 lanes of 64 MiB: a batch holds at most ten of the headline-shape requests (6 MiB each)
     srv = sfft.Server(hbm_bytes=128 << 20, lanes=2, max_batch=16)
     t0 = srv.clock_ns() + 2_000_000
     rel = t0 + np.cumsum(rng.exponential(150_000.0, n)).astype(np.int64)   # ~6.7 k requests/s
@@ -97,21 +97,21 @@ def test_serving_results_equal_alone(sfft):
 
 
 def test_serving_batches_fit_the_lane(sfft):
-    """Every batch's workspace fits the lane's share: with 40 MiB lanes and
-    requests of about 17 MiB each, no batch holds more than two of them."""
+    """Every batch's workspace fits the lane's share: with 15 MiB lanes and
+    requests of about 6 MiB each, no batch holds more than two of them."""
     dev = torch.device("cuda")
     N, K = 2 ** 22, 1024
     sp = siggen.make_spec(N, K, 9)
     x = siggen.synth_torch(sp, dev)
     plan = sfft.Plan(N, K, 4, 2, seed=9, B0=2048)
     ws, _ = sfft.workspace([plan])
-    assert 16 << 20 < ws["bytes"] < 20 << 20
+    assert 5 << 20 < ws["bytes"] < 7 << 20
     n = 12
     idxs = [torch.empty(K, dtype=torch.int64, device=dev) for _ in range(n)]
     vals = [torch.empty(K, dtype=torch.complex64, device=dev) for _ in range(n)]
     counts = torch.zeros(n, dtype=torch.int64, device=dev)
     status = torch.zeros(n, dtype=torch.int32, device=dev)
-    srv = sfft.Server(hbm_bytes=80 << 20, lanes=2, max_batch=64)
+    srv = sfft.Server(hbm_bytes=30 << 20, lanes=2, max_batch=64)
     first = srv.submit([plan] * n, [x] * n, idxs, vals, counts, status)
     srv.drain()
     rq = srv.requests(first, n)
@@ -127,7 +127,7 @@ def test_serving_refuses_oversized_request(sfft):
     dev = torch.device("cuda")
     plan = sfft.Plan(2 ** 22, 1024, 4, 2, seed=1, B0=2048)
     x = torch.zeros(plan.N, dtype=torch.complex64, device=dev)
-    srv = sfft.Server(hbm_bytes=8 << 20, lanes=1, max_batch=4)
+    srv = sfft.Server(hbm_bytes=4 << 20, lanes=1, max_batch=4)  # the request's workspace: about 6 MiB
     with pytest.raises(sfft.SfftError) as e:
         srv.submit([plan], [x], [torch.empty(plan.K, dtype=torch.int64, device=dev)],
                    [torch.empty(plan.K, dtype=torch.complex64, device=dev)],

@@ -13,9 +13,12 @@ Index expressions audited (element indices):
   mvec    (multi_off + j) nmax + i, i < n <= nmax
   jacc    level-0 classify, k_children, k_jump_pass, k_jump_resolve:
           (multi_off + j) jstride + t, t < L' <= jump_L <= jstride
-  jcol    k_col_pass / k_col_resolve: jcol_off + j L + t, j < multi_cap, t < L = N/B0
+  jcol    k_col_pass / k_col_resolve / k_col_deep: jcol_off + j L + t, j < col_rows <= multi_cap,
+          t < L = N/B0 (col_rows: the expected level-0 multi-tons x 1.5 + 64)
   pre     k_sched: 7 (nsig + 1) int32
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -36,7 +39,7 @@ def audit(plans):
     need_jacc = 0
     for p, s in zip(plans, sig):
         inf = p.info
-        N, B0, R, D = int(inf.N), int(inf.B0), int(inf.R), int(inf.D)
+        N, K, B0, R, D = int(inf.N), int(inf.K), int(inf.B0), int(inf.R), int(inf.D)
         if inf.kind == sfft.KIND_TREE:
             n = R * D
             assert s["n"] == n <= nmax
@@ -66,7 +69,10 @@ def audit(plans):
                 tc = 512 // (B0 // 32)
                 G = max(2, 16 // tc)
                 assert L % tc == 0 and (L // tc) % G == 0
-                spans["jcol"].append((s["jcol_off"], s["jcol_off"] + s["multi_cap"] * L))
+                lam = K / B0
+                want = min(s["multi_cap"], math.ceil(1.5 * B0 * (1 - math.exp(-lam) * (1 + lam))) + 64)
+                assert s["col_rows"] == want and 0 < want <= s["multi_cap"]
+                spans["jcol"].append((s["jcol_off"], s["jcol_off"] + s["col_rows"] * L))
                 assert s["jump_L"] == 0
         else:
             nb = sum(int(inf.stage_B[j]) for j in range(R))
@@ -106,8 +112,11 @@ def test_headline_batch_bounds(jump_L, l1):
     ws, sig = audit(headline(jump_L, l1))
     assert all(s["l1"] == l1 for s in sig)
     if l1:
-        # 256 x 1024 rows of 2048 complex64: the 4 GiB of column-pass rows
-        assert ws["jcol"] == 256 * 1024 * 2048
+        # 256 x 342 rows of 2048 complex64 (185 level-0 multi-tons expected of
+        # K = 1024 tones in 2048 classes, x 1.5 + 64): 1.4 GB instead of the
+        # 4.3 GB that K rows a signal would take
+        assert all(s["col_rows"] == 342 for s in sig)
+        assert ws["jcol"] == 256 * 342 * 2048
 
 
 def test_two_ton_variant_bounds():

@@ -54,7 +54,7 @@ def check_equal(a, b):
 def test_noalloc_two_calls_second_smaller(sfft):
     dev = torch.device("cuda")
     cases = [
-        # headline shape: level-1 column pass, 17 MiB of workspace
+        # headline shape: level-1 column pass, 6 MiB of workspace
         (dict(N=2 ** 22, K=1024, stages=4, delays=2, seed=9000), dict(B0=2048)),
         # smaller: level-by-level tree with the dense pass
         (dict(N=2 ** 16, K=300, stages=4, delays=2, seed=4), dict(B0=512)),
@@ -89,8 +89,8 @@ def test_noalloc_mixed_kinds_and_repeat(sfft):
 
 
 def test_noalloc_rejects_oversized_workspace(sfft):
-    # column-pass rows of 4096 slots x 4096 samples: 128 MiB > the scratch
-    plan = sfft.Plan(2 ** 24, 4096, 4, 2, seed=1, B0=4096)
+    # column-pass rows of 1889 slots x 8192 samples: 124 MB > the scratch
+    plan = sfft.Plan(2 ** 24, 4096, 4, 2, seed=1, B0=2048)
     ws, _ = sfft.workspace([plan])
     assert ws["bytes"] > sfft.NOALLOC_SCRATCH_MIB << 20
     dev = torch.device("cuda")

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
   gq *fx = nullptr;
   gh *fxh = nullptr;   // packed FP16 rows (binary16 pairs)
   float sc_n = 1.0f;   // the next item's scale (packed FP16 form)
-  uint32_t foff = 0;
+  uint32_t foff = 0, fofb = 0;  // the lane's element and byte offsets in a row (< 2^31 bytes)
   int64_t frs = 0;
   bool fon = false;
   auto fetch = [&](int item, int sg) {
@@ -186,6 +186,7 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
       fx = (gq *)xs + col0;
     }
     foff = (uint32_t)(p * L + t);  // < B0 L / 32: fits
+    fofb = foff * (F16 ? 4u : 8u);
     frs = (int64_t)P * L;
     fon = true;
   };
@@ -199,13 +200,23 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
       }
       return;
     }
+    // each row's base in scalar registers (the empty asm keeps the compiler
+    // from folding the lane's offset into a 64-bit vector address), the
+    // lane's 32-bit byte offset apart: the loads take no vector ALU work
+    typedef __attribute__((address_space(1))) const char gc;
     if constexpr (F16) {
 #pragma unroll
-      for (int q = 8 * part; q < 8 * part + 8; q++) xr[q] = (fxh + q * frs)[foff];
+      for (int q = 8 * part; q < 8 * part + 8; q++) {
+        gc *rb = (gc *)(fxh + q * frs);
+        asm volatile("" : "+s"(rb));
+        xr[q] = *(gh *)(rb + fofb);
+      }
     } else {
 #pragma unroll
       for (int q = 8 * part; q < 8 * part + 8; q++) {
-        const unsigned long long u = (fx + q * frs)[foff];
+        gc *rb = (gc *)(fx + q * frs);
+        asm volatile("" : "+s"(rb));
+        const unsigned long long u = *(gq *)(rb + fofb);
         xn[q] = make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
       }
     }
@@ -399,7 +410,7 @@ __global__ __launch_bounds__(1024) void k_col_pass16(LaunchCtx c) {
   gq *fx = nullptr;
   gh *fxh = nullptr;
   float sc_n = 1.0f;
-  uint32_t foff = 0;
+  uint32_t foff = 0, fofb = 0;  // the lane's element and byte offsets in a row (< 2^31 bytes)
   int64_t frs = 0;
   int m_n = 0;
   bool fon = false;
@@ -417,6 +428,7 @@ __global__ __launch_bounds__(1024) void k_col_pass16(LaunchCtx c) {
       fx = (gq *)xs + col0;
     }
     foff = (uint32_t)(p * L + t);  // < 128 L
+    fofb = foff * (F16 ? 4u : 8u);
     frs = 128 * L;
     fon = true;
   };
@@ -430,13 +442,23 @@ __global__ __launch_bounds__(1024) void k_col_pass16(LaunchCtx c) {
       }
       return;
     }
+    // each row's base in scalar registers (the empty asm keeps the compiler
+    // from folding the lane's offset into a 64-bit vector address), the
+    // lane's 32-bit byte offset apart: the loads take no vector ALU work
+    typedef __attribute__((address_space(1))) const char gc;
     if constexpr (F16) {
 #pragma unroll
-      for (int q = 8 * part; q < 8 * part + 8; q++) xr[q] = (fxh + q * frs)[foff];
+      for (int q = 8 * part; q < 8 * part + 8; q++) {
+        gc *rb = (gc *)(fxh + q * frs);
+        asm volatile("" : "+s"(rb));
+        xr[q] = *(gh *)(rb + fofb);
+      }
     } else {
 #pragma unroll
       for (int q = 8 * part; q < 8 * part + 8; q++) {
-        const unsigned long long u = (fx + q * frs)[foff];
+        gc *rb = (gc *)(fx + q * frs);
+        asm volatile("" : "+s"(rb));
+        const unsigned long long u = *(gq *)(rb + fofb);
         xn[q] = make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
       }
     }
@@ -606,7 +628,7 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
   gq *fx = nullptr;
   gh *fxh = nullptr;
   float sc_n = 1.0f;
-  uint32_t foff = 0;
+  uint32_t foff = 0, fofb = 0;  // the lane's element and byte offsets in a row (< 32 L x 8 <= 2^27)
   int64_t frs = 0;
   int m_n = 0;
   bool fon = false;
@@ -624,6 +646,7 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
       fx = (gq *)xs + col0;
     }
     foff = (uint32_t)(p * L + t);  // < 32 L
+    fofb = foff * (F16 ? 4u : 8u);
     frs = 32 * L;
     fon = true;
   };
@@ -640,13 +663,23 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
       }
       return;
     }
+    // each row's base in scalar registers (the empty asm keeps the compiler
+    // from folding the lane's offset into a 64-bit vector address), the
+    // lane's 32-bit byte offset apart: the loads take no vector ALU work
+    typedef __attribute__((address_space(1))) const char gc;
     if constexpr (F16) {
 #pragma unroll
-      for (int q = q0; q < q0 + 16; q++) xr[q] = (fxh + q * frs)[foff];
+      for (int q = q0; q < q0 + 16; q++) {
+        gc *rb = (gc *)(fxh + q * frs);
+        asm volatile("" : "+s"(rb));
+        xr[q] = *(gh *)(rb + fofb);
+      }
     } else {
 #pragma unroll
       for (int q = q0; q < q0 + 16; q++) {
-        const unsigned long long u = (fx + q * frs)[foff];
+        gc *rb = (gc *)(fx + q * frs);
+        asm volatile("" : "+s"(rb));
+        const unsigned long long u = *(gq *)(rb + fofb);
         xn[q] = make_float2(__uint_as_float((unsigned)u), __uint_as_float((unsigned)(u >> 32)));
       }
     }

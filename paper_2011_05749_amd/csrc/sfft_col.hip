@@ -283,8 +283,10 @@ __global__ __launch_bounds__(kColThreads, 2) void k_col_pass(LaunchCtx c) {
     int p_it = p, h_it = h;
     if constexpr (LP >= 7) asm volatile("" : "+v"(p_it), "+v"(h_it));
     dft_reg<5>(v);
-    fetch_part(2);
     __syncthreads();  // the previous item's outputs are out of E and open_c
+    // the third part after that barrier, not before it: the barrier would
+    // wait for the last wave to issue these loads
+    fetch_part(2);
     if (s != s_open) {
       // first item of another signal: its open classes (read after the
       // second barrier below, by this item's stores in the next iteration)
@@ -596,10 +598,12 @@ __device__ __forceinline__ float2 rot64(float2 v, int k) {
 // halves, even k1 and then odd k1, through one LDS buffer of 16 x 32 x 32
 // values; thread (t, k') of a half (k1 = 2 k' + half) stores its open classes
 // from registers, 16 lanes writing one 128-byte run.  The registers a half
-// frees take the next item's rows: q < 16 after the even write, then a quarter
-// after the even stores, after the odd write and after the odd stores; the odd
-// k1's 32-point DFT over q runs after the even stores, so that the rows of
-// two quarters are in flight meanwhile.  LDS slot of
+// frees take the next item's rows: q < 16 once the barrier after the even
+// write is passed (issued just before that barrier they made the launch about
+// 2 % longer, the barrier then waiting for the last wave to issue its loads),
+// then a quarter after the even stores, after the odd write and after the odd
+// stores; the odd k1's 32-point DFT over q runs after the even stores, so that
+// the rows of two quarters are in flight meanwhile.  LDS slot of
 // (t, k', p): t ST + k' SK + p, ST = 2 mod 32 and SK = 33, so that the
 // 8-byte accesses of every 32 lanes fall on distinct bank pairs both ways.
 // Persistent work-groups, each walking a contiguous range of items.
@@ -741,7 +745,6 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
       for (int j = tid; j < B0; j += NT) slot_of[j] = -1;
       if (tid < 64) omask[tid] = 0u;
     }
-    fetch_quarter(0);
     __syncthreads();
     if (s != s_open) {
       // first item of another signal: its open classes and their row slots
@@ -753,6 +756,7 @@ __global__ __launch_bounds__(512) void k_col_pass_t16(LaunchCtx c) {
       }
       __syncthreads();
     }
+    fetch_quarter(0);
     // the item's first column in the rows of the open classes: a uniform base
     // and 32-bit offsets sl L + t < N <= 2^30
     const uint32_t L = (uint32_t)(d.N >> 11);

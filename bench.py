@@ -294,9 +294,9 @@ WORKLOADS = {
 
 def run_workload(name, sfft, torch, np, steps, warmup, dev):
     """One configuration alone, as one captured batch: spectra/s, per-kernel
-    event timings, the longest kernel, and the roofline of the longest kernel
-    that moves HBM bytes by the method's count (algorithmic bytes per launch /
-    its average duration), for profiling runs of that shape."""
+    event timings, the longest kernel, and the roofline of the kernel that
+    moves the most HBM bytes by the method's count (algorithmic bytes per
+    launch / its average duration), for profiling runs of that shape."""
     import siggen
     N, K, B0, R, D, mode, snr, mag, nb, seed0 = WORKLOADS[name]
     seeds = [seed0 + i for i in range(nb)]
@@ -319,12 +319,13 @@ def run_workload(name, sfft, torch, np, steps, warmup, dev):
         e["ms"] += ms
         e["launches"] += 1
         e["bytes"] += kernel_bytes(kname, lvl, plans, stats)
-    # the roofline of the longest kernel with HBM work by the method's count
-    # (the classification kernels of noisy shapes have none: they are
-    # VALU-bound, and are named apart as the longest kernel)
+    # the roofline of the kernel with the most HBM bytes by the method's count
+    # (the classifications of noisy shapes read a few MB and are bound by VALU
+    # issue, not HBM; the level-0 launches, timed together, hold one of them,
+    # so the longest kernel is named apart)
     longest = max(per, key=lambda k: per[k]["ms"])
     hbm = [k for k in per if per[k]["bytes"] > 0]
-    dom = max(hbm, key=lambda k: per[k]["ms"]) if hbm else longest
+    dom = max(hbm, key=lambda k: per[k]["bytes"]) if hbm else longest
     d = per[dom]
     avg = d["ms"] / d["launches"]
     bpl = d["bytes"] / d["launches"]

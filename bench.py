@@ -258,8 +258,9 @@ def run_serving(sfft, torch, np, dev, n_req=3000, per_n=16, seed=7000):
 def run_tuned(sfft, torch, np, steps, warmup, dev):
     """Autotuner (paper_2011_05749_amd.tune) on two shapes, with a throw-away
     cache: the noisy N = 2^20, K = 256 batch of 64 (B0 = 512, 20 dB) and the
-    exactly sparse N = 2^22, K = 1024 batch of 64 (B0 = 2048); each batch timed
-    with the default knobs and with the tuned ones."""
+    exactly sparse N = 2^22, K = 1024 batch of 64 (B0 = 2048), each tuned at
+    its batch of 64; each batch timed with the default knobs and with the
+    tuned ones."""
     import tempfile
 
     import siggen
@@ -269,7 +270,7 @@ def run_tuned(sfft, torch, np, steps, warmup, dev):
     for name, N, K, B0, mode, snr, seed0 in (("noisy_n2p20_k256_20db_batch64", 2 ** 20, 256, 512, 1, 20.0, 1000),
                                               ("exact_n2p22_k1024_batch64", 2 ** 22, 1024, 2048, 0, None, 9000)):
         t0 = time.perf_counter()
-        e = tune.tune(N, K, 4, 2, B0=B0, mode=mode, batch=16, reps=3, path=path)
+        e = tune.tune(N, K, 4, 2, B0=B0, mode=mode, batch=64, reps=5, path=path)
         t_tune = time.perf_counter() - t0
         seeds = list(range(seed0, seed0 + 64))
         specs = [siggen.make_spec(N, K, s, snr_db=snr) for s in seeds]

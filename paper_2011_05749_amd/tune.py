@@ -22,11 +22,16 @@ not what it computes:
   teams).
 
 Each candidate runs a captured batch of synthetic signals of the shape
-(random K-sparse spectra, unit magnitudes, generated on the device) and the
-fastest median wins.  Results go to a JSON cache keyed by the device, the
-library build (sha256 of libsfft.so) and the shape, so a rebuilt library or
-another device re-tunes; lookup() returns the stored knobs (or {}), ready
-to pass to Plan(...).
+(random K-sparse spectra, unit magnitudes, generated on the device), as many
+as the batches the caller will run: how the work spreads over the 256 CUs
+depends on the batch, and so does the fastest setting.  The sweep keeps the
+median of a few replays per candidate; the default and the sweep's fastest
+few are then timed again in alternating rounds, and a setting replaces the
+default only if it is faster there by more than a noise margin.  Results go
+to a JSON cache keyed by the device, the library build (sha256 of
+libsfft.so), the shape and the batch class (the batch rounded up to a power
+of two), so a rebuilt library or another device re-tunes; lookup() returns
+the stored knobs (or {}), ready to pass to Plan(...).
 """
 from __future__ import annotations
 
@@ -36,7 +41,7 @@ import json
 import os
 import time
 
-CACHE_VERSION = 1
+CACHE_VERSION = 2
 
 
 def cache_path() -> str:
@@ -62,9 +67,15 @@ def device_tag() -> str:
     return f"{arch.split(':')[0]}-{p.multi_processor_count}cu"
 
 
-def shape_key(N, K, rounds, delays, B0, mode, device=None, lib=None) -> str:
+def batch_class(batch) -> int:
+    """The batch rounded up to a power of two (batches of one class share
+    tuned knobs)."""
+    return 1 << max(0, (int(batch) - 1).bit_length())
+
+
+def shape_key(N, K, rounds, delays, B0, mode, device=None, lib=None, batch=1) -> str:
     return (f"{device or device_tag()}|{lib or _lib_sha16()}|N={int(N)}|K={int(K)}|R={int(rounds)}"
-            f"|D={int(delays)}|B0={int(B0)}|mode={int(mode)}")
+            f"|D={int(delays)}|B0={int(B0)}|mode={int(mode)}|batch={batch_class(batch)}")
 
 
 def _load(path):
@@ -86,13 +97,14 @@ def _store(path, cache):
     os.replace(tmp, path)
 
 
-def lookup(N, K, rounds, delays, B0=0, mode=0, path=None, device=None, lib=None) -> dict:
-    """Stored knobs for the shape on this device and library build, or {}.
-    B0 as the plan resolves it (0 is looked up as the default B0)."""
+def lookup(N, K, rounds, delays, B0=0, mode=0, path=None, device=None, lib=None, batch=1) -> dict:
+    """Stored knobs for the shape and batch class on this device and library
+    build, or {}.  B0 as the plan resolves it (0 is looked up as the default
+    B0)."""
     mode = {"exact": 0, "noisy": 1}.get(mode, mode)
     if not B0:
         B0 = min(1 << max(0, (2 * int(K) - 1).bit_length()), int(N))
-    e = _load(path or cache_path())["entries"].get(shape_key(N, K, rounds, delays, B0, mode, device, lib))
+    e = _load(path or cache_path())["entries"].get(shape_key(N, K, rounds, delays, B0, mode, device, lib, batch))
     return dict(e["best"]) if e else {}
 
 
@@ -141,9 +153,12 @@ def _signals(N, K, n, seed, dev):
 
 
 def tune(N, K, rounds, delays, B0=0, mode=0, batch=32, reps=5, seed=1, path=None, verbose=False,
-         timer=None, limit=None) -> dict:
-    """Time every candidate on a captured batch of `batch` synthetic signals
-    and store the fastest in the cache.  Returns the cache entry."""
+         timer=None, limit=None, finalists=3, confirm=3, margin=0.02) -> dict:
+    """Time every candidate on a captured batch of `batch` synthetic signals,
+    time the default and the `finalists` fastest again in `confirm`
+    alternating rounds, and store the winner in the cache: the fastest of
+    those by median, unless it beats the default by no more than `margin`
+    (then the default).  Returns the cache entry."""
     import torch
 
     from . import Batch, Plan, release_batches
@@ -153,38 +168,57 @@ def tune(N, K, rounds, delays, B0=0, mode=0, batch=32, reps=5, seed=1, path=None
     B0 = int(base.info.B0)
     eligible = bool(base.info.l1_resolve)
     xs = _signals(N, K, batch, seed, dev)
-    results = []
     cands = candidates(N, B0, delays, eligible, mode)
     if limit is not None:
         cands = cands[:limit]
-    for cand in cands:
+    default = default_knobs(B0, delays, eligible)
+
+    def replays(cand, n):
         plans = [Plan(N, K, rounds, delays, seed=seed + i, B0=B0, mode=mode, **cand) for i in range(batch)]
         b = Batch(plans, xs)
-        b.run(graph=True)
+        for _ in range(2):
+            b.run(graph=True)
         torch.cuda.synchronize()
         ts = []
-        for _ in range(reps):
+        for _ in range(n):
             t0 = time.perf_counter()
             b.run(graph=True)
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
-        ts.sort()
-        med = ts[len(ts) // 2] if timer is None else timer(cand, ts)
-        results.append((med, cand))
-        if verbose:
-            print(f"tune N={N} K={K} B0={B0} {cand}: {med * 1e3:.3f} ms / batch of {batch}", flush=True)
         del b, plans
         release_batches()
-    default = default_knobs(B0, delays, eligible)
-    default_t = next(t for t, c in results if c == default)
+        return ts
+
+    def median(ts):
+        ts = sorted(ts)
+        return ts[len(ts) // 2]
+
+    results = []
+    for cand in cands:
+        ts = replays(cand, reps)
+        med = median(ts) if timer is None else timer(cand, ts)
+        results.append((med, cand))
+        if verbose:
+            print(f"tune N={N} K={K} B0={B0} batch={batch} {cand}: {med * 1e3:.3f} ms", flush=True)
     results.sort(key=lambda r: r[0])
-    best_t, best = results[0]
-    entry = {"best": best, "ms_per_batch": round(best_t * 1e3, 4), "batch": batch,
-             "default": default, "default_ms_per_batch": round(default_t * 1e3, 4),
-             "tried": len(results), "timestamp": int(time.time())}
+    final = [default] + [c for _, c in results if c != default][:finalists]
+    times = {i: [] for i in range(len(final))}
+    for _ in range(confirm):
+        for i, cand in enumerate(final):
+            times[i] += replays(cand, reps)
+    meds = [median(times[i]) if timer is None else timer(final[i], times[i]) for i in range(len(final))]
+    bi = min(range(len(final)), key=lambda i: meds[i])
+    if meds[bi] >= meds[0] * (1.0 - margin):
+        bi = 0  # not clearly faster than the default
+    if verbose:
+        for c, m in zip(final, meds):
+            print(f"tune confirm {c}: {m * 1e3:.3f} ms", flush=True)
+    entry = {"best": final[bi], "ms_per_batch": round(meds[bi] * 1e3, 4), "batch": batch,
+             "default": default, "default_ms_per_batch": round(meds[0] * 1e3, 4),
+             "tried": len(results), "finalists": len(final) - 1, "timestamp": int(time.time())}
     p = path or cache_path()
     cache = _load(p)
-    cache["entries"][shape_key(N, K, rounds, delays, B0, mode)] = entry
+    cache["entries"][shape_key(N, K, rounds, delays, B0, mode, batch=batch)] = entry
     _store(p, cache)
     return entry
 
@@ -200,8 +234,9 @@ def main(argv=None):
     ap.add_argument("--mode", default="exact")
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--confirm", type=int, default=3)
     a = ap.parse_args(argv)
-    e = tune(a.N, a.K, a.rounds, a.delays, a.B0, a.mode, a.batch, a.reps, verbose=True)
+    e = tune(a.N, a.K, a.rounds, a.delays, a.B0, a.mode, a.batch, a.reps, verbose=True, confirm=a.confirm)
     print(json.dumps(e))
 
 

@@ -55,7 +55,10 @@ def test_tune_stores_the_fastest(sfft, tmp_path):
     path = str(tmp_path / "tune.json")
     e = tune.tune(2 ** 16, 64, 4, 2, B0=128, batch=8, reps=3, path=path, limit=6)
     assert e["tried"] == 6 and e["ms_per_batch"] <= e["default_ms_per_batch"]
-    best = tune.lookup(2 ** 16, 64, 4, 2, 128, 0, path=path)
+    # a winner other than the default is faster than it by the margin in the confirmation rounds
+    assert e["best"] == e["default"] or e["ms_per_batch"] < 0.98 * e["default_ms_per_batch"] + 1e-4
+    best = tune.lookup(2 ** 16, 64, 4, 2, 128, 0, path=path, batch=8)
+    assert tune.lookup(2 ** 16, 64, 4, 2, 128, 0, path=path, batch=64) == {}  # another batch class
     assert best == e["best"]
     sp = siggen.make_spec(2 ** 16, 64, 62)
     x = siggen.synth(sp)

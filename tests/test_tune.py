@@ -1,5 +1,5 @@
-"""Autotuner host logic (no GPU): cache keys carry the device and the library
-build, a cache of another version is ignored, lookups return the stored
+"""Autotuner host logic (no GPU): cache keys carry the device, the library
+build and the batch class, a cache of another version is ignored, lookups return the stored
 knobs, every candidate is a valid plan whose knobs round-trip through
 sfft_plan_info, and out-of-range knob values are rejected."""
 import json
@@ -23,6 +23,16 @@ def test_cache_roundtrip_and_version(tmp_path):
     # another library build or device: not found
     assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx950-256cu", lib="abd") == {}
     assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx942-304cu", lib="abc") == {}
+    # the batch class is part of the key: batches up to the next power of two share it
+    kb = tune.shape_key(2 ** 20, 256, 4, 2, 512, 1, device="gfx950-256cu", lib="abc", batch=48)
+    assert kb.endswith("|batch=64") and key.endswith("|batch=1")
+    assert tune.batch_class(64) == 64 and tune.batch_class(65) == 128 and tune.batch_class(1) == 1
+    json.dump({"version": tune.CACHE_VERSION, "entries": {kb: {"best": {"jump_L": 32, "l1_resolve": 0}}}},
+              open(path, "w"))
+    assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx950-256cu", lib="abc",
+                       batch=64) == {"jump_L": 32, "l1_resolve": 0}
+    assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx950-256cu", lib="abc", batch=33) != {}
+    assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx950-256cu", lib="abc") == {}
     # a cache written by another format version is ignored
     json.dump({"version": tune.CACHE_VERSION + 1, "entries": {key: {"best": {"jump_L": 0}}}}, open(path, "w"))
     assert tune.lookup(2 ** 20, 256, 4, 2, 512, 1, path=path, device="gfx950-256cu", lib="abc") == {}

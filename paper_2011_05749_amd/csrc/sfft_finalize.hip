@@ -110,9 +110,9 @@ hipError_t launch_finalize(const LaunchCtx &c, hipStream_t s) {
   }
   const int grid = c.nsig < 4096 ? c.nsig : 4096;
   const size_t lds = (sizeof(uint64_t) + sizeof(int32_t)) * (size_t)c.max_found_cap;
-  // a signal a work-group; batches too small to fill the CUs sort with 1024
-  // threads a signal (every loop strides by the work-group size)
-  const int nt = c.nsig < 256 ? 1024 : kThreads;
+  // a signal a work-group; batches that give each CU at most one signal sort
+  // with 1024 threads a signal (every loop strides by the work-group size)
+  const int nt = c.nsig <= 256 ? 1024 : kThreads;
   hipLaunchKernelGGL(k_finalize, dim3(grid), dim3(nt), lds, s, c);
   return hipGetLastError();
 }

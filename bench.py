@@ -275,7 +275,9 @@ def run_tuned(sfft, torch, np, steps, warmup, dev):
         seeds = list(range(seed0, seed0 + 64))
         specs = [siggen.make_spec(N, K, s, snr_db=snr) for s in seeds]
         xs = [siggen.synth_torch(sp, dev) for sp in specs]
-        res = {"tuned_knobs": e["best"], "candidates": e["tried"], "tune_s": round(t_tune, 2)}
+        # equal knobs: the two timings below differ only by run-to-run noise
+        res = {"tuned_knobs": e["best"], "tuned_is_default": e["best"] == e["default"],
+               "candidates": e["tried"], "tune_s": round(t_tune, 2)}
         for label, kw in (("default", {}), ("tuned", e["best"])):
             plans = [sfft.Plan(N, K, 4, 2, seed=s, B0=B0, mode=mode, **kw) for s in seeds]
             r = _time_plans(sfft, torch, np, plans, xs, specs, K, steps, warmup)

@@ -152,6 +152,14 @@ def _signals(N, K, n, seed, dev):
     return xs
 
 
+def choose(meds, margin) -> int:
+    """Index of the setting kept, given the confirmation medians with the
+    default's first: the fastest, unless it is not faster than the default by
+    more than the fraction `margin` (then the default, 0)."""
+    bi = min(range(len(meds)), key=lambda i: meds[i])
+    return bi if meds[bi] < meds[0] * (1.0 - margin) else 0
+
+
 def tune(N, K, rounds, delays, B0=0, mode=0, batch=32, reps=5, seed=1, path=None, verbose=False,
          timer=None, limit=None, finalists=3, confirm=3, margin=0.02) -> dict:
     """Time every candidate on a captured batch of `batch` synthetic signals,
@@ -207,9 +215,7 @@ def tune(N, K, rounds, delays, B0=0, mode=0, batch=32, reps=5, seed=1, path=None
         for i, cand in enumerate(final):
             times[i] += replays(cand, reps)
     meds = [median(times[i]) if timer is None else timer(final[i], times[i]) for i in range(len(final))]
-    bi = min(range(len(final)), key=lambda i: meds[i])
-    if meds[bi] >= meds[0] * (1.0 - margin):
-        bi = 0  # not clearly faster than the default
+    bi = choose(meds, margin)
     if verbose:
         for c, m in zip(final, meds):
             print(f"tune confirm {c}: {m * 1e3:.3f} ms", flush=True)

@@ -61,3 +61,12 @@ def test_knob_validation():
     for bad in (dict(fft_tile_lg=4), dict(fft_tile_lg=12), dict(gather_unroll=3), dict(gather_unroll=16)):
         with pytest.raises(sfft.SfftError):
             sfft.Plan(2 ** 16, 64, 2, 2, B0=2048, **bad)
+
+
+def test_choose_keeps_the_default_within_the_margin():
+    # medians with the default's first
+    assert tune.choose([1.00, 0.99, 1.05], 0.02) == 0      # 1 % faster: noise, keep the default
+    assert tune.choose([1.00, 0.97, 0.975], 0.02) == 1     # 3 % faster: taken
+    assert tune.choose([1.00, 0.99, 0.95], 0.02) == 2      # the fastest, not the first past the margin
+    assert tune.choose([1.00, 1.10], 0.02) == 0            # slower candidates never win
+    assert tune.choose([1.00], 0.02) == 0

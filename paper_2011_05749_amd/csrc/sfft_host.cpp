@@ -309,6 +309,7 @@ int32_t make_layout(const std::vector<const sfft_plan_s *> &ps, bool no_jump, in
   for (int s = 0; s < nsig; s++) {
     const SigDesc &d = Y.desc[s];
     if (d.kind == SFFT_KIND_TREE && d.precision == 1) Y.any_fp32 = 1;
+    if (d.kind == SFFT_KIND_TREE && d.mode == SFFT_NOISY && !(d.noise_var > 0.0)) Y.any_noise_est = 1;
     if (d.l1 && ps[s]->info.col_form == 2) Y.col16_mask |= d.fp16 ? 2 : 1;
     else if (d.l1 && ps[s]->info.col_form == 3) Y.col16_mask |= d.fp16 ? 8 : 4;
     else if (d.l1) (d.fp16 ? Y.col_f16_mask : Y.col_lp_mask) |= 1 << (d.log2B0 - 9);  // bit LP - 4, B0 = 2^(LP + 5)
@@ -459,6 +460,7 @@ void bind_layout(const Layout &Y, char *base, const float2 *tw, LaunchCtx &c) {
   c.any_noisy0 = Y.any_noisy0;
   c.l0_spread_lg = Y.l0_spread_lg;
   c.any_noisy = Y.any_noisy;
+  c.any_noise_est = Y.any_noise_est;
   c.gather_u = Y.gather_u;
   c.l0_lds = Y.l0_lds;
   c.any_wide_jump = Y.any_wide_jump;

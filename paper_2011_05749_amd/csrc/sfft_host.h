@@ -27,7 +27,8 @@ struct Layout {
   int nmax = 1, max_B0 = 1, max_stage = 1, max_found_cap = 64;
   int32_t jrows = kJumpItemRows, any_fp32 = 0, col_lp_mask = 0, col_f16_mask = 0, col16_mask = 0,
           any_wide_jump = 0,
-          any_noisy0 = 0, any_noisy = 0, l0_spread_lg = 0, gather_u = 4, l0_lds = 16, deep_lds = 0;
+          any_noisy0 = 0, any_noisy = 0, any_noise_est = 0, l0_spread_lg = 0, gather_u = 4, l0_lds = 16,
+          deep_lds = 0;
   bool any_jump = false;
   std::vector<LevelLaunch> levels;
   // arena sizes in elements

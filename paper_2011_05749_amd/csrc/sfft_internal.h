@@ -111,6 +111,7 @@ struct SigState {
   uint64_t level_mask;    // bit l set when tree level l gathered samples
   double sref2;
   double noise_var;
+  double e0[SFFT_MAX_ROUNDS];  // tree: level-0 bucket power of each round (over its D planes)
 };
 
 struct Arena {
@@ -164,6 +165,7 @@ struct LaunchCtx {
                            // the classes are spread over several lanes (team enumeration compiled in)
   int32_t any_noisy;       // some noisy tree signal has subtree candidate ranges longer than
                            // its enum_share blocks (team enumeration compiled in)
+  int32_t any_noise_est;   // some noisy tree signal estimates its noise level (statistics launch)
   int32_t gather_u;        // gather loads in flight per thread (2, 4 or 8)
   int32_t deep_lds;        // dynamic LDS bytes of the deep resolution (largest L x 8), 0: none
   int32_t l0_lds;          // dynamic LDS bytes of the level-0 transform (largest tile x D)

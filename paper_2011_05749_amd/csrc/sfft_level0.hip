@@ -24,6 +24,15 @@ __global__ void k_reset(LaunchCtx c) {
   z.level_mask = 0;
   z.sref2 = 0.0;
   z.noise_var = 0.0;
+  for (int r = 0; r < SFFT_MAX_ROUNDS; r++) z.e0[r] = 0.0;
+  const SigDesc &d = c.desc[s];
+  if (d.kind == SFFT_KIND_TREE) {
+    // level 0 reads n B0 samples; the noise level is the plan's unless the
+    // level-0 statistics estimate it
+    z.samples = (int64_t)d.n * d.B0;
+    z.level_mask = 1ull;
+    z.noise_var = d.noise_var;
+  }
   c.st[s] = z;
 }
 
@@ -32,10 +41,13 @@ __global__ void k_reset(LaunchCtx c) {
 // P0 = B0 / Bs sub-FFTs of size Bs; with m = m' P0 + p,
 //   Yhat[c] = (1/B0) sum_p e^{-2 pi i c p / B0} FFT_Bs(y[m' P0 + p])[c mod Bs],
 // accumulated in the level-0 planes Y0[(r D + d) B0 + c] by this work-group
-// alone (fixed order, no atomics).
+// alone (fixed order, no atomics).  The round's bucket power sum_{d, c}
+// |Yhat|^2 goes to the signal's state (the zero-ton threshold's reference,
+// Sect. 3.2, from the sum over rounds).
 template <int U>
 __global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
   extern __shared__ float2 lds[];
+  __shared__ double red[16];
   for (int item = blockIdx.x; item < c.l0_items; item += gridDim.x) {
     const int li = find_owner(c.l0_pre, c.ntree, item);
     const int s = c.tree_list[li];
@@ -72,45 +84,32 @@ __global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
       }
       __syncthreads();
     }
+    // this thread's buckets, as it wrote them, in a fixed order
+    double psum = 0.0;
+    for (int64_t cc = threadIdx.x; cc < B; cc += blockDim.x)
+      for (int dl = 0; dl < D; dl++) {
+        const float2 y = Y0[(int64_t)dl * B + cc];
+        psum += (double)y.x * y.x + (double)y.y * y.y;
+      }
+    const double e = block_sum_d(psum, red);
+    if (threadIdx.x == 0) c.st[s].e0[r] = e;
   }
 }
 
-// Level-0 statistics of every tree signal: mean bucket power and, in noisy
-// mode, the noise variance from a quantile of B0 |Yhat|^2.
+// Level-0 noise level of the noisy tree signals whose plan leaves it to be
+// estimated: a quantile of B0 |Yhat|^2 over the signal's level-0 values
+// (launched only for batches holding such a signal).
 __global__ __launch_bounds__(kThreads) void k_level0_stats(LaunchCtx c) {
-  __shared__ double red[16];
   __shared__ uint32_t hist[256];
   __shared__ uint32_t sel[2];
   for (int li = blockIdx.x; li < c.ntree; li += gridDim.x) {
     const int s = c.tree_list[li];
     const SigDesc &d = c.desc[s];
+    if (!(d.mode == SFFT_NOISY && !(d.noise_var > 0.0))) continue;  // uniform over the work-group
     const int64_t cnt = (int64_t)d.n * d.B0;
     const float2 *Y0 = c.A.y0 + d.y0_off;
-    double psum = 0.0;
-    for (int64_t i0 = 0; i0 < cnt; i0 += 8 * kThreads) {
-      // 8 loads a thread in flight at once
-      float2 y[8];
-#pragma unroll
-      for (int j = 0; j < 8; j++) {
-        const int64_t i = i0 + j * kThreads + threadIdx.x;
-        y[j] = i < cnt ? Y0[i] : make_float2(0.f, 0.f);
-      }
-#pragma unroll
-      for (int j = 0; j < 8; j++) psum += (double)y[j].x * y[j].x + (double)y[j].y * y[j].y;
-    }
-    const double sref2 = block_sum_d(psum, red) / (double)cnt;
-    double nv = d.noise_var;
-    if (d.mode == SFFT_NOISY && !(nv > 0.0)) {
-      const float q = select_kth_power(Y0, cnt, (float)d.B0, d.noise_at, hist, sel);
-      nv = (double)q / d.noise_p_den;
-    }
-    if (threadIdx.x == 0) {
-      c.st[s].sref2 = sref2;
-      c.st[s].noise_var = nv;
-      c.st[s].samples = cnt;
-      c.st[s].level_mask = 1ull;
-      c.st[s].levels = 0;
-    }
+    const float q = select_kth_power(Y0, cnt, (float)d.B0, d.noise_at, hist, sel);
+    if (threadIdx.x == 0) c.st[s].noise_var = (double)q / d.noise_p_den;
     __syncthreads();
   }
 }
@@ -133,7 +132,12 @@ __global__ __launch_bounds__(kThreads, 2) void k_level0_classify(LaunchCtx c) {
     const int64_t L = d.N >> d.log2B0;
     const int n = d.n;
     const float2 *Y0 = c.A.y0 + d.y0_off;
-    const double sref2 = cst(c.st)[s].sref2, nv = cst(c.st)[s].noise_var;
+    // mean level-0 bucket power: the rounds' sums in round order, over n B0
+    double e0 = 0.0;
+    for (int r = 0; r < d.R; r++) e0 += cst(c.st)[s].e0[r];
+    const double sref2 = e0 / (double)((int64_t)n * B), nv = cst(c.st)[s].noise_var;
+    // the signal's first item records it for the later levels and the statistics
+    if (item == cst(c.l0c_pre)[li] && threadIdx.x == 0) c.st[s].sref2 = sref2;
     // 64 >> lg classes a wave, on its first lanes; the rest of the wave joins
     // the team enumeration only
     const int lg = c.l0_spread_lg;
@@ -254,8 +258,10 @@ hipError_t launch_level0(const LaunchCtx &c, hipStream_t s) {
     else hipLaunchKernelGGL(k_level0_fft<4>, g0, b0, lds, s, c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_level0_stats, dim3(c.ntree < 4096 ? c.ntree : 4096), dim3(kThreads), 0, s, c);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (c.any_noise_est) {
+      hipLaunchKernelGGL(k_level0_stats, dim3(c.ntree < 4096 ? c.ntree : 4096), dim3(kThreads), 0, s, c);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     const int g = c.l0c_items < 8192 ? c.l0c_items : 8192;
     SFFT_LAUNCH_CLASSIFIER_W(k_level0_classify, c, c.any_noisy0 != 0, dim3(g), dim3(kThreads), 0, s, c);
     if ((e = hipGetLastError()) != hipSuccess) return e;

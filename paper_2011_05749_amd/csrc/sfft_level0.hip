@@ -64,6 +64,7 @@ __global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
     const int P = (int)(B >> lgs);
     const float inv = 1.0f / (float)B;
     float2 *Y0 = c.A.y0 + d.y0_off + (int64_t)r * D * B;
+    double psum = 0.0;  // this thread's final buckets' power, cc ascending, then d
     for (int p = 0; p < P; p++) {
       gather_delays<U>(lds, src, Bs, lgs, (uint64_t)L, (uint64_t)P, (uint64_t)p, d.shift[r],
                     (uint64_t)(N - 1), D);
@@ -78,19 +79,13 @@ __global__ __launch_bounds__(kThreads) void k_level0_fft(LaunchCtx c) {
         for (int dl = 0; dl < D; dl++) {
           const float2 v = cmulf(lds[(int64_t)dl * Bs + (cc & (Bs - 1))], w);
           float2 *o = Y0 + (int64_t)dl * B + cc;
-          if (p == 0) *o = v;
-          else *o = make_float2(o->x + v.x, o->y + v.y);
+          const float2 y = p == 0 ? v : make_float2(o->x + v.x, o->y + v.y);
+          *o = y;
+          if (p == P - 1) psum += (double)y.x * y.x + (double)y.y * y.y;
         }
       }
       __syncthreads();
     }
-    // this thread's buckets, as it wrote them, in a fixed order
-    double psum = 0.0;
-    for (int64_t cc = threadIdx.x; cc < B; cc += blockDim.x)
-      for (int dl = 0; dl < D; dl++) {
-        const float2 y = Y0[(int64_t)dl * B + cc];
-        psum += (double)y.x * y.x + (double)y.y * y.y;
-      }
     const double e = block_sum_d(psum, red);
     if (threadIdx.x == 0) c.st[s].e0[r] = e;
   }
